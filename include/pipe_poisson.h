@@ -1,0 +1,216 @@
+/*
+ * pipe_poisson.h -- C ABI of libpipe: Poisson's equation in an open-ended
+ * rectangular pipe by zero-padded FFT mixed convolution/correlation, on
+ * AMD MI355X (gfx950).
+ *
+ * Method: R. D. Ryne, "On FFT-based convolutions and correlations, with
+ * application to solving Poisson's equation in an open rectangular pipe"
+ * (arXiv:1111.4971).  The potential on the mesh is
+ *
+ *   phi[i,j,k] = hx hy hz sum_{i',j',k'} rho[i',j',k']
+ *                 { R(X_i-X_i', Y_j-Y_j', w) - R(X_i-X_i', Y_j+Y_j', w)
+ *                 - R(X_i+X_i', Y_j-Y_j', w) + R(X_i+X_i', Y_j+Y_j', w) },
+ *   w = (k-k') hz,
+ *
+ * (the Eq. 4 discretisation of Eq. 1 with the four-term Green function of
+ * Eq. 8), with R from Eq. 9 (PIPE_GREEN_POINT) or its z-integrated form
+ * R_int from Eq. 14-16 (PIPE_GREEN_IGF_Z), the mode sums truncated at
+ * m <= mx, n <= my.  It is computed as in Eq. 10: one forward transform of
+ * the zero-padded charge, a pointwise product against Green spectra computed
+ * once per plan, and one backward transform; the four terms' mixed FFT
+ * directions become index reflections of the charge spectrum (Appendix, A.9).
+ *
+ * Conventions shared by every entry point:
+ *  - Mesh node i (0-based) sits at X_i = (i+1) hx, node j at Y_j = (j+1) hy;
+ *    z is translation invariant (only k - k' enters).  The pipe walls are at
+ *    x in {0, a}, y in {0, b}; nodes must satisfy nx hx <= a, ny hy <= b.
+ *  - R carries the prefactor 1/(2 pi a b) printed in Eq. 9 (Eq. 7 as printed
+ *    is a quarter of Eq. 8 with that R).  Multiply by 4 pi^2 for G -> 1/r in
+ *    the free-space limit.
+ *  - Arrays rho and phi are device pointers to C-contiguous (nx, ny, nz)
+ *    arrays, z fastest, of double (PIPE_PREC_FP64 plans) or float
+ *    (PIPE_PREC_FP32 plans).  The Green function is always evaluated and
+ *    transformed in FP64; FP32 plans store its spectra rounded to FP32.
+ *  - Every function returns a status and never throws or aborts.  Arguments
+ *    are validated before any HIP call.  pipe_last_error() returns a
+ *    thread-local message about the most recent failure on this thread.
+ *  - Solve calls are asynchronous on the given hipStream_t (NULL = default
+ *    stream); they read rho, write phi and use the caller's workspace, and
+ *    allocate nothing.  Concurrent solves on one plan need distinct
+ *    workspaces.
+ */
+#ifndef PIPE_POISSON_H
+#define PIPE_POISSON_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pipe_plan_s* pipe_plan_t;
+typedef struct pipe_batch_s* pipe_batch_t;
+
+typedef enum pipe_status {
+    PIPE_OK = 0,
+    PIPE_ERR_INVALID_ARG = 1,      /* bad size, spacing, geometry, handle or pointer        */
+    PIPE_ERR_UNSUPPORTED_SIZE = 2, /* padded length not available (see pipe_green_plan_ex)  */
+    PIPE_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed                               */
+    PIPE_ERR_NO_DEVICE = 4,        /* no HIP device visible                                  */
+    PIPE_ERR_HIP = 5,              /* a HIP runtime call failed (message has the HIP error)  */
+    PIPE_ERR_ALIASING = 6          /* rho and phi overlap                                    */
+} pipe_status_t;
+
+/* kind flags: low nibble = Green function, bits 4..7 = FFT/product precision */
+enum {
+    PIPE_GREEN_POINT = 0,   /* R of Eq. 9: z-factor e^{-kappa|w|}                         */
+    PIPE_GREEN_IGF_Z = 1,   /* R_int of Eq. 16: z-factor g_z(w) of Eq. 15 (hat basis)     */
+    PIPE_PREC_FP64 = 0x00,  /* transforms, products, rho and phi in double                */
+    PIPE_PREC_FP32 = 0x10,  /* transforms, products, rho and phi in float                 */
+    PIPE_KEEP_GREEN = 0x100 /* keep the on-mesh Green table for pipe_plan_green_table     */
+};
+
+typedef struct pipe_plan_info {
+    int nx, ny, nz;          /* physical mesh                                               */
+    int lx, ly, lz;          /* padded transform lengths (each even, >= 2n - 1)             */
+    int mx, my;              /* mode truncation m <= mx, n <= my                            */
+    int kind;                /* as passed                                                   */
+    int real_bytes;          /* 8 (FP64) or 4 (FP32)                                        */
+    double hx, hy, hz, a, b;
+    double norm;             /* the R prefactor 1/(2 pi a b)                                */
+    size_t workspace_bytes;  /* device bytes a solve needs as scratch                       */
+    size_t spectra_bytes;    /* device bytes held by the plan's Green spectra               */
+    double model_bytes;      /* algorithmic HBM bytes of one solve (all passes)             */
+    double pass_bytes[5];    /* the same per pass: z-forward, y-forward, x+product,         */
+                             /* y-inverse, z-inverse                                        */
+    double build_ms;         /* wall time of the plan build (Green evaluation + spectra)    */
+} pipe_plan_info_t;
+
+/*
+ * pipe_green_plan -- evaluate the Green function on the mesh and cache its
+ * spectra (the "computed once, transformed 4 ways, stored and reused" step of
+ * Sec. 5 and the tabulation after Eq. 10).
+ *
+ * nx, ny, nz >= 1 nodes; hx, hy, hz > 0 spacings; a, b > 0 pipe widths with
+ * nx*hx <= a and ny*hy <= b (1e-12 relative slack, so a node may sit on a
+ * wall).  kind = PIPE_GREEN_* | PIPE_PREC_*.  Modes default to mx = 2nx,
+ * my = 2ny and padded lengths to the smallest supported even L >= 2n.
+ * Blocks until the plan is built.  *out receives an opaque handle owned by
+ * the caller (free with pipe_plan_destroy).
+ * Errors: INVALID_ARG, UNSUPPORTED_SIZE, NO_DEVICE, OUT_OF_MEMORY, HIP.
+ */
+pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, double hz,
+                              double a, double b, int kind, pipe_plan_t* out);
+
+/*
+ * pipe_green_plan_ex -- as pipe_green_plan with explicit mode counts
+ * (mx, my >= 1) and padded lengths (0 = default).  Each padded length must be
+ * even, at least 2n - 1 (Appendix: N >= M = J + K - 1), and of the form
+ * 2^p 3^q with lx, ly in [8, 1024] and lz/2 in [8, 1024]; otherwise
+ * UNSUPPORTED_SIZE.  The physical result does not depend on the padded
+ * lengths.  hip_stream (a hipStream_t, may be NULL) orders the build's GPU
+ * work; the call still returns only when the build has finished.
+ */
+pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, double hz,
+                                 double a, double b, int kind, int mx, int my,
+                                 int lx, int ly, int lz, void* hip_stream, pipe_plan_t* out);
+
+/* pipe_plan_info -- sizes and constants of a plan.  Errors: INVALID_ARG. */
+pipe_status_t pipe_plan_info(pipe_plan_t plan, pipe_plan_info_t* out);
+
+/*
+ * pipe_poisson_solve -- phi = A rho for the plan's mesh (Eq. 10, all four
+ * terms summed).  rho, phi: device arrays as described above; workspace: a
+ * device buffer of at least info.workspace_bytes, 256-byte aligned.
+ * rho is read-only and must not overlap phi (ALIASING).  Asynchronous on
+ * hip_stream.  Errors: INVALID_ARG, ALIASING, HIP.
+ */
+pipe_status_t pipe_poisson_solve(pipe_plan_t plan, const void* rho, void* phi,
+                                 void* workspace, void* hip_stream);
+
+/*
+ * pipe_poisson_adjoint -- drho = A^T dphi: the transposed gather of the
+ * spectral product, sum_ab sigma_ab conj(T_ab(S_ab k)) g(S_ab k), on the same
+ * cached spectra, between the same transforms.  A is symmetric (the Green
+ * function of Eq. 7 is symmetric in (x,y,z) <-> (x',y',z')), so this equals
+ * pipe_poisson_solve up to rounding.  Same arguments and errors.
+ */
+pipe_status_t pipe_poisson_adjoint(pipe_plan_t plan, const void* dphi, void* drho,
+                                   void* workspace, void* hip_stream);
+
+/*
+ * pipe_batch_create -- group count >= 1 plans (any sizes, one precision) for
+ * repeated batched solves: the per-plan pass launches are captured once into
+ * a HIP graph and replayed by pipe_batch_solve.  The plans must outlive the
+ * batch.  The workspace a batched solve needs is reported by
+ * pipe_batch_workspace.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
+ */
+pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_t* out);
+
+/* pipe_batch_workspace -- bytes of device workspace pipe_batch_solve needs. */
+pipe_status_t pipe_batch_workspace(pipe_batch_t batch, size_t* bytes);
+
+/*
+ * pipe_batch_solve -- phi[s] = A_s rho[s] for every member s.  rho and phi
+ * are host arrays of count device pointers; the graph is rebuilt only when
+ * the pointers or workspace differ from the previous call.  Asynchronous on
+ * hip_stream.  Errors: INVALID_ARG, ALIASING, HIP.
+ */
+pipe_status_t pipe_batch_solve(pipe_batch_t batch, const void* const* rho, void* const* phi,
+                               void* workspace, void* hip_stream);
+
+/* Destroy a plan or batch.  A handle that is not live (e.g. destroyed twice)
+ * is rejected with INVALID_ARG.  Waits for the device before freeing. */
+pipe_status_t pipe_plan_destroy(pipe_plan_t plan);
+pipe_status_t pipe_batch_destroy(pipe_batch_t batch);
+
+const char* pipe_status_string(pipe_status_t status);
+const char* pipe_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Inspection and measurement hooks (tests and benchmarks).                 */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * pipe_plan_green_table -- copy the on-mesh Green table the plan evaluated
+ * (Eq. 9 or Eq. 16 at the distances the four terms need) to out_device:
+ * FP64 array [2nx+1][2ny+1][nz], element [p][q][r] = R(p hx, q hy, r hz).
+ * Returns INVALID_ARG unless the plan was built with PIPE_KEEP_GREEN in kind.
+ */
+pipe_status_t pipe_plan_green_table(pipe_plan_t plan, void* out_device, void* hip_stream);
+
+/*
+ * pipe_plan_spectra -- copy the plan's compressed Green spectra to out_device
+ * (plan precision): 9 planes of (lx/2+1)(ly/2+1)(lz/2) values followed by 9
+ * planes of (lx/2+1)(ly/2+1) values for kz = lz/2.  For orbit
+ * (kx, ky, kz), kx <= lx/2, ky <= ly/2, with T_ab the unscaled forward 3-D DFT
+ * of term ab's zero-padded Green array (Appendix A.3, A.9 layouts):
+ *   plane 0 = Re T_cc(kx,ky,kz); planes 1,2 = T_cr(kx,ky,kz);
+ *   planes 3,4 = T_rc(kx,ky,kz); planes 5,6 = T_rr(kx,ky,kz);
+ *   planes 7,8 = T_rr(lx-kx,ky,kz)   (re, im pairs).
+ */
+pipe_status_t pipe_plan_spectra(pipe_plan_t plan, void* out_device, void* hip_stream);
+
+/*
+ * pipe_poisson_solve_timed -- pipe_poisson_solve preceded and followed by
+ * HIP events around each of its five kernels on hip_stream; pass_ms[5]
+ * receives the elapsed time of each kernel of this call (blocks until done).
+ */
+pipe_status_t pipe_poisson_solve_timed(pipe_plan_t plan, const void* rho, void* phi,
+                                       void* workspace, void* hip_stream, float* pass_ms);
+
+/*
+ * pipe_fft_lines -- the library's batched 1-D complex DFT, exposed for tests:
+ * for each of howmany lines (line l at in + l*n_in, out + l*len, complex
+ * interleaved, real_bytes 4 or 8), out = sum_{e<n_in} in[e] W^{+-ek} for
+ * k < len, W = e^{-2 pi i/len}, sign -1 (forward, dir = -1) or +1 (dir = +1),
+ * unscaled.  len must be a supported length; 1 <= n_in <= len.
+ */
+pipe_status_t pipe_fft_lines(int real_bytes, int len, int n_in, int howmany, int dir,
+                             const void* in_device, void* out_device, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIPE_POISSON_H */

@@ -55,32 +55,24 @@ def solve(rho, hx, hy, hz, a, b, mx, my, kind):
 def solve_at(rho, points, hx, hy, hz, a, b, mx, my, kind):
     """The same direct sum, evaluated only at the listed output nodes (i, j, k).
 
-    For full-size grids: R is tabulated once at every distance the listed
-    points need (all X_i -/+ X_i', Y_j -/+ Y_j', (k-k') h_z), then each point
-    is a plain weighted sum over all source cells.
+    For full-size meshes: the mode factor g(kappa_mn, w)/kappa_mn is computed
+    once for every z distance, then for each listed node R is summed over the
+    modes at the distances X_i -/+ X_i', Y_j -/+ Y_j' that node needs, and the
+    node's potential is a plain weighted sum over all source cells.
     """
     rho = np.asarray(rho, dtype=np.float64)
     nx, ny, nz = rho.shape
-    points = [tuple(int(t) for t in p) for p in points]
     X, Y = green.node_coords(nx, ny, hx, hy)
-    pi = sorted({p[0] for p in points})
-    pj = sorted({p[1] for p in points})
-    um = np.subtract.outer(X[pi], X)
-    up = np.add.outer(X[pi], X)
-    vm = np.subtract.outer(Y[pj], Y)
-    vp = np.add.outer(Y[pj], Y)
-    u_vals, u_inv = _unique_table(np.stack([um, up]))
-    v_vals, v_inv = _unique_table(np.stack([vm, vp]))
     r = np.arange(-(nz - 1), nz)
-    tab = green.R_table(u_vals, v_vals, r, hz, a, b, mx, my, kind)
-    out = []
+    d = green.mode_coefficients(r, hz, a, b, mx, my, kind)     # (mx, my, 2nz-1)
     kp = np.arange(nz)
+    out = []
     for (i, j, k) in points:
-        ii, jj = pi.index(i), pj.index(j)
-        d = k - kp + (nz - 1)
-        def term(su, sv):
-            return tab[u_inv[su, ii]][:, v_inv[sv, jj]][:, :, d]     # (nx, ny, nz)
-        g = term(0, 0) - term(0, 1) - term(1, 0) + term(1, 1)
+        u = np.concatenate([X[i] - X, X[i] + X])
+        v = np.concatenate([Y[j] - Y, Y[j] + Y])
+        dk = d[:, :, k - kp + (nz - 1)]                         # (mx, my, nz) over k'
+        tab = green.R_from_coefficients(u, v, dk, a, b)          # (2nx, 2ny, nz)
+        g = tab[:nx, :ny] - tab[:nx, ny:] - tab[nx:, :ny] + tab[nx:, ny:]
         out.append(hx * hy * hz * float(np.sum(g * rho)))
     return np.array(out)
 

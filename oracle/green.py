@@ -102,6 +102,27 @@ def gz(kind, kap, r, hz):
     raise ValueError("unknown Green kind %r" % (kind,))
 
 
+def mode_coefficients(r, hz, a, b, mx, my, kind):
+    """D[m, n, t] = g(kappa_mn, r_t hz) / (2 pi a b kappa_mn): the (u, v)-independent factor of Eq. 9/16."""
+    kap = kappa(a, b, mx, my)
+    return gz(kind, kap, np.atleast_1d(np.asarray(r)), hz) / kap[..., None] / (2.0 * np.pi * a * b)
+
+
+def R_from_coefficients(u, v, d, a, b):
+    """sum_{m,n} cos(m pi u/a) cos(n pi v/b) D[m, n, t] for the tensor grid u x v x t."""
+    u = np.atleast_1d(np.asarray(u, dtype=np.float64))
+    v = np.atleast_1d(np.asarray(v, dtype=np.float64))
+    mx, my, nr = d.shape
+    m = np.arange(1, mx + 1, dtype=np.float64)
+    n = np.arange(1, my + 1, dtype=np.float64)
+    cx = np.cos(np.pi * np.multiply.outer(u, m) / a)
+    cy = np.cos(np.pi * np.multiply.outer(v, n) / b)
+    out = np.empty((u.size, v.size, nr))
+    for t in range(nr):
+        out[:, :, t] = cx @ d[:, :, t] @ cy.T
+    return out
+
+
 def R_table(u, v, r, hz, a, b, mx, my, kind):
     """R(u, v, r*hz) (Eq. 9) or R_int (Eq. 16) on the tensor grid u x v x r.
 

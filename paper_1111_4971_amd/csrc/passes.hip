@@ -1,0 +1,447 @@
+// passes.hip -- the five transform passes of one open-pipe solve, and their launchers.
+//
+// Data layout: C-order [x][y][z], z fastest.  A solve is
+//   P1 z-forward  real (nx, ny, nz) -> half spectrum (nx, ny, lz/2)       [z_r2c]
+//   P2 y-forward  (nx, ny, lz/2)    -> (nx, ly, lz/2), input rows j < ny  [strided]
+//   P3 x-forward, mixed product, x-inverse, in place on (nx, ly, lz/2)    [xprod]
+//   P4 y-inverse  (nx, ly, lz/2)    -> (nx, ny, lz/2), rows j < ny kept   [strided]
+//   P5 z-inverse  (nx, ny, lz/2)    -> real (nx, ny, nz), scaled           [z_c2r]
+// The half spectrum stores kz = 0 .. lz/2 - 1 with the real kz = lz/2 value
+// packed into the imaginary part of the kz = 0 slot (both are real for real
+// input), so every z line holds exactly lz/2 complex values.
+//
+// The four terms of Eq. 10 (convolution or correlation in x and in y) are one
+// product: a correlation along a dimension, taken as F^f{F^f(rho) F^b(xi)},
+// equals the plain inverse transform of rho_hat(-k) xi_hat(k) (Appendix, A.9:
+// swapping both transform directions reflects the spectral index), so
+//   Phi(kx,ky) = T_cc rho(kx,ky) - T_cr rho(kx,-ky) - T_rc rho(-kx,ky) + T_rr rho(-kx,-ky)
+// with every T_ab the forward transform of its own Green array.  z is always a
+// convolution, so no reflection ever leaves the stored half spectrum.
+#include "fft_engine.h"
+#include "pipe_internal.h"
+
+namespace pipe {
+
+template <> const float2* TwiddleBank::get<float2>(int n) const {
+    for (int i = 0; i < kNumTw; ++i)
+        if (kTwLengths[i] == n) return reinterpret_cast<const float2*>(d32) + offset[i];
+    return nullptr;
+}
+template <> const double2* TwiddleBank::get<double2>(int n) const {
+    for (int i = 0; i < kNumTw; ++i)
+        if (kTwLengths[i] == n) return reinterpret_cast<const double2*>(d64) + offset[i];
+    return nullptr;
+}
+
+// LDS views ----------------------------------------------------------------
+
+// Column-interleaved: element e of column c at base[e * T] (base = lds + c).
+template <typename C, int T> struct LdsCol {
+    C* base;
+    __device__ __forceinline__ C get(int e) const { return base[e * T]; }
+    __device__ __forceinline__ void set(int e, C v) const { base[e * T] = v; }
+};
+
+// Contiguous line padded by one slot every 16 (breaks power-of-two strides).
+__device__ __forceinline__ int lpad(int e) { return e + (e >> 4); }
+template <typename C> struct LdsLine {
+    C* base;
+    __device__ __forceinline__ C get(int e) const { return base[lpad(e)]; }
+    __device__ __forceinline__ void set(int e, C v) const { base[lpad(e)] = v; }
+};
+
+constexpr int ce_max(int a, int b) { return a > b ? a : b; }
+
+// P1 / spectra z pass: real lines of n_in values (zero-padded to 2*NH) -> NH packed bins.
+// A real line x of length L = 2 NH is read as z[m] = x[2m] + i x[2m+1]; with
+// Z = DFT_NH(z) the half spectrum is
+//   X[k] = (Z[k] + conj Z[NH-k]) / 2 - i W_L^k (Z[k] - conj Z[NH-k]) / 2,
+//   X[0] = Re Z[0] + Im Z[0],  X[NH] = Re Z[0] - Im Z[0]  (stored as slot 0 = (X[0], X[NH])).
+template <typename real, int NH>
+__global__ __launch_bounds__(ce_max(1, 256 / (NH / Plan<NH>::E)) * (NH / Plan<NH>::E))
+void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long out_pitch, long nlines,
+                  const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2) {
+    using C = cplx<real>;
+    constexpr int E = Plan<NH>::E, P = NH / E, LPW = ce_max(1, 256 / P);
+    constexpr int PADN = NH + NH / 16 + 1;
+    __shared__ C lds[LPW * PADN];
+    const int t = threadIdx.x % P, l = threadIdx.x / P;
+    const long line = (long)blockIdx.x * LPW + l;
+    const bool active = line < nlines;
+    const real* src = in + (active ? line : 0) * in_pitch;
+    C* L = lds + l * PADN;
+    LdsLine<C> view{L};
+    fft_line<NH, false, false>(
+        t, tw,
+        [&](int m) -> C {
+            real x0 = 0, x1 = 0;
+            if (active) {
+                if (2 * m < n_in) x0 = src[2 * m];
+                if (2 * m + 1 < n_in) x1 = src[2 * m + 1];
+            }
+            return cmake<C>(x0, x1);
+        },
+        [&](int k, C v) { view.set(k, v); }, view);
+    __syncthreads();
+    if (!active) return;
+    C* dst = out + line * out_pitch;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int k = t + q * P;
+        const C zk = view.get(k);
+        if (k == 0) {
+            dst[0] = cmake<C>(zk.x + zk.y, zk.x - zk.y);
+        } else {
+            const C zn = cconj(view.get(NH - k));
+            const C A = cadd(zk, zn), B = csub(zk, zn);
+            // -i * W^k * B
+            const C wb = cmul(B, tw2[k]);
+            dst[k] = cscale(cmake<C>(A.x + wb.y, A.y - wb.x), (real)0.5);
+        }
+    }
+}
+
+// P5: NH packed bins -> real line, unscaled inverse of length 2*NH times `scale`,
+// first n_out values kept.  Z'[k] = (X[k] + conj X[NH-k]) + i W_L^{-k} (X[k] - conj X[NH-k]),
+// then x[2m] + i x[2m+1] = IDFT_NH(Z')[m].
+template <typename real, int NH>
+__global__ __launch_bounds__(ce_max(1, 256 / (NH / Plan<NH>::E)) * (NH / Plan<NH>::E))
+void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch, int n_out, long nlines,
+                  real scale, const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2) {
+    using C = cplx<real>;
+    constexpr int E = Plan<NH>::E, P = NH / E, LPW = ce_max(1, 256 / P);
+    constexpr int PADN = NH + NH / 16 + 1;
+    __shared__ C lds[LPW * PADN];
+    const int t = threadIdx.x % P, l = threadIdx.x / P;
+    const long line = (long)blockIdx.x * LPW + l;
+    const bool active = line < nlines;
+    C* L = lds + l * PADN;
+    LdsLine<C> view{L};
+    const C* src = in + (active ? line : 0) * in_pitch;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int k = t + q * P;
+        view.set(k, active ? src[k] : cmake<C>(0, 0));
+    }
+    __syncthreads();
+    real* dst = out + (active ? line : 0) * out_pitch;
+    fft_line<NH, true, true>(
+        t, tw,
+        [&](int k) -> C {
+            const C xk = view.get(k);
+            if (k == 0) return cmake<C>(xk.x + xk.y, xk.x - xk.y);
+            const C xn = cconj(view.get(NH - k));
+            const C A = cadd(xk, xn), B = csub(xk, xn);
+            const C wb = cmulc(B, tw2[k]);  // W^{-k} B
+            return cmake<C>(A.x - wb.y, A.y + wb.x);  // A + i W^{-k} B
+        },
+        [&](int m, C v) {
+            if (active) {
+                if (2 * m < n_out) dst[2 * m] = v.x * scale;
+                if (2 * m + 1 < n_out) dst[2 * m + 1] = v.y * scale;
+            }
+        },
+        view);
+}
+
+// P2 / P4 / spectra y and x passes: lines along a strided dimension.
+// Block = T contiguous columns x P threads per line x SPW slabs.
+template <typename real, int N, int T, bool INV>
+__global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N>::E) * T)) * (N / Plan<N>::E) * T)
+void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, long in_es, long out_es,
+                    long ncols, long in_ss, long out_ss, long nslabs, const cplx<real>* __restrict__ tw) {
+    using C = cplx<real>;
+    constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
+    __shared__ C lds[SPW * N * T];
+    const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
+    const long slab = (long)blockIdx.y * SPW + s;
+    const long col = (long)blockIdx.x * T + c;
+    const bool active = slab < nslabs && col < ncols;
+    const C* src = in + (active ? slab * in_ss + col : 0);
+    C* dst = out + (active ? slab * out_ss + col : 0);
+    LdsCol<C, T> view{lds + s * N * T + c};
+    fft_line<N, INV, false>(
+        t, tw, [&](int e) -> C { return (active && e < n_in) ? src[e * in_es] : cmake<C>(0, 0); },
+        [&](int e, C v) {
+            if (active && e < n_out) dst[e * out_es] = v;
+        },
+        view);
+}
+
+// P3: for one ky pair (ky, ly-ky) and T consecutive kz: forward x transform of
+// the nx nonzero rows, the mixed product on each orbit {+-kx} x {+-ky}, inverse
+// x transform, rows i < nx written back in place.
+//
+// Spectra table (plan precision), 9 planes over orbits (kx <= lx/2, ky <= ly/2, kz):
+//   0: T_cc (real)   1,2: T_cr   3,4: T_rc   5,6: T_rr(kx,ky)   7,8: T_rr(-kx,ky)
+// and the same 9 planes for kz = lz/2 in `nyq`.  Symmetries of real Green
+// arrays: T_cc real and even in kx, ky; T_cr even in kx, T_cr(kx,-ky) = conj;
+// T_rc even in ky, T_rc(-kx,ky) = conj; T_rr(-kx,-ky) = conj T_rr(kx,ky).
+template <typename real> struct Orbit {
+    real cc;
+    cplx<real> cr, rc, rr, rr2;
+};
+
+template <typename real>
+__device__ __forceinline__ Orbit<real> load_orbit(const real* __restrict__ tab, long plane, long i) {
+    using C = cplx<real>;
+    Orbit<real> o;
+    o.cc = tab[i];
+    o.cr = cmake<C>(tab[plane + i], tab[2 * plane + i]);
+    o.rc = cmake<C>(tab[3 * plane + i], tab[4 * plane + i]);
+    o.rr = cmake<C>(tab[5 * plane + i], tab[6 * plane + i]);
+    o.rr2 = cmake<C>(tab[7 * plane + i], tab[8 * plane + i]);
+    return o;
+}
+
+// T_ab at (sx kx, sy ky) from the orbit entry (sx, sy = +1 or -1).
+template <typename real> struct OrbitView {
+    const Orbit<real>& o;
+    __device__ __forceinline__ cplx<real> cc(int, int) const { return cmake<cplx<real>>(o.cc, (real)0); }
+    __device__ __forceinline__ cplx<real> cr(int, int sy) const { return sy > 0 ? o.cr : cconj(o.cr); }
+    __device__ __forceinline__ cplx<real> rc(int sx, int) const { return sx > 0 ? o.rc : cconj(o.rc); }
+    __device__ __forceinline__ cplx<real> rr(int sx, int sy) const {
+        if (sx > 0 && sy > 0) return o.rr;
+        if (sx < 0 && sy < 0) return cconj(o.rr);
+        if (sx < 0) return o.rr2;            // (-kx, ky)
+        return cconj(o.rr2);                 // (kx, -ky)
+    }
+};
+
+// r[q] = rho at point q of the orbit: q = 0 (kx,ky), 1 (-kx,ky), 2 (kx,-ky), 3 (-kx,-ky).
+// Forward: Phi(p) = sum_ab sigma_ab T_ab(p) rho(S_ab p).
+// Adjoint: Phi(p) = sum_ab sigma_ab conj(T_ab(S_ab p)) g(S_ab p)  (transposed gather).
+template <bool ADJ, typename real>
+__device__ __forceinline__ void orbit_product(const Orbit<real>& o, const cplx<real>* r, cplx<real>* out) {
+    using C = cplx<real>;
+    OrbitView<real> T{o};
+    const int SX[4] = {1, -1, 1, -1}, SY[4] = {1, 1, -1, -1};
+    auto idx = [](int sx, int sy) { return (sx > 0 ? 0 : 1) + (sy > 0 ? 0 : 2); };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int sx = SX[q], sy = SY[q];
+        const int qcr = idx(sx, -sy), qrc = idx(-sx, sy), qrr = idx(-sx, -sy);
+        C tcc, tcr, trc, trr;
+        if constexpr (!ADJ) {
+            tcc = T.cc(sx, sy);
+            tcr = T.cr(sx, sy);
+            trc = T.rc(sx, sy);
+            trr = T.rr(sx, sy);
+        } else {
+            tcc = cconj(T.cc(sx, sy));
+            tcr = cconj(T.cr(sx, -sy));
+            trc = cconj(T.rc(-sx, sy));
+            trr = cconj(T.rr(-sx, -sy));
+        }
+        C acc = cmul(tcc, r[q]);
+        acc = csub(acc, cmul(tcr, r[qcr]));
+        acc = csub(acc, cmul(trc, r[qrc]));
+        acc = cadd(acc, cmul(trr, r[qrr]));
+        out[q] = acc;
+    }
+}
+
+template <typename real, int N, int T, bool ADJ>
+__global__ __launch_bounds__(2 * (N / Plan<N>::E) * T)
+void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restrict__ table,
+                  const real* __restrict__ nyq, const cplx<real>* __restrict__ tw) {
+    using C = cplx<real>;
+    constexpr int P = N / Plan<N>::E, NT = 2 * P * T;
+    __shared__ C lds[2 * N * T];
+    const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
+    const int ky = blockIdx.y;
+    const int kyl = l == 0 ? ky : (ly - ky) % ly;
+    const bool self = (ky == 0) || (2 * ky == ly);
+    const long kz = (long)blockIdx.x * T + c;
+    const bool active = kz < nh;
+    const long xs = (long)ly * nh;
+    C* line = data + (active ? (long)kyl * nh + kz : 0);
+    LdsCol<C, T> view{lds + l * N * T + c};
+
+    fft_line<N, false, false>(
+        t, tw, [&](int e) -> C { return (active && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
+        [&](int e, C v) { view.set(e, v); }, view);
+    __syncthreads();
+
+    const int kyo = ky;
+    const long plane = (long)(N / 2 + 1) * (ly / 2 + 1) * nh;
+    const long nplane = (long)(N / 2 + 1) * (ly / 2 + 1);
+    for (int w = threadIdx.x; w < (N / 2 + 1) * T; w += NT) {
+        const int cc = w % T, o = w / T;
+        const long kzz = (long)blockIdx.x * T + cc;
+        if (kzz >= nh) continue;
+        const int on = (N - o) % N;
+        C* L0 = lds + cc;
+        C* L1 = lds + N * T + cc;
+        C r[4] = {L0[o * T], L0[on * T], L1[o * T], L1[on * T]};
+        C p[4];
+        const long ti = ((long)o * (ly / 2 + 1) + kyo) * nh + kzz;
+        const Orbit<real> ob = load_orbit(table, plane, ti);
+        if (kzz != 0) {
+            orbit_product<ADJ>(ob, r, p);
+        } else {
+            // slot 0 carries A + iB, A at kz = 0, B at kz = lz/2 (both Hermitian in (kx,ky)):
+            // A(k) = (P(k) + conj P(-k))/2, B(k) = (P(k) - conj P(-k))/(2i); -point of q is 3-q.
+            C ra[4], rb[4], pa[4], pb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const C pm = cconj(r[3 - q]);
+                const C s = cadd(r[q], pm), d = csub(r[q], pm);
+                ra[q] = cscale(s, (real)0.5);
+                rb[q] = cscale(cmake<C>(d.y, -d.x), (real)0.5);
+            }
+            const Orbit<real> obn = load_orbit(nyq, nplane, (long)o * (ly / 2 + 1) + kyo);
+            orbit_product<ADJ>(ob, ra, pa);
+            orbit_product<ADJ>(obn, rb, pb);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) p[q] = cmake<C>(pa[q].x - pb[q].y, pa[q].y + pb[q].x);
+        }
+        L0[o * T] = p[0];
+        L0[on * T] = p[1];
+        L1[o * T] = p[2];
+        L1[on * T] = p[3];
+    }
+    __syncthreads();
+
+    fft_line<N, true, true>(
+        t, tw, [&](int e) -> C { return view.get(e); },
+        [&](int e, C v) {
+            if (active && e < nx && !(l == 1 && self)) line[e * xs] = v;
+        },
+        view);
+}
+
+// ---------------------------------------------------------------- launchers
+
+#define PIPE_FOR_EACH_N(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+template <typename real>
+hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* out, long out_pitch,
+                        long nlines, const TwiddleBank& twb, hipStream_t s) {
+    using C = cplx<real>;
+    const C* tw = twb.get<C>(nh);
+    const C* tw2 = twb.get<C>(2 * nh);
+    if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
+    switch (nh) {
+#define X(N_)                                                                                   \
+    case N_: {                                                                                  \
+        constexpr int P = N_ / Plan<N_>::E, LPW = ce_max(1, 256 / P);                           \
+        dim3 grid((unsigned)((nlines + LPW - 1) / LPW));                                        \
+        hipLaunchKernelGGL((z_r2c_kernel<real, N_>), grid, dim3(LPW * P), 0, s, in, in_pitch,   \
+                           n_in, (C*)out, out_pitch, nlines, tw, tw2);                          \
+        return hipGetLastError();                                                               \
+    }
+        PIPE_FOR_EACH_N(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename real>
+hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long out_pitch, int n_out,
+                        long nlines, real scale, const TwiddleBank& twb, hipStream_t s) {
+    using C = cplx<real>;
+    const C* tw = twb.get<C>(nh);
+    const C* tw2 = twb.get<C>(2 * nh);
+    if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
+    switch (nh) {
+#define X(N_)                                                                                   \
+    case N_: {                                                                                  \
+        constexpr int P = N_ / Plan<N_>::E, LPW = ce_max(1, 256 / P);                           \
+        dim3 grid((unsigned)((nlines + LPW - 1) / LPW));                                        \
+        hipLaunchKernelGGL((z_c2r_kernel<real, N_>), grid, dim3(LPW * P), 0, s, (const C*)in,   \
+                           in_pitch, out, out_pitch, n_out, nlines, scale, tw, tw2);            \
+        return hipGetLastError();                                                               \
+    }
+        PIPE_FOR_EACH_N(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+// Column tile: up to 16 complex values (128 B in FP32, 256 B in FP64) per row
+// segment, halved until the block's LDS (N x T complex) fits in 64 KB.
+template <typename real, int N> constexpr int strided_T() {
+    int t = 16;
+    while (t > 1 && N * t * (int)sizeof(real) * 2 > 64 * 1024) t /= 2;
+    return t;
+}
+
+template <typename real>
+hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_in, int n_out, long in_es,
+                          long out_es, long ncols, long in_ss, long out_ss, long nslabs,
+                          const TwiddleBank& twb, hipStream_t s) {
+    using C = cplx<real>;
+    const C* tw = twb.get<C>(n);
+    if (!tw || ncols <= 0 || nslabs <= 0) return hipErrorInvalidValue;
+    switch (n) {
+#define X(N_)                                                                                      \
+    case N_: {                                                                                     \
+        constexpr int T = strided_T<real, N_>();                                                   \
+        constexpr int P = N_ / Plan<N_>::E, SPW = ce_max(1, 256 / (P * T));                        \
+        dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW));          \
+        if (inverse)                                                                               \
+            hipLaunchKernelGGL((strided_kernel<real, N_, T, true>), grid, dim3(SPW * P * T), 0, s, \
+                               (const C*)in, (C*)out, n_in, n_out, in_es, out_es, ncols, in_ss,     \
+                               out_ss, nslabs, tw);                                                \
+        else                                                                                       \
+            hipLaunchKernelGGL((strided_kernel<real, N_, T, false>), grid, dim3(SPW * P * T), 0,   \
+                               s, (const C*)in, (C*)out, n_in, n_out, in_es, out_es, ncols, in_ss,  \
+                               out_ss, nslabs, tw);                                                \
+        return hipGetLastError();                                                                  \
+    }
+        PIPE_FOR_EACH_N(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+// kz tile of the fused x pass: 2 lines x lx x T complex values in LDS.
+template <typename real, int N> constexpr int xprod_T() {
+    constexpr int bytes = sizeof(real) * 2;
+    constexpr int P = N / Plan<N>::E;
+    int t = 16;
+    while (t > 1 && (2 * N * t * bytes > 64 * 1024 || 2 * P * t > 1024)) t /= 2;
+    return t;
+}
+
+template <typename real>
+hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh, const real* table,
+                        const real* nyq, const TwiddleBank& twb, hipStream_t s) {
+    using C = cplx<real>;
+    const C* tw = twb.get<C>(lx);
+    if (!tw) return hipErrorInvalidValue;
+    switch (lx) {
+#define X(N_)                                                                                     \
+    case N_: {                                                                                    \
+        constexpr int T = xprod_T<real, N_>();                                                    \
+        constexpr int P = N_ / Plan<N_>::E;                                                       \
+        dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1));                          \
+        if (adjoint)                                                                              \
+            hipLaunchKernelGGL((xprod_kernel<real, N_, T, true>), grid, dim3(2 * P * T), 0, s,    \
+                               (C*)data, nx, ly, nh, table, nyq, tw);                             \
+        else                                                                                      \
+            hipLaunchKernelGGL((xprod_kernel<real, N_, T, false>), grid, dim3(2 * P * T), 0, s,   \
+                               (C*)data, nx, ly, nh, table, nyq, tw);                             \
+        return hipGetLastError();                                                                 \
+    }
+        PIPE_FOR_EACH_N(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+#define PIPE_INST(real)                                                                               \
+    template hipError_t launch_z_r2c<real>(int, const real*, long, int, void*, long, long,             \
+                                           const TwiddleBank&, hipStream_t);                           \
+    template hipError_t launch_z_c2r<real>(int, const void*, long, real*, long, int, long, real,       \
+                                           const TwiddleBank&, hipStream_t);                           \
+    template hipError_t launch_strided<real>(int, bool, const void*, void*, int, int, long, long, long, \
+                                             long, long, long, const TwiddleBank&, hipStream_t);       \
+    template hipError_t launch_xprod<real>(int, bool, void*, int, int, int, const real*, const real*,  \
+                                           const TwiddleBank&, hipStream_t);
+PIPE_INST(float)
+PIPE_INST(double)
+#undef PIPE_INST
+
+}  // namespace pipe

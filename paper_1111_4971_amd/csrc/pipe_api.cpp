@@ -1,0 +1,605 @@
+// pipe_api.cpp -- host side of libpipe: argument validation, plan build
+// (Green evaluation, arrangement, spectra), solve orchestration, batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/pipe_poisson.h"
+#include "pipe_internal.h"
+
+using namespace pipe;
+
+// ---------------------------------------------------------------- errors
+
+namespace {
+
+thread_local std::string g_err;
+
+pipe_status_t fail(pipe_status_t st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+pipe_status_t hip_fail(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(PIPE_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
+    if (e == hipErrorNoDevice || e == hipErrorInvalidDevice)
+        return fail(PIPE_ERR_NO_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return fail(PIPE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                         \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+bool fault_inject_alloc() {
+    const char* v = getenv("PIPE_FAULT_INJECT");
+    return v && strcmp(v, "alloc") == 0;
+}
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (fault_inject_alloc()) return hipErrorOutOfMemory;
+    if (bytes == 0) bytes = 256;
+    return hipMalloc(p, bytes);
+}
+
+// ---------------------------------------------------------------- device context
+
+struct DeviceCtx {
+    bool ready = false;
+    TwiddleBank tw;
+};
+std::mutex g_ctx_mu;
+DeviceCtx g_ctx[64];
+
+pipe_status_t device_ctx(int dev, DeviceCtx** out) {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    if (dev < 0 || dev >= 64) return fail(PIPE_ERR_NO_DEVICE, "device index %d out of range", dev);
+    DeviceCtx& c = g_ctx[dev];
+    if (!c.ready) {
+        size_t off = 0;
+        for (int i = 0; i < kNumTw; ++i) {
+            c.tw.offset[i] = off;
+            off += kTwLengths[i];
+        }
+        c.tw.total = off;
+        std::vector<double> h64(2 * off);
+        std::vector<float> h32(2 * off);
+        for (int i = 0; i < kNumTw; ++i) {
+            const int n = kTwLengths[i];
+            for (int m = 0; m < n; ++m) {
+                // W_n^m = exp(-2 pi i m / n), evaluated in long double and rounded once
+                const long double ang = -2.0L * 3.141592653589793238462643383279503L * (long double)m / (long double)n;
+                const long double cr = cosl(ang), ci = sinl(ang);
+                const size_t k = c.tw.offset[i] + m;
+                h64[2 * k] = (double)cr;
+                h64[2 * k + 1] = (double)ci;
+                h32[2 * k] = (float)cr;
+                h32[2 * k + 1] = (float)ci;
+            }
+        }
+        HIP_TRY(dev_alloc(&c.tw.d64, h64.size() * sizeof(double)), "twiddle allocation");
+        hipError_t e = dev_alloc(&c.tw.d32, h32.size() * sizeof(float));
+        if (e != hipSuccess) {
+            (void)hipFree(c.tw.d64);
+            c.tw.d64 = nullptr;
+            return hip_fail(e, "twiddle allocation");
+        }
+        HIP_TRY(hipMemcpy(c.tw.d64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice), "twiddle upload");
+        HIP_TRY(hipMemcpy(c.tw.d32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice), "twiddle upload");
+        c.ready = true;
+    }
+    *out = &c;
+    return PIPE_OK;
+}
+
+std::mutex g_reg_mu;
+std::set<const void*> g_live;
+
+void reg_add(const void* p) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_live.insert(p);
+}
+bool reg_has(const void* p) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    return p && g_live.count(p);
+}
+bool reg_del(const void* p) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    return p && g_live.erase(p) == 1;
+}
+
+int pick_length(int need) {
+    for (int v : kFftLengths)
+        if (v >= need) return v;
+    return -1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- plan
+
+struct pipe_plan_s {
+    int nx, ny, nz, lx, ly, lz, nh, mx, my, kind, rb;
+    double hx, hy, hz, a, b;
+    int device;
+    DeviceCtx* ctx;
+    void* table = nullptr;   // 9 planes (lx/2+1)(ly/2+1) nh
+    void* nyq = nullptr;     // 9 planes (lx/2+1)(ly/2+1)
+    size_t table_elems = 0, nyq_elems = 0;
+    double* green = nullptr; // optional copy of Rbar
+    double build_ms = 0;
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t plan_ws_bytes(const pipe_plan_s* p) {
+    const size_t cb = 2 * (size_t)p->rb;
+    const size_t a1 = (size_t)p->nx * p->ny * p->nh * cb;
+    const size_t a2 = (size_t)p->nx * p->ly * p->nh * cb;
+    return align256(a1) + align256(a2);
+}
+
+void plan_pass_bytes(const pipe_plan_s* p, double out[5]) {
+    const double rb = p->rb, cb = 2.0 * p->rb;
+    const double phys = (double)p->nx * p->ny * p->nz * rb;
+    const double a1 = (double)p->nx * p->ny * p->nh * cb;
+    const double a2 = (double)p->nx * p->ly * p->nh * cb;
+    const double tab = 9.0 * (p->table_elems / 9 + p->nyq_elems / 9) * rb;
+    out[0] = phys + a1;
+    out[1] = a1 + a2;
+    out[2] = 2.0 * a2 + tab;
+    out[3] = a2 + a1;
+    out[4] = a1 + phys;
+}
+
+pipe_status_t validate(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b, int kind,
+                       int mx, int my, int* lx, int* ly, int* lz) {
+    if (nx < 1 || ny < 1 || nz < 1) return fail(PIPE_ERR_INVALID_ARG, "mesh sizes must be >= 1 (got %d,%d,%d)", nx, ny, nz);
+    const double v[5] = {hx, hy, hz, a, b};
+    for (double t : v)
+        if (!(t > 0.0) || !std::isfinite(t)) return fail(PIPE_ERR_INVALID_ARG, "spacings and pipe sizes must be finite and > 0");
+    if (nx * hx > a * (1.0 + 1e-12)) return fail(PIPE_ERR_INVALID_ARG, "nx*hx = %g exceeds the pipe width a = %g", nx * hx, a);
+    if (ny * hy > b * (1.0 + 1e-12)) return fail(PIPE_ERR_INVALID_ARG, "ny*hy = %g exceeds the pipe height b = %g", ny * hy, b);
+    const int g = kind & 0x0f, pr = kind & ~0x0f;
+    if (g != PIPE_GREEN_POINT && g != PIPE_GREEN_IGF_Z) return fail(PIPE_ERR_INVALID_ARG, "unknown Green kind %d", g);
+    if (pr != PIPE_PREC_FP64 && pr != PIPE_PREC_FP32) return fail(PIPE_ERR_INVALID_ARG, "unknown precision flag 0x%x", pr);
+    if (mx < 1 || my < 1 || mx > 8192 || my > 8192) return fail(PIPE_ERR_INVALID_ARG, "mode counts must be in [1, 8192]");
+    // padded lengths
+    auto choose = [&](int n, int* L, bool half, const char* nm) -> pipe_status_t {
+        if (*L == 0) {
+            const int h = pick_length(half ? n : 2 * n);
+            if (h < 0) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "%s: no supported padded length for n = %d", nm, n);
+            *L = half ? 2 * h : h;
+            return PIPE_OK;
+        }
+        if (*L < 2 * n - 1) return fail(PIPE_ERR_INVALID_ARG, "%s: padded length %d < 2n - 1 = %d", nm, *L, 2 * n - 1);
+        if (*L % 2) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "%s: padded length %d must be even", nm, *L);
+        if (!fft_length_ok(half ? *L / 2 : *L)) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "%s: padded length %d not supported", nm, *L);
+        return PIPE_OK;
+    };
+    pipe_status_t st;
+    if ((st = choose(nx, lx, false, "lx")) != PIPE_OK) return st;
+    if ((st = choose(ny, ly, false, "ly")) != PIPE_OK) return st;
+    if ((st = choose(nz, lz, true, "lz")) != PIPE_OK) return st;
+    return PIPE_OK;
+}
+
+struct Scratch {
+    std::vector<void*> ptrs;
+    ~Scratch() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    hipError_t get(void** p, size_t bytes) {
+        hipError_t e = dev_alloc(p, bytes);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+};
+
+pipe_status_t build_spectra(pipe_plan_s* p, hipStream_t st, bool keep_green) {
+    const int px = 2 * p->nx + 1, qy = 2 * p->ny + 1, rz = p->nz;
+    const int lx = p->lx, ly = p->ly, lz = p->lz, nh = p->nh;
+    Scratch s;
+    double *cx, *cy, *d, *u, *rbar, *buf;
+    HIP_TRY(s.get((void**)&cx, sizeof(double) * px * p->mx), "allocation (cos table)");
+    HIP_TRY(s.get((void**)&cy, sizeof(double) * qy * p->my), "allocation (cos table)");
+    HIP_TRY(s.get((void**)&d, sizeof(double) * (size_t)p->mx * p->my * rz), "allocation (mode table)");
+    HIP_TRY(s.get((void**)&u, sizeof(double) * (size_t)p->mx * qy * rz), "allocation (partial sums)");
+    HIP_TRY(s.get((void**)&rbar, sizeof(double) * (size_t)px * qy * rz), "allocation (Green table)");
+    HIP_TRY(s.get((void**)&buf, sizeof(double) * (size_t)lx * ly * lz), "allocation (spectrum buffer)");
+
+    const double norm = 1.0 / (2.0 * M_PI * p->a * p->b);
+    HIP_TRY(launch_cos_table(cx, px, p->mx, p->hx / p->a, st), "cos table");
+    HIP_TRY(launch_cos_table(cy, qy, p->my, p->hy / p->b, st), "cos table");
+    HIP_TRY(launch_modes(d, p->mx, p->my, rz, p->a, p->b, p->hz, (p->kind & 0x0f) == PIPE_GREEN_IGF_Z, norm, st), "mode table");
+    // U[m] (qy x rz) = Cy (qy x my) * D[m] (my x rz)
+    HIP_TRY(launch_gemm_f64(cy, d, u, qy, rz, p->my, p->my, rz, rz, 0, (long)p->my * rz, (long)qy * rz, p->mx, st),
+            "mode contraction (y)");
+    // Rbar (px x qy*rz) = Cx (px x mx) * U (mx x qy*rz)
+    HIP_TRY(launch_gemm_f64(cx, u, rbar, px, qy * rz, p->mx, p->mx, (long)qy * rz, (long)qy * rz, 0, 0, 0, 1, st),
+            "mode contraction (x)");
+    for (int term = 0; term < 4; ++term) {
+        const int xcorr = (term == 2 || term == 3), ycorr = (term == 1 || term == 3);
+        HIP_TRY(launch_arrange(buf, rbar, p->nx, p->ny, p->nz, lx, ly, lz, xcorr, ycorr, st), "Green arrangement");
+        HIP_TRY(launch_z_r2c<double>(nh, buf, lz, lz, buf, nh, (long)lx * ly, p->ctx->tw, st), "spectra z transform");
+        HIP_TRY(launch_strided<double>(ly, false, buf, buf, ly, ly, nh, nh, nh, (long)ly * nh, (long)ly * nh, lx,
+                                       p->ctx->tw, st),
+                "spectra y transform");
+        HIP_TRY(launch_strided<double>(lx, false, buf, buf, lx, lx, (long)ly * nh, (long)ly * nh, (long)ly * nh, 0, 0, 1,
+                                       p->ctx->tw, st),
+                "spectra x transform");
+        HIP_TRY(launch_compress(buf, p->table, p->nyq, p->rb, term, lx, ly, nh, st), "spectra compression");
+    }
+    if (keep_green) {
+        HIP_TRY(dev_alloc((void**)&p->green, sizeof(double) * (size_t)px * qy * rz), "allocation (kept Green table)");
+        HIP_TRY(hipMemcpyAsync(p->green, rbar, sizeof(double) * (size_t)px * qy * rz, hipMemcpyDeviceToDevice, st),
+                "Green table copy");
+    }
+    HIP_TRY(hipStreamSynchronize(st), "plan build");
+    return PIPE_OK;
+}
+
+void plan_free(pipe_plan_s* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->table) (void)hipFree(p->table);
+    if (p->nyq) (void)hipFree(p->nyq);
+    if (p->green) (void)hipFree(p->green);
+    delete p;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+pipe_status_t check_solve_args(pipe_plan_t plan, const void* rho, void* phi, void* ws) {
+    if (!reg_has(plan)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
+    if (!rho || !phi || !ws) return fail(PIPE_ERR_INVALID_ARG, "rho, phi and workspace must be non-null");
+    if (((uintptr_t)ws) & 255) return fail(PIPE_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (((uintptr_t)rho) % plan->rb || ((uintptr_t)phi) % plan->rb)
+        return fail(PIPE_ERR_INVALID_ARG, "rho and phi must be aligned to the element size");
+    const size_t nb = (size_t)plan->nx * plan->ny * plan->nz * plan->rb;
+    if (overlaps(rho, nb, phi, nb)) return fail(PIPE_ERR_ALIASING, "rho and phi overlap");
+    if (overlaps(rho, nb, ws, plan->ws_bytes) || overlaps(phi, nb, ws, plan->ws_bytes))
+        return fail(PIPE_ERR_ALIASING, "workspace overlaps rho or phi");
+    return PIPE_OK;
+}
+
+enum { EV_NONE = 0 };
+
+template <typename real>
+pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, hipStream_t st, bool adjoint,
+                         hipEvent_t* ev) {
+    const size_t cb = 2 * sizeof(real);
+    char* A1 = (char*)ws;
+    char* A2 = A1 + align256((size_t)p->nx * p->ny * p->nh * cb);
+    const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly, nh = p->nh;
+    const TwiddleBank& tw = p->ctx->tw;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event");
+    HIP_TRY(launch_z_r2c<real>(nh, (const real*)rho, nz, nz, A1, nh, (long)nx * ny, tw, st), "z forward pass");
+    if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
+    HIP_TRY(launch_strided<real>(ly, false, A1, A2, ny, ly, nh, nh, nh, (long)ny * nh, (long)ly * nh, nx, tw, st),
+            "y forward pass");
+    if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
+    HIP_TRY(launch_xprod<real>(p->lx, adjoint, A2, nx, ly, nh, (const real*)p->table, (const real*)p->nyq, tw, st),
+            "x pass with spectral product");
+    if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event");
+    HIP_TRY(launch_strided<real>(ly, true, A2, A1, ly, ny, nh, nh, nh, (long)ly * nh, (long)ny * nh, nx, tw, st),
+            "y inverse pass");
+    if (ev) HIP_TRY(hipEventRecord(ev[4], st), "event");
+    const real scale = (real)(p->hx * p->hy * p->hz / ((double)p->lx * p->ly * p->lz));
+    HIP_TRY(launch_z_c2r<real>(nh, A1, nh, (real*)phi, nz, nz, (long)nx * ny, scale, tw, st), "z inverse pass");
+    if (ev) HIP_TRY(hipEventRecord(ev[5], st), "event");
+    return PIPE_OK;
+}
+
+pipe_status_t solve_impl(pipe_plan_t plan, const void* rho, void* phi, void* ws, void* stream, bool adjoint,
+                         hipEvent_t* ev) {
+    pipe_status_t s = check_solve_args(plan, rho, phi, ws);
+    if (s != PIPE_OK) return s;
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != plan->device) HIP_TRY(hipSetDevice(plan->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    s = plan->rb == 8 ? run_passes<double>(plan, rho, phi, ws, st, adjoint, ev)
+                      : run_passes<float>(plan, rho, phi, ws, st, adjoint, ev);
+    if (cur != plan->device) (void)hipSetDevice(cur);
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pipe_status_string(pipe_status_t s) {
+    switch (s) {
+        case PIPE_OK: return "PIPE_OK";
+        case PIPE_ERR_INVALID_ARG: return "PIPE_ERR_INVALID_ARG";
+        case PIPE_ERR_UNSUPPORTED_SIZE: return "PIPE_ERR_UNSUPPORTED_SIZE";
+        case PIPE_ERR_OUT_OF_MEMORY: return "PIPE_ERR_OUT_OF_MEMORY";
+        case PIPE_ERR_NO_DEVICE: return "PIPE_ERR_NO_DEVICE";
+        case PIPE_ERR_HIP: return "PIPE_ERR_HIP";
+        case PIPE_ERR_ALIASING: return "PIPE_ERR_ALIASING";
+    }
+    return "PIPE_ERR_UNKNOWN";
+}
+
+const char* pipe_last_error(void) { return g_err.c_str(); }
+
+pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b,
+                                 int kind, int mx, int my, int lx, int ly, int lz, void* hip_stream,
+                                 pipe_plan_t* out) {
+    if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
+    *out = nullptr;
+    const bool keep = (kind & 0x100) != 0;
+    kind &= 0xff;
+    pipe_status_t s = validate(nx, ny, nz, hx, hy, hz, a, b, kind, mx, my, &lx, &ly, &lz);
+    if (s != PIPE_OK) return s;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return fail(PIPE_ERR_NO_DEVICE, "no HIP device available");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    DeviceCtx* ctx = nullptr;
+    if ((s = device_ctx(dev, &ctx)) != PIPE_OK) return s;
+
+    auto t0 = std::chrono::steady_clock::now();
+    pipe_plan_s* p = new pipe_plan_s();
+    p->nx = nx; p->ny = ny; p->nz = nz; p->lx = lx; p->ly = ly; p->lz = lz; p->nh = lz / 2;
+    p->mx = mx; p->my = my; p->kind = kind; p->rb = (kind & PIPE_PREC_FP32) ? 4 : 8;
+    p->hx = hx; p->hy = hy; p->hz = hz; p->a = a; p->b = b;
+    p->device = dev; p->ctx = ctx;
+    const size_t orbits = (size_t)(lx / 2 + 1) * (ly / 2 + 1);
+    p->table_elems = 9 * orbits * p->nh;
+    p->nyq_elems = 9 * orbits;
+    e = dev_alloc(&p->table, p->table_elems * p->rb);
+    if (e == hipSuccess) e = dev_alloc(&p->nyq, p->nyq_elems * p->rb);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "allocation (Green spectra)");
+    }
+    s = build_spectra(p, (hipStream_t)hip_stream, keep);
+    if (s != PIPE_OK) {
+        plan_free(p);
+        return s;
+    }
+    p->ws_bytes = plan_ws_bytes(p);
+    p->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    reg_add(p);
+    *out = p;
+    return PIPE_OK;
+}
+
+pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b, int kind,
+                              pipe_plan_t* out) {
+    return pipe_green_plan_ex(nx, ny, nz, hx, hy, hz, a, b, kind, 2 * nx, 2 * ny, 0, 0, 0, nullptr, out);
+}
+
+pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
+    if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
+    if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
+    memset(out, 0, sizeof *out);
+    out->nx = p->nx; out->ny = p->ny; out->nz = p->nz;
+    out->lx = p->lx; out->ly = p->ly; out->lz = p->lz;
+    out->mx = p->mx; out->my = p->my; out->kind = p->kind; out->real_bytes = p->rb;
+    out->hx = p->hx; out->hy = p->hy; out->hz = p->hz; out->a = p->a; out->b = p->b;
+    out->norm = 1.0 / (2.0 * M_PI * p->a * p->b);
+    out->workspace_bytes = p->ws_bytes;
+    out->spectra_bytes = (p->table_elems + p->nyq_elems) * p->rb;
+    plan_pass_bytes(p, out->pass_bytes);
+    out->model_bytes = 0;
+    for (double v : out->pass_bytes) out->model_bytes += v;
+    out->build_ms = p->build_ms;
+    return PIPE_OK;
+}
+
+pipe_status_t pipe_poisson_solve(pipe_plan_t plan, const void* rho, void* phi, void* ws, void* stream) {
+    return solve_impl(plan, rho, phi, ws, stream, false, nullptr);
+}
+
+pipe_status_t pipe_poisson_adjoint(pipe_plan_t plan, const void* dphi, void* drho, void* ws, void* stream) {
+    return solve_impl(plan, dphi, drho, ws, stream, true, nullptr);
+}
+
+pipe_status_t pipe_poisson_solve_timed(pipe_plan_t plan, const void* rho, void* phi, void* ws, void* stream,
+                                       float* pass_ms) {
+    if (!pass_ms) return fail(PIPE_ERR_INVALID_ARG, "pass_ms must be non-null");
+    pipe_status_t s = check_solve_args(plan, rho, phi, ws);
+    if (s != PIPE_OK) return s;
+    hipEvent_t ev[6];
+    for (int i = 0; i < 6; ++i) HIP_TRY(hipEventCreate(&ev[i]), "hipEventCreate");
+    s = solve_impl(plan, rho, phi, ws, stream, false, ev);
+    if (s == PIPE_OK) {
+        hipError_t e = hipEventSynchronize(ev[5]);
+        if (e != hipSuccess) s = hip_fail(e, "hipEventSynchronize");
+        for (int i = 0; i < 5 && s == PIPE_OK; ++i) {
+            e = hipEventElapsedTime(&pass_ms[i], ev[i], ev[i + 1]);
+            if (e != hipSuccess) s = hip_fail(e, "hipEventElapsedTime");
+        }
+    }
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    return s;
+}
+
+pipe_status_t pipe_plan_destroy(pipe_plan_t p) {
+    if (!reg_del(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or already destroyed plan handle");
+    plan_free(p);
+    return PIPE_OK;
+}
+
+pipe_status_t pipe_plan_green_table(pipe_plan_t p, void* out, void* stream) {
+    if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
+    if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
+    if (!p->green) return fail(PIPE_ERR_INVALID_ARG, "plan was built without keeping its Green table");
+    const size_t n = (size_t)(2 * p->nx + 1) * (2 * p->ny + 1) * p->nz;
+    HIP_TRY(hipMemcpyAsync(out, p->green, n * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream), "copy");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "copy");
+    return PIPE_OK;
+}
+
+pipe_status_t pipe_plan_spectra(pipe_plan_t p, void* out, void* stream) {
+    if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
+    if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(out, p->table, p->table_elems * p->rb, hipMemcpyDeviceToDevice, st), "copy");
+    HIP_TRY(hipMemcpyAsync((char*)out + p->table_elems * p->rb, p->nyq, p->nyq_elems * p->rb,
+                           hipMemcpyDeviceToDevice, st), "copy");
+    HIP_TRY(hipStreamSynchronize(st), "copy");
+    return PIPE_OK;
+}
+
+pipe_status_t pipe_fft_lines(int real_bytes, int len, int n_in, int howmany, int dir, const void* in, void* out,
+                             void* stream) {
+    if (real_bytes != 4 && real_bytes != 8) return fail(PIPE_ERR_INVALID_ARG, "real_bytes must be 4 or 8");
+    if (!fft_length_ok(len)) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "length %d not supported", len);
+    if (n_in < 1 || n_in > len || howmany < 1) return fail(PIPE_ERR_INVALID_ARG, "bad n_in or howmany");
+    if (dir != -1 && dir != 1) return fail(PIPE_ERR_INVALID_ARG, "dir must be -1 or +1");
+    if (!in || !out) return fail(PIPE_ERR_INVALID_ARG, "null pointer");
+    int dev = 0;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PIPE_ERR_NO_DEVICE, "no HIP device available");
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    DeviceCtx* ctx = nullptr;
+    pipe_status_t s = device_ctx(dev, &ctx);
+    if (s != PIPE_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (real_bytes == 8)
+        HIP_TRY(launch_strided<double>(len, dir > 0, in, out, n_in, len, 1, 1, 1, n_in, len, howmany, ctx->tw, st),
+                "fft lines");
+    else
+        HIP_TRY(launch_strided<float>(len, dir > 0, in, out, n_in, len, 1, 1, 1, n_in, len, howmany, ctx->tw, st),
+                "fft lines");
+    return PIPE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+
+struct pipe_batch_s {
+    std::vector<pipe_plan_t> plans;
+    int device = 0, rb = 8;
+    size_t ws_bytes = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> last_rho;
+    std::vector<void*> last_phi;
+    void* last_ws = nullptr;
+};
+
+namespace {
+void batch_drop_graph(pipe_batch_s* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+}  // namespace
+
+extern "C" {
+
+pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_t* out) {
+    if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
+    *out = nullptr;
+    if (!plans || count < 1) return fail(PIPE_ERR_INVALID_ARG, "need at least one plan");
+    for (int i = 0; i < count; ++i)
+        if (!reg_has(plans[i])) return fail(PIPE_ERR_INVALID_ARG, "plan %d is not a live plan", i);
+    for (int i = 1; i < count; ++i)
+        if (plans[i]->rb != plans[0]->rb || plans[i]->device != plans[0]->device)
+            return fail(PIPE_ERR_INVALID_ARG, "batch members must share precision and device");
+    pipe_batch_s* b = new pipe_batch_s();
+    b->plans.assign(plans, plans + count);
+    b->device = plans[0]->device;
+    b->rb = plans[0]->rb;
+    for (auto p : b->plans) b->ws_bytes = std::max(b->ws_bytes, p->ws_bytes);
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "hipStreamCreate");
+    }
+    reg_add(b);
+    *out = b;
+    return PIPE_OK;
+}
+
+pipe_status_t pipe_batch_workspace(pipe_batch_t b, size_t* bytes) {
+    if (!reg_has(b)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed batch handle");
+    if (!bytes) return fail(PIPE_ERR_INVALID_ARG, "bytes must be non-null");
+    *bytes = b->ws_bytes;
+    return PIPE_OK;
+}
+
+pipe_status_t pipe_batch_solve(pipe_batch_t b, const void* const* rho, void* const* phi, void* ws, void* stream) {
+    if (!reg_has(b)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed batch handle");
+    if (!rho || !phi || !ws) return fail(PIPE_ERR_INVALID_ARG, "null array");
+    const size_t n = b->plans.size();
+    for (size_t i = 0; i < n; ++i) {
+        if (!reg_has(b->plans[i])) return fail(PIPE_ERR_INVALID_ARG, "member plan %zu was destroyed", i);
+        pipe_status_t s = check_solve_args(b->plans[i], rho[i], phi[i], ws);
+        if (s != PIPE_OK) return s;
+    }
+    bool same = b->exec && b->last_ws == ws;
+    for (size_t i = 0; same && i < n; ++i) same = b->last_rho[i] == rho[i] && b->last_phi[i] == phi[i];
+    if (!same) {
+        batch_drop_graph(b);
+        HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "graph capture");
+        pipe_status_t s = PIPE_OK;
+        for (size_t i = 0; i < n && s == PIPE_OK; ++i) s = solve_impl(b->plans[i], rho[i], phi[i], ws, b->cap, false, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap, &g);
+        if (s != PIPE_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return hip_fail(e, "graph capture");
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            batch_drop_graph(b);
+            return hip_fail(e, "graph instantiate");
+        }
+        b->last_rho.assign(rho, rho + n);
+        b->last_phi.assign(phi, phi + n);
+        b->last_ws = ws;
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream), "graph launch");
+    return PIPE_OK;
+}
+
+pipe_status_t pipe_batch_destroy(pipe_batch_t b) {
+    if (!reg_del(b)) return fail(PIPE_ERR_INVALID_ARG, "invalid or already destroyed batch handle");
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    batch_drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return PIPE_OK;
+}
+
+}  // extern "C"

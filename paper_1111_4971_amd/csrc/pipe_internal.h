@@ -1,0 +1,56 @@
+// pipe_internal.h -- declarations shared by the host API and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace pipe {
+
+// Supported complex FFT lengths (2^p 3^q); the twiddle bank also holds 1536, 2048
+// for the real-to-complex post-processing of z lines of length 2 * 768, 2 * 1024.
+constexpr int kFftLengths[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+constexpr int kTwLengths[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048};
+constexpr int kNumTw = sizeof(kTwLengths) / sizeof(int);
+
+inline bool fft_length_ok(int n) {
+    for (int v : kFftLengths) if (v == n) return true;
+    return false;
+}
+
+// Per-device twiddle bank: tw[m] = exp(-2 pi i m / N) for every N in kTwLengths.
+struct TwiddleBank {
+    void* d64 = nullptr;   // double2
+    void* d32 = nullptr;   // float2
+    size_t offset[kNumTw] = {};
+    size_t total = 0;
+    template <typename C> const C* get(int n) const;
+};
+
+// Kernel launchers (passes.hip).  All return hipSuccess or the launch error.
+template <typename real>
+hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* out, long out_pitch,
+                        long nlines, const TwiddleBank& tw, hipStream_t s);
+template <typename real>
+hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long out_pitch, int n_out,
+                        long nlines, real scale, const TwiddleBank& tw, hipStream_t s);
+template <typename real>
+hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_in, int n_out,
+                          long in_es, long out_es, long ncols, long in_ss, long out_ss, long nslabs,
+                          const TwiddleBank& tw, hipStream_t s);
+template <typename real>
+hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh,
+                        const real* table, const real* nyq, const TwiddleBank& tw, hipStream_t s);
+
+// Green evaluation (green.hip).
+hipError_t launch_cos_table(double* out, int np, int m, double s, hipStream_t st);
+hipError_t launch_modes(double* d, int mx, int my, int rz, double a, double b, double hz, int igf,
+                        double norm, hipStream_t st);
+hipError_t launch_gemm_f64(const double* A, const double* B, double* C, int M, int N, int K,
+                           long lda, long ldb, long ldc, long sA, long sB, long sC, int batch,
+                           hipStream_t st);
+hipError_t launch_arrange(double* xi, const double* rbar, int nx, int ny, int nz, int lx, int ly,
+                          int lz, int xcorr, int ycorr, hipStream_t st);
+hipError_t launch_compress(const void* spec, void* table, void* nyq, int real_bytes, int term,
+                           int lx, int ly, int nh, hipStream_t st);
+
+}  // namespace pipe

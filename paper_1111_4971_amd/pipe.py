@@ -1,0 +1,315 @@
+"""Python binding of libpipe (ctypes): argument marshalling only.
+
+Every step of a solve runs in the HIP kernels of libpipe.so.  PyTorch supplies
+device memory (tensors) and streams.  If the shared library is missing this
+module raises at load time; there is no fallback.
+
+Entry points mirror include/pipe_poisson.h:
+  GreenPlan(...)            -> pipe_green_plan_ex
+  GreenPlan.solve(rho)      -> pipe_poisson_solve
+  GreenPlan.adjoint(dphi)   -> pipe_poisson_adjoint
+  Batch(plans).solve(rhos)  -> pipe_batch_create / pipe_batch_solve
+  PipePoissonFn.apply(rho, plan): autograd function whose backward is the adjoint.
+"""
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpipe.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pipe_poisson.h")
+
+POINT, IGF_Z = 0, 1
+PREC_FP64, PREC_FP32 = 0x00, 0x10
+KEEP_GREEN = 0x100
+
+STATUS = {0: "PIPE_OK", 1: "PIPE_ERR_INVALID_ARG", 2: "PIPE_ERR_UNSUPPORTED_SIZE", 3: "PIPE_ERR_OUT_OF_MEMORY",
+          4: "PIPE_ERR_NO_DEVICE", 5: "PIPE_ERR_HIP", 6: "PIPE_ERR_ALIASING"}
+
+
+class PipeError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+        self.message = message
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("lx", ctypes.c_int), ("ly", ctypes.c_int), ("lz", ctypes.c_int),
+                ("mx", ctypes.c_int), ("my", ctypes.c_int), ("kind", ctypes.c_int),
+                ("real_bytes", ctypes.c_int),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("norm", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_size_t), ("spectra_bytes", ctypes.c_size_t),
+                ("model_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double * 5),
+                ("build_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["pass_bytes"] = list(self.pass_bytes)
+        return d
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+
+def lib():
+    """Load libpipe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpipe.so is not built (%s); run `python -m paper_1111_4971_amd.build`" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "pipe_green_plan": ([_I, _I, _I, _D, _D, _D, _D, _D, _I, ctypes.POINTER(_P)], _I),
+        "pipe_green_plan_ex": ([_I, _I, _I, _D, _D, _D, _D, _D, _I, _I, _I, _I, _I, _I, _P,
+                                ctypes.POINTER(_P)], _I),
+        "pipe_plan_info": ([_P, ctypes.POINTER(PlanInfo)], _I),
+        "pipe_poisson_solve": ([_P, _P, _P, _P, _P], _I),
+        "pipe_poisson_adjoint": ([_P, _P, _P, _P, _P], _I),
+        "pipe_poisson_solve_timed": ([_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_float)], _I),
+        "pipe_batch_create": ([ctypes.POINTER(_P), _I, ctypes.POINTER(_P)], _I),
+        "pipe_batch_workspace": ([_P, ctypes.POINTER(ctypes.c_size_t)], _I),
+        "pipe_batch_solve": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _P], _I),
+        "pipe_plan_destroy": ([_P], _I),
+        "pipe_batch_destroy": ([_P], _I),
+        "pipe_status_string": ([_I], ctypes.c_char_p),
+        "pipe_last_error": ([], ctypes.c_char_p),
+        "pipe_plan_green_table": ([_P, _P, _P], _I),
+        "pipe_plan_spectra": ([_P, _P, _P], _I),
+        "pipe_fft_lines": ([_I, _I, _I, _I, _I, _P, _P, _P], _I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions include/pipe_poisson.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pipe_[a-z_0-9]+)\s*\(", txt)))
+
+
+def check(status):
+    if status != 0:
+        raise PipeError(status, lib().pipe_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype(real_bytes):
+    torch = _torch()
+    return torch.float64 if real_bytes == 8 else torch.float32
+
+
+class GreenPlan:
+    """Cached Green spectra for one mesh (pipe_green_plan_ex).
+
+    kind: POINT or IGF_Z; precision: 'fp64' or 'fp32'.  mx, my default to
+    2 nx, 2 ny; L = (lx, ly, lz) defaults to the smallest supported even
+    lengths >= 2n.
+    """
+
+    def __init__(self, nx, ny, nz, hx, hy, hz, a, b, kind=IGF_Z, precision="fp64", mx=None, my=None,
+                 L=None, keep_green=False, stream=None):
+        flags = int(kind) | (PREC_FP32 if precision == "fp32" else PREC_FP64) | (KEEP_GREEN if keep_green else 0)
+        lx, ly, lz = L if L is not None else (0, 0, 0)
+        h = _P()
+        st = _stream_ptr(stream) if stream is not None else None
+        check(lib().pipe_green_plan_ex(nx, ny, nz, hx, hy, hz, a, b, flags, mx or 2 * nx, my or 2 * ny,
+                                       lx, ly, lz, st, ctypes.byref(h)))
+        self._h = h
+        info = PlanInfo()
+        check(lib().pipe_plan_info(h, ctypes.byref(info)))
+        self.info = info
+        self.shape = (nx, ny, nz)
+        self.dtype = _dtype(info.real_bytes)
+        self._ws = None
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise PipeError(1, "plan already destroyed")
+        return self._h
+
+    def workspace(self, device="cuda"):
+        torch = _torch()
+        if self._ws is None or self._ws.device != torch.device(device):
+            self._ws = torch.empty(self.info.workspace_bytes + 256, dtype=torch.uint8, device=device)
+        return self._aligned(self._ws)
+
+    @staticmethod
+    def _aligned(t):
+        off = (-t.data_ptr()) % 256
+        return t[off:]
+
+    def _prep(self, x):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError("expected a CUDA tensor")
+        if tuple(x.shape) != self.shape:
+            raise ValueError("expected shape %s, got %s" % (self.shape, tuple(x.shape)))
+        if x.dtype != self.dtype:
+            raise TypeError("expected %s, got %s" % (self.dtype, x.dtype))
+        return x.contiguous()
+
+    def _run(self, fn, x, out, workspace, stream):
+        torch = _torch()
+        x = self._prep(x)
+        if out is None:
+            out = torch.empty_like(x)
+        ws = workspace if workspace is not None else self.workspace(x.device)
+        check(fn(self.handle, _P(x.data_ptr()), _P(out.data_ptr()), _P(ws.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def solve(self, rho, out=None, workspace=None, stream=None):
+        return self._run(lib().pipe_poisson_solve, rho, out, workspace, stream)
+
+    def adjoint(self, dphi, out=None, workspace=None, stream=None):
+        return self._run(lib().pipe_poisson_adjoint, dphi, out, workspace, stream)
+
+    def solve_timed(self, rho, out=None, workspace=None, stream=None):
+        torch = _torch()
+        x = self._prep(rho)
+        out = torch.empty_like(x) if out is None else out
+        ws = workspace if workspace is not None else self.workspace(x.device)
+        ms = (ctypes.c_float * 5)()
+        check(lib().pipe_poisson_solve_timed(self.handle, _P(x.data_ptr()), _P(out.data_ptr()),
+                                             _P(ws.data_ptr()), _stream_ptr(stream), ms))
+        return out, list(ms)
+
+    def green_table(self):
+        torch = _torch()
+        nx, ny, nz = self.shape
+        out = torch.empty((2 * nx + 1, 2 * ny + 1, nz), dtype=torch.float64, device="cuda")
+        check(lib().pipe_plan_green_table(self.handle, _P(out.data_ptr()), _stream_ptr()))
+        return out
+
+    def spectra(self):
+        """(table, nyquist) as tensors of shape (9, lx/2+1, ly/2+1, lz/2) and (9, lx/2+1, ly/2+1)."""
+        torch = _torch()
+        i = self.info
+        kx, ky, nh = i.lx // 2 + 1, i.ly // 2 + 1, i.lz // 2
+        flat = torch.empty(9 * kx * ky * (nh + 1), dtype=self.dtype, device="cuda")
+        check(lib().pipe_plan_spectra(self.handle, _P(flat.data_ptr()), _stream_ptr()))
+        n1 = 9 * kx * ky * nh
+        return flat[:n1].view(9, kx, ky, nh), flat[n1:].view(9, kx, ky)
+
+    def close(self):
+        if self._h is not None:
+            check(lib().pipe_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if self._h is not None:
+                lib().pipe_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many plans solved by one replay of a captured HIP graph (pipe_batch_*)."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (_P * len(self.plans))(*[p.handle for p in self.plans])
+        h = _P()
+        check(lib().pipe_batch_create(arr, len(self.plans), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_size_t()
+        check(lib().pipe_batch_workspace(h, ctypes.byref(n)))
+        self.workspace_bytes = n.value
+        self._ws = None
+
+    def workspace(self, device="cuda"):
+        torch = _torch()
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
+        return GreenPlan._aligned(self._ws)
+
+    def solve(self, rhos, outs=None, workspace=None, stream=None):
+        torch = _torch()
+        if outs is None:
+            outs = [torch.empty_like(r) for r in rhos]
+        ws = workspace if workspace is not None else self.workspace()
+        n = len(self.plans)
+        ra = (_P * n)(*[r.data_ptr() for r in rhos])
+        pa = (_P * n)(*[o.data_ptr() for o in outs])
+        check(lib().pipe_batch_solve(self._h, ra, pa, _P(ws.data_ptr()), _stream_ptr(stream)))
+        return outs
+
+    def close(self):
+        if self._h is not None:
+            check(lib().pipe_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if self._h is not None:
+                lib().pipe_batch_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def fft_lines(x, length, direction=-1, stream=None):
+    """Batched 1-D DFT of the rows of a complex (howmany, n_in) CUDA tensor, zero-padded to `length`."""
+    torch = _torch()
+    if x.dtype not in (torch.complex64, torch.complex128) or x.dim() != 2:
+        raise TypeError("expected a 2-D complex tensor")
+    x = x.contiguous()
+    rb = 8 if x.dtype == torch.complex128 else 4
+    out = torch.empty((x.shape[0], length), dtype=x.dtype, device=x.device)
+    check(lib().pipe_fft_lines(rb, length, x.shape[1], x.shape[0], direction, _P(x.data_ptr()),
+                               _P(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def _make_fn():
+    torch = _torch()
+
+    class PipePoissonFn(torch.autograd.Function):
+        """phi = A rho on a GreenPlan; backward applies the adjoint kernel to dL/dphi."""
+
+        @staticmethod
+        def forward(ctx, rho, plan):
+            ctx.plan = plan
+            return plan.solve(rho)
+
+        @staticmethod
+        def backward(ctx, grad_phi):
+            return ctx.plan.adjoint(grad_phi.contiguous()), None
+
+    return PipePoissonFn
+
+
+class _Lazy:
+    _fn = None
+
+    def __getattr__(self, item):
+        if _Lazy._fn is None:
+            _Lazy._fn = _make_fn()
+        return getattr(_Lazy._fn, item)
+
+
+PipePoissonFn = _Lazy()

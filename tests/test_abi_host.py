@@ -1,0 +1,120 @@
+"""Host-side checks of the C ABI: no GPU compute.
+
+The library must load, export every function include/pipe_poisson.h declares,
+and reject bad arguments with the documented status before any HIP call.
+"""
+import ctypes
+import os
+
+import pytest
+
+from paper_1111_4971_amd import pipe
+
+LIB = pipe.LIB_PATH
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libpipe.so not built")
+
+
+def _has_device():
+    # counting devices does not initialise the runtime on this image
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+@needs_lib
+def test_library_exports_every_declared_function():
+    L = pipe.lib()
+    names = pipe.header_functions()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@needs_lib
+def test_status_strings():
+    L = pipe.lib()
+    for code, name in pipe.STATUS.items():
+        assert L.pipe_status_string(code).decode() == name
+
+
+def _plan(*args, **kw):
+    L = pipe.lib()
+    h = ctypes.c_void_p()
+    defaults = dict(mx=8, my=8, lx=0, ly=0, lz=0)
+    defaults.update(kw)
+    st = L.pipe_green_plan_ex(*args, defaults["mx"], defaults["my"], defaults["lx"], defaults["ly"],
+                              defaults["lz"], None, ctypes.byref(h))
+    return st, h
+
+
+@needs_lib
+@pytest.mark.parametrize("args,kw,expect", [
+    ((0, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {}, 1),                     # n < 1
+    ((4, 4, 4, -0.1, 0.1, 0.1, 1.0, 1.0, 0), {}, 1),                    # h <= 0
+    ((4, 4, 4, 0.1, float("nan"), 0.1, 1.0, 1.0, 0), {}, 1),            # NaN
+    ((4, 4, 4, 0.1, 0.1, float("inf"), 1.0, 1.0, 0), {}, 1),            # inf
+    ((4, 4, 4, 0.3, 0.1, 0.1, 1.0, 1.0, 0), {}, 1),                     # node outside the pipe
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 0.0, 0), {}, 1),                     # b = 0
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 7), {}, 1),                     # unknown kind
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0x20), {}, 1),                  # unknown precision
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"mx": 0}, 1),              # no modes
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"lx": 6}, 1),              # L < 2n - 1
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"lx": 9}, 2),              # odd L
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"lx": 10}, 2),             # 10 = 2 * 5 unsupported
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"lz": 2048 * 2}, 2),       # beyond the largest length
+    ((2000, 4, 4, 1e-4, 0.1, 0.1, 1.0, 1.0, 0), {}, 2),                 # no padded length for n
+])
+def test_argument_validation(args, kw, expect):
+    st, h = _plan(*args, **kw)
+    assert st == expect, pipe.lib().pipe_last_error().decode()
+    assert not h.value
+    assert len(pipe.lib().pipe_last_error()) > 0
+
+
+@needs_lib
+def test_node_exactly_on_the_wall_is_accepted_by_validation():
+    if _has_device():
+        pytest.skip("would build a plan on the device")
+    # n h == a exactly (up to rounding): passes validation, then fails only for lack of a device
+    st, _ = _plan(7, 7, 4, 1.0 / 7, 1.0 / 7, 0.1, 1.0, 1.0, 0)
+    assert st == 4
+
+
+@needs_lib
+def test_no_device_is_reported():
+    if _has_device():
+        pytest.skip("a device is present")
+    st, h = _plan(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0)
+    assert st == 4 and not h.value
+    L = pipe.lib()
+    buf = (ctypes.c_double * 16)()
+    assert L.pipe_fft_lines(8, 8, 8, 1, -1, buf, buf, None) == 4
+
+
+@needs_lib
+def test_invalid_handles_are_rejected():
+    L = pipe.lib()
+    bogus = ctypes.c_void_p(0x1234)
+    assert L.pipe_plan_destroy(bogus) == 1
+    assert L.pipe_plan_destroy(None) == 1
+    assert L.pipe_batch_destroy(bogus) == 1
+    info = pipe.PlanInfo()
+    assert L.pipe_plan_info(bogus, ctypes.byref(info)) == 1
+    assert L.pipe_poisson_solve(bogus, bogus, bogus, bogus, None) == 1
+    assert L.pipe_poisson_adjoint(bogus, bogus, bogus, bogus, None) == 1
+    out = ctypes.c_void_p()
+    assert L.pipe_batch_create(None, 0, ctypes.byref(out)) == 1
+    arr = (ctypes.c_void_p * 1)(bogus)
+    assert L.pipe_batch_create(arr, 1, ctypes.byref(out)) == 1
+    assert L.pipe_fft_lines(8, 10, 5, 1, -1, bogus, bogus, None) == 2
+    assert L.pipe_fft_lines(8, 8, 9, 1, -1, bogus, bogus, None) == 1
+    assert L.pipe_fft_lines(2, 8, 8, 1, -1, bogus, bogus, None) == 1
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(pipe, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(pipe, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        pipe.lib()

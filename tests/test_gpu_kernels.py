@@ -1,0 +1,106 @@
+"""GPU unit tests of the pieces of the hot path, each against the oracle or numpy.
+
+* the batched FFT engine (every supported length, both precisions and directions,
+  zero-padded input) against numpy.fft;
+* the on-mesh Green table (Eq. 9 / Eq. 16 at the distances the four terms need)
+  against the oracle's mode sum;
+* the compressed Green spectra against the oracle's literal Eq. 10 transforms.
+"""
+import numpy as np
+import pytest
+
+from helpers import log, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+LENGTHS = [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fft_lines_all_lengths(torch_cuda, prec):
+    torch = torch_cuda
+    from paper_1111_4971_amd import pipe
+    rng = np.random.default_rng(1)
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    tol = 1e-14 if prec == "fp64" else 3e-7
+    for n in LENGTHS:
+        for n_in in sorted({n, n // 2 + 1, 1}):
+            for direction in (-1, 1):
+                log("fft_lines %s len=%d n_in=%d dir=%d" % (prec, n, n_in, direction))
+                x = rng.standard_normal((7, n_in)) + 1j * rng.standard_normal((7, n_in))
+                xt = torch.from_numpy(x).to(device="cuda", dtype=cdt)
+                y = pipe.fft_lines(xt, n, direction).cpu().numpy()
+                xp = np.zeros((7, n), complex)
+                xp[:, :n_in] = x
+                ref = np.fft.fft(xp, axis=1) if direction < 0 else np.fft.ifft(xp, axis=1) * n
+                err = float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+                assert err <= tol, (n, n_in, direction, err)
+
+
+def _small_plan(kind, prec, nx=7, ny=5, nz=9, a=1.0, b=1.3, keep=True, **kw):
+    from paper_1111_4971_amd import pipe
+    hx, hy = a / (nx + 1), 0.9 * b / (ny + 1)
+    return pipe.GreenPlan(nx, ny, nz, hx, hy, 0.11, a, b, kind=kind, precision=prec,
+                          keep_green=keep, **kw), (nx, ny, nz, hx, hy, 0.11, a, b)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_green_table_matches_oracle_small(torch_cuda, kind):
+    from oracle import green
+    log("green table small kind=%d" % kind)
+    plan, (nx, ny, nz, hx, hy, hz, a, b) = _small_plan(kind, "fp64", mx=13, my=9)
+    got = plan.green_table().cpu().numpy()
+    ref = green.R_table(np.arange(2 * nx + 1) * hx, np.arange(2 * ny + 1) * hy, np.arange(nz), hz,
+                        a, b, 13, 9, kind)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("which", ["plain_fp64_32cubed", "igf_long_bunch"])
+def test_green_table_matches_oracle_full_size(torch_cuda, which):
+    from oracle import green
+    from paper_1111_4971_amd import pipe, workloads
+    wl = getattr(workloads, which)()
+    log("green table %s" % which)
+    plan = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind,
+                          precision="fp64", mx=wl.mx, my=wl.my, keep_green=True)
+    got = plan.green_table().cpu().numpy()
+    ref = green.R_table(np.arange(2 * wl.nx + 1) * wl.hx, np.arange(2 * wl.ny + 1) * wl.hy,
+                        np.arange(wl.nz), wl.hz, wl.a, wl.b, wl.mx, wl.my, wl.kind)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-13, err
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_spectra_match_oracle_transforms(torch_cuda, kind, prec):
+    from oracle import fourterm
+    log("spectra kind=%d %s" % (kind, prec))
+    plan, (nx, ny, nz, hx, hy, hz, a, b) = _small_plan(kind, prec, mx=13, my=9)
+    i = plan.info
+    L = (i.lx, i.ly, i.lz)
+    tab, nyq = (t.double().cpu().numpy() for t in plan.spectra())
+    S = fourterm.green_spectra((nx, ny, nz), L, (hx, hy, hz), (a, b, 13, 9), kind)
+    kx, ky, nh = i.lx // 2 + 1, i.ly // 2 + 1, i.lz // 2
+    KX = np.arange(kx)[:, None]
+    KY = np.arange(ky)[None, :]
+    full = np.concatenate([tab, nyq[..., None]], axis=3)        # kz = 0 .. lz/2
+    ref = np.empty_like(full)
+    cc, cr, rc, rr = (s[:kx, :ky, :nh + 1] for s in S)
+    rr2 = S[3][(i.lx - np.arange(kx)) % i.lx][:, :ky, :nh + 1]
+    ref[0] = cc.real
+    ref[1], ref[2] = cr.real, cr.imag
+    ref[3], ref[4] = rc.real, rc.imag
+    ref[5], ref[6] = rr.real, rr.imag
+    ref[7], ref[8] = rr2.real, rr2.imag
+    scale = np.max(np.abs(ref))
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    assert np.max(np.abs(full - ref)) <= tol * scale
+    # the discarded parts really are zero: T_cc is real
+    assert np.max(np.abs(cc.imag)) <= 1e-13 * scale

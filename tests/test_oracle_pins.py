@@ -350,3 +350,16 @@ def test_gradient_oracle_matches_finite_differences():
         lp = gradient.loss(rho + e, A(rho + e), tgt)
         lm = gradient.loss(rho - e, A(rho - e), tgt)
         assert abs((lp - lm) / (2 * eps) - g[idx]) <= 1e-8 * np.max(np.abs(g))
+
+
+def test_sampled_direct_sum_equals_full_direct_sum():
+    rng = np.random.default_rng(27)
+    nx, ny, nz = 5, 4, 6
+    a, b = 1.0, 1.2
+    hx, hy = 0.9 * a / (nx + 1), b / (ny + 1)
+    rho = rng.standard_normal((nx, ny, nz))
+    for kind in (POINT, IGF):
+        full = direct.solve(rho, hx, hy, 0.1, a, b, 9, 7, kind)
+        pts = [(0, 0, 0), (4, 3, 5), (2, 1, 3), (1, 2, 0)]
+        got = direct.solve_at(rho, pts, hx, hy, 0.1, a, b, 9, 7, kind)
+        assert np.allclose(got, [full[p] for p in pts], rtol=1e-13, atol=1e-15 * np.max(np.abs(full)))
