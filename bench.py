@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Open-pipe Poisson solves/s on one MI355X (FP32 and FP64 legs) with roofline and CPU baseline.
+
+Workload: 128 x 128 x 512 mesh (padded 256 x 256 x 1024) in a 1 x 1 pipe,
+z-integrated Green function (IGF), 256 x 256 modes, charge = three seeded
+Gaussian sub-bunches sampled with 2^28 macroparticles and deposited by
+cloud-in-cell.  One step = one full solve (all five kernels: z forward,
+y forward, x forward + mixed product + x inverse, y inverse, z inverse) of
+that charge, input already resident in HBM.  The Green spectra are built once
+per plan before timing (the paper computes them once and reuses them).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py --copy-calibration   (a plain copy of known size, for counter scaling)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "open-pipe Poisson solves/s at 128x128x512 (FP32 vs FP64) + % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+PASS_NAMES = ["z_forward", "y_forward", "x_product", "y_inverse", "z_inverse"]
+KERNEL_NAMES = ["z_r2c_kernel", "strided_kernel<fwd>", "xprod_kernel", "strided_kernel<inv>", "z_c2r_kernel"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_three_bunch_cic.json")
+KERNEL_SOURCES = ["paper_1111_4971_amd/csrc/passes.hip", "paper_1111_4971_amd/csrc/fft_engine.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(leg, kernel_index):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != kernel_source_sha():
+        return None
+    e = t.get("legs", {}).get(leg, {}).get(PASS_NAMES[kernel_index])
+    return None if e is None else float(e["bytes_per_launch"])
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": nbytes, "copy_calibration_bytes_written": nbytes,
+                      "reps": reps}))
+
+
+def time_leg(pipe, torch, wl, precision, steps, warmup):
+    import numpy as np
+    log("[bench] %s: building plan" % precision)
+    plan = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind,
+                          precision=precision, mx=wl.mx, my=wl.my)
+    info = plan.info
+    rho = torch.from_numpy(np.ascontiguousarray(wl.rho)).to(device="cuda", dtype=plan.dtype)
+    phi = torch.empty_like(rho)
+    ws = plan.workspace()
+    for _ in range(warmup):
+        plan.solve(rho, out=phi, workspace=ws)
+    torch.cuda.synchronize()
+    log("[bench] %s: timing %d steps" % (precision, steps))
+    # timed region: K solves, per-kernel HIP events recorded on the solve stream
+    plan.timing_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve(rho, out=phi, workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pass_ms, n = plan.timing_stop()
+    ms_step = (t1 - t0) * 1e3 / steps
+    # the same K solves without events, to show the instrumentation costs nothing
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve(rho, out=phi, workspace=ws)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t2) * 1e3 / steps
+    out = phi.double().cpu().numpy()
+    dom = max(range(5), key=lambda i: pass_ms[i])
+    achieved = info.pass_bytes[dom] / (pass_ms[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(precision, dom)
+    leg = {
+        "value": steps / (t1 - t0),
+        "ms_per_step": ms_step,
+        "ms_per_step_without_events": ms_plain,
+        "events_recorded": n,
+        "plan_build_ms": info.build_ms,
+        "model_bytes_per_solve": info.model_bytes,
+        "model_GBps_whole_solve": info.model_bytes / (ms_step * 1e-3) / 1e9,
+        "passes": {PASS_NAMES[i]: {"kernel": KERNEL_NAMES[i], "ms": pass_ms[i],
+                                   "model_bytes": info.pass_bytes[i],
+                                   "GBps": info.pass_bytes[i] / (pass_ms[i] * 1e-3) / 1e9}
+                   for i in range(5)},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": info.pass_bytes[dom], "avg_launch_ms": pass_ms[dom]},
+    }
+    plan.close()
+    return leg, out
+
+
+def cpu_baseline(wl):
+    """The oracle's literal Eq. 10 (FP64, scipy.fft on all host cores) on one full
+    solve of the same workload; its Green spectra are built first and not timed,
+    as the GPU plan build is not."""
+    from oracle import fourterm
+    g = wl.geometry()
+    L = (2 * wl.nx, 2 * wl.ny, 2 * wl.nz)
+    log("[bench] cpu baseline: oracle spectra build")
+    t = time.perf_counter()
+    spec = fourterm.green_spectra(wl.shape, L, (wl.hx, wl.hy, wl.hz), (wl.a, wl.b, wl.mx, wl.my), wl.kind)
+    build_s = time.perf_counter() - t
+    log("[bench] cpu baseline: oracle solve")
+    t = time.perf_counter()
+    phi = fourterm.solve(wl.rho, L=L, spectra=spec, **g)
+    dt = time.perf_counter() - t
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": fourterm._WORKERS, "kind": "oracle",
+            "sample": "one 128x128x512 IGF solve, FP64, by the oracle's literal four-term Eq. 10 "
+                      "(1 forward + 4 mixed-direction inverse 3-D FFTs, scipy.fft); its Green spectra "
+                      "built beforehand in %.1f s and not timed" % build_s,
+            "seconds": dt}, phi
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--legs", default="fp32,fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    from paper_1111_4971_amd import pipe, workloads
+    pipe.lib()
+    log("[bench] generating the 128x128x512 three-bunch CIC charge")
+    t = time.perf_counter()
+    wl = workloads.three_bunch_cic()
+    log("[bench] generated in %.1f s (%d macroparticles)" % (time.perf_counter() - t, wl.notes["n_particles"]))
+
+    legs = {}
+    outs = {}
+    for prec in args.legs.split(","):
+        legs[prec], outs[prec] = time_leg(pipe, torch, wl, prec, args.steps, args.warmup)
+        log("[bench] %s: %.1f solves/s, %.3f ms/solve, dominant %s at %.0f GB/s" % (
+            prec, legs[prec]["value"], legs[prec]["ms_per_step"], legs[prec]["roofline"]["kernel"],
+            legs[prec]["roofline"]["achieved"]))
+
+    primary = "fp32" if "fp32" in legs else list(legs)[0]
+    res = {
+        "metric": METRIC,
+        "value": legs[primary]["value"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": legs[primary]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if primary == "fp32" else "f64",
+        "data": "synthetic: three seeded Gaussian sub-bunches, 2^28 CIC macroparticles",
+        "config": {"workload": "three_bunch_cic 128x128x512 (padded 256x256x1024), pipe 1x1, IGF Green "
+                               "function, 256x256 modes, h=1/129, hz=20/511",
+                   "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "lx": 2 * wl.nx, "ly": 2 * wl.ny, "lz": 2 * wl.nz,
+                   "green": "IGF_Z", "modes": [wl.mx, wl.my], "n_particles": wl.notes["n_particles"],
+                   "peak_node_rel_noise": wl.notes["peak_rel_noise"]},
+        "roofline": legs[primary]["roofline"],
+        "legs": legs,
+    }
+    if "fp32" in legs and "fp64" in legs:
+        res["fp32_speedup_over_fp64"] = legs["fp32"]["value"] / legs["fp64"]["value"]
+        d = outs["fp32"] - outs["fp64"]
+        res["fp32_vs_fp64_rel_l2"] = float(np.linalg.norm(d) / np.linalg.norm(outs["fp64"]))
+        res["fp32_vs_fp64_rel_max"] = float(np.max(np.abs(d)) / np.max(np.abs(outs["fp64"])))
+    if not args.no_cpu_baseline:
+        cb, ophi = cpu_baseline(wl)
+        res["cpu_baseline"] = cb
+        if "fp64" in outs:
+            res["fp64_vs_oracle_rel_l2"] = float(np.linalg.norm(outs["fp64"] - ophi) / np.linalg.norm(ophi))
+        if "fp32" in outs:
+            res["fp32_vs_oracle_rel_l2"] = float(np.linalg.norm(outs["fp32"] - ophi) / np.linalg.norm(ophi))
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

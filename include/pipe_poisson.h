@@ -200,6 +200,18 @@ pipe_status_t pipe_poisson_solve_timed(pipe_plan_t plan, const void* rho, void* 
                                        void* workspace, void* hip_stream, float* pass_ms);
 
 /*
+ * pipe_plan_timing -- per-kernel timing of ordinary solves on this plan.
+ * max_solves > 0 starts recording: each of the next max_solves calls of
+ * pipe_poisson_solve / pipe_poisson_adjoint on this plan records a HIP event
+ * on its own stream before, between and after its five kernels (no host
+ * synchronisation).  max_solves = 0 stops recording, waits for the last
+ * recorded solve and writes the mean elapsed time of each kernel over the
+ * recorded solves to pass_ms_mean[5] and their number to *count (either may
+ * be NULL).  Not thread-safe with concurrent solves on the same plan.
+ */
+pipe_status_t pipe_plan_timing(pipe_plan_t plan, int max_solves, float* pass_ms_mean, int* count);
+
+/*
  * pipe_fft_lines -- the library's batched 1-D complex DFT, exposed for tests:
  * for each of howmany lines (line l at in + l*n_in, out + l*len, complex
  * interleaved, real_bytes 4 or 8), out = sum_{e<n_in} in[e] W^{+-ek} for

@@ -148,6 +148,9 @@ struct pipe_plan_s {
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
     size_t ws_bytes = 0;
+    // event timing (pipe_plan_timing): 6 events per recorded solve
+    std::vector<hipEvent_t> tev;
+    int tmax = 0, tn = 0;
 };
 
 namespace {
@@ -265,6 +268,7 @@ void plan_free(pipe_plan_s* p) {
     if (!p) return;
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
+    for (hipEvent_t e : p->tev) (void)hipEventDestroy(e);
     if (p->table) (void)hipFree(p->table);
     if (p->nyq) (void)hipFree(p->nyq);
     if (p->green) (void)hipFree(p->green);
@@ -326,6 +330,7 @@ pipe_status_t solve_impl(pipe_plan_t plan, const void* rho, void* phi, void* ws,
     HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
     if (cur != plan->device) HIP_TRY(hipSetDevice(plan->device), "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    if (!ev && plan->tn < plan->tmax) ev = &plan->tev[6 * (size_t)plan->tn++];
     s = plan->rb == 8 ? run_passes<double>(plan, rho, phi, ws, st, adjoint, ev)
                       : run_passes<float>(plan, rho, phi, ws, st, adjoint, ev);
     if (cur != plan->device) (void)hipSetDevice(cur);
@@ -444,6 +449,42 @@ pipe_status_t pipe_poisson_solve_timed(pipe_plan_t plan, const void* rho, void* 
     }
     for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
     return s;
+}
+
+pipe_status_t pipe_plan_timing(pipe_plan_t p, int max_solves, float* pass_ms_mean, int* count) {
+    if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
+    if (max_solves < 0) return fail(PIPE_ERR_INVALID_ARG, "max_solves must be >= 0");
+    if (max_solves > 0) {
+        const size_t need = 6 * (size_t)max_solves;
+        while (p->tev.size() < need) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+            p->tev.push_back(e);
+        }
+        p->tmax = max_solves;
+        p->tn = 0;
+        return PIPE_OK;
+    }
+    const int n = p->tn;
+    p->tmax = 0;
+    p->tn = 0;
+    if (count) *count = n;
+    if (pass_ms_mean) {
+        for (int i = 0; i < 5; ++i) pass_ms_mean[i] = 0.f;
+        if (n > 0) {
+            HIP_TRY(hipEventSynchronize(p->tev[6 * (size_t)(n - 1) + 5]), "hipEventSynchronize");
+            double acc[5] = {0, 0, 0, 0, 0};
+            for (int s = 0; s < n; ++s)
+                for (int i = 0; i < 5; ++i) {
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, p->tev[6 * (size_t)s + i], p->tev[6 * (size_t)s + i + 1]),
+                            "hipEventElapsedTime");
+                    acc[i] += ms;
+                }
+            for (int i = 0; i < 5; ++i) pass_ms_mean[i] = (float)(acc[i] / n);
+        }
+    }
+    return PIPE_OK;
 }
 
 pipe_status_t pipe_plan_destroy(pipe_plan_t p) {

@@ -83,6 +83,7 @@ def lib():
         "pipe_plan_green_table": ([_P, _P, _P], _I),
         "pipe_plan_spectra": ([_P, _P, _P], _I),
         "pipe_fft_lines": ([_I, _I, _I, _I, _I, _P, _P, _P], _I),
+        "pipe_plan_timing": ([_P, _I, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_I)], _I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -195,6 +196,16 @@ class GreenPlan:
         check(lib().pipe_poisson_solve_timed(self.handle, _P(x.data_ptr()), _P(out.data_ptr()),
                                              _P(ws.data_ptr()), _stream_ptr(stream), ms))
         return out, list(ms)
+
+    def timing_start(self, max_solves):
+        check(lib().pipe_plan_timing(self.handle, int(max_solves), None, None))
+
+    def timing_stop(self):
+        """Mean ms of each of the five kernels over the recorded solves, and their count."""
+        ms = (ctypes.c_float * 5)()
+        n = _I()
+        check(lib().pipe_plan_timing(self.handle, 0, ms, ctypes.byref(n)))
+        return list(ms), n.value
 
     def green_table(self):
         torch = _torch()

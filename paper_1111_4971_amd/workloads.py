@@ -13,6 +13,7 @@ centred, Z_k = (k - (nz-1)/2) h_z.  "Unit charge" means h_x h_y h_z sum(rho) = 1
 """
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -112,8 +113,12 @@ def igf_long_bunch(seed=2):
     return Workload("igf_long_bunch", nx, ny, nz, hx, hy, hz, a, b, IGF_Z, 128, 128, rho)
 
 
-def _cic_deposit(px, py, pz, nx, ny, nz, hx, hy, hz, out):
-    """Cloud-in-cell (trilinear) deposit of unit-weight particles onto the nodes."""
+def _cic_weights(px, py, pz, nx, ny, nz, hx, hy, hz):
+    """Cloud-in-cell (trilinear) node indices and weights of unit-weight particles.
+
+    Particles outside the node box are dropped.  Returns (index, weight) arrays
+    holding the 8 corner contributions of every kept particle.
+    """
     X0, Y0 = hx, hy
     Z0 = -0.5 * (nz - 1) * hz
     tx, ty, tz = (px - X0) / hx, (py - Y0) / hy, (pz - Z0) / hz
@@ -122,14 +127,18 @@ def _cic_deposit(px, py, pz, nx, ny, nz, hx, hy, hz, out):
     ix, iy, iz = tx.astype(np.int64), ty.astype(np.int64), tz.astype(np.int64)
     fx, fy, fz = tx - ix, ty - iy, tz - iz
     base = (ix * ny + iy) * nz + iz
-    size = nx * ny * nz
+    m = base.size
+    idx = np.empty(8 * m, dtype=np.int64)
+    wts = np.empty(8 * m)
+    c = 0
     for dx, wx in ((0, 1.0 - fx), (1, fx)):
         for dy, wy in ((0, 1.0 - fy), (1, fy)):
             wxy = wx * wy
             for dz, wz in ((0, 1.0 - fz), (1, fz)):
-                idx = base + (dx * ny + dy) * nz + dz
-                out += np.bincount(idx, weights=wxy * wz, minlength=size)
-    return int(keep.sum())
+                idx[c * m:(c + 1) * m] = base + ((dx * ny + dy) * nz + dz)
+                wts[c * m:(c + 1) * m] = wxy * wz
+                c += 1
+    return idx, wts
 
 
 def three_bunch_cic(nx=128, ny=128, nz=512, seed=3, max_particles=1 << 28, target_peak=1.0e4):
@@ -158,16 +167,34 @@ def three_bunch_cic(nx=128, ny=128, nz=512, seed=3, max_particles=1 << 28, targe
         peak = max(peak, mix, dens)
     n_p = int(min(max_particles, math.ceil(target_peak / (peak * hx * hy * hz))))
     counts = rng.multinomial(n_p, w)
-    rho = np.zeros(nx * ny * nz)
-    kept = 0
-    chunk = 1 << 22
+    # Chunks of at most 2^20 particles, each drawn from its own child stream of
+    # the seed (SeedSequence.spawn), generated in worker threads and
+    # accumulated in chunk order, so the result does not depend on timing.
+    chunk = 1 << 20
+    jobs = []
     for c in range(3):
         left = int(counts[c])
         while left > 0:
-            m = min(chunk, left)
-            p = rng.standard_normal((3, m)) * sig[c][:, None] + cen[c][:, None]
-            kept += _cic_deposit(p[0], p[1], p[2], nx, ny, nz, hx, hy, hz, rho)
-            left -= m
+            jobs.append((c, min(chunk, left)))
+            left -= jobs[-1][1]
+    streams = np.random.SeedSequence(seed).spawn(len(jobs))
+
+    def draw(j):
+        c, m = jobs[j]
+        g = np.random.default_rng(streams[j])
+        p = g.standard_normal((3, m)) * sig[c][:, None] + cen[c][:, None]
+        return _cic_weights(p[0], p[1], p[2], nx, ny, nz, hx, hy, hz)
+
+    import concurrent.futures
+    import torch
+    acc = torch.zeros(nx * ny * nz, dtype=torch.float64)
+    kept = 0
+    workers = min(8, os.cpu_count() or 1)
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        for idx, wts in ex.map(draw, range(len(jobs))):
+            acc.index_add_(0, torch.from_numpy(idx), torch.from_numpy(wts))
+            kept += idx.size // 8
+    rho = acc.numpy()
     rho = rho.reshape(nx, ny, nz)
     peak_hits = float(rho.max())
     rho = _unit_charge(rho, hx, hy, hz)

@@ -88,12 +88,21 @@ def test_spectra_match_oracle_transforms(torch_cuda, kind, prec):
     tab, nyq = (t.double().cpu().numpy() for t in plan.spectra())
     S = fourterm.green_spectra((nx, ny, nz), L, (hx, hy, hz), (a, b, 13, 9), kind)
     kx, ky, nh = i.lx // 2 + 1, i.ly // 2 + 1, i.lz // 2
-    KX = np.arange(kx)[:, None]
-    KY = np.arange(ky)[None, :]
     full = np.concatenate([tab, nyq[..., None]], axis=3)        # kz = 0 .. lz/2
+    # The oracle holds Eq. 10's mixed-direction transforms (F^fff, F^fbf, F^bff,
+    # F^bbf); the plan stores plain forward transforms.  A backward transform
+    # along a dimension is the forward one at the reflected index, so
+    # T_cr(kx,ky) = S_cr(kx,-ky), T_rc(kx,ky) = S_rc(-kx,ky), T_rr(kx,ky) = S_rr(-kx,-ky).
+    px = np.arange(kx)
+    py = np.arange(ky)
+    mx_ = (i.lx - px) % i.lx
+    my_ = (i.ly - py) % i.ly
+    cc = S[0][np.ix_(px, py)][..., :nh + 1]
+    cr = S[1][np.ix_(px, my_)][..., :nh + 1]
+    rc = S[2][np.ix_(mx_, py)][..., :nh + 1]
+    rr = S[3][np.ix_(mx_, my_)][..., :nh + 1]
+    rr2 = S[3][np.ix_(px, my_)][..., :nh + 1]                 # T_rr(-kx, ky)
     ref = np.empty_like(full)
-    cc, cr, rc, rr = (s[:kx, :ky, :nh + 1] for s in S)
-    rr2 = S[3][(i.lx - np.arange(kx)) % i.lx][:, :ky, :nh + 1]
     ref[0] = cc.real
     ref[1], ref[2] = cr.real, cr.imag
     ref[3], ref[4] = rc.real, rc.imag
