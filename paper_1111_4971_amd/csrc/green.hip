@@ -153,7 +153,7 @@ __global__ void arrange_kernel(double* xi, const double* __restrict__ rbar, int 
 // packed into slot 0 as A + iB).  term: 0 cc, 1 cr, 2 rc, 3 rr.
 template <typename out_t>
 __global__ void compress_kernel(const double2* __restrict__ S, out_t* table, out_t* nyq, int term, int lx, int ly,
-                                int nh) {
+                                int nh, int tile) {
     const int kxo_n = lx / 2 + 1, kyo_n = ly / 2 + 1;
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long total = (long)kxo_n * kyo_n * nh;
@@ -161,8 +161,10 @@ __global__ void compress_kernel(const double2* __restrict__ S, out_t* table, out
     const int kz = (int)(i % nh);
     const int kyo = (int)((i / nh) % kyo_n);
     const int kxo = (int)(i / ((long)nh * kyo_n));
-    const long plane = total, nplane = (long)kxo_n * kyo_n;
-    const long ni = (long)kxo * kyo_n + kyo;
+    const int ntiles = (nh + tile - 1) / tile;
+    // tile-blocked position of (kxo, kyo, kz), plane p at ti + p * tile; kz = lz/2 at ni + p
+    const long ti = ((((long)kyo * ntiles + kz / tile) * kxo_n + kxo) * 9) * tile + kz % tile;
+    const long ni = ((long)kyo * kxo_n + kxo) * 9;
     auto at = [&](int kx, int ky) { return S[((long)kx * ly + ky) * nh + kz]; };
     // value at (kx, ky): main (kz) and, for kz = 0, the kz = lz/2 part
     auto split = [&](int kx, int ky, double2& A, double2& B) {
@@ -181,8 +183,8 @@ __global__ void compress_kernel(const double2* __restrict__ S, out_t* table, out
     double2 A, B, A2, B2;
     split(kxo, kyo, A, B);
     auto put = [&](int pl, double va, double vb) {
-        table[pl * plane + i] = (out_t)va;
-        if (kz == 0) nyq[pl * nplane + ni] = (out_t)vb;
+        table[ti + (long)pl * tile] = (out_t)va;
+        if (kz == 0) nyq[ni + pl] = (out_t)vb;
     };
     switch (term) {
         case 0: put(0, A.x, B.x); break;
@@ -195,6 +197,26 @@ __global__ void compress_kernel(const double2* __restrict__ S, out_t* table, out
             put(7, A2.x, B2.x);
             put(8, A2.y, B2.y);
             break;
+    }
+}
+
+// Tile-blocked table -> 9 planes [p][kx][ky][kz] followed by 9 planes [p][kx][ky] (kz = lz/2).
+template <typename T_>
+__global__ void untile_kernel(const T_* __restrict__ table, const T_* __restrict__ nyq, T_* out, int lx, int ly,
+                              int nh, int tile) {
+    const int kxo_n = lx / 2 + 1, kyo_n = ly / 2 + 1;
+    const long plane = (long)kxo_n * kyo_n * nh;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= plane) return;
+    const int kz = (int)(i % nh);
+    const int kyo = (int)((i / nh) % kyo_n);
+    const int kxo = (int)(i / ((long)nh * kyo_n));
+    const int ntiles = (nh + tile - 1) / tile;
+    const long ti = ((((long)kyo * ntiles + kz / tile) * kxo_n + kxo) * 9) * tile + kz % tile;
+    for (int p = 0; p < 9; ++p) out[p * plane + i] = table[ti + (long)p * tile];
+    if (kz == 0) {
+        const long np_ = (long)kxo_n * kyo_n, ni = (long)kxo * kyo_n + kyo;
+        for (int p = 0; p < 9; ++p) out[9 * plane + p * np_ + ni] = nyq[((long)kyo * kxo_n + kxo) * 9 + p];
     }
 }
 
@@ -232,14 +254,28 @@ hipError_t launch_arrange(double* xi, const double* rbar, int nx, int ny, int nz
 }
 
 hipError_t launch_compress(const void* spec, void* table, void* nyq, int real_bytes, int term, int lx, int ly,
-                           int nh, hipStream_t st) {
+                           int nh, int tile, hipStream_t st) {
     const long n = (long)(lx / 2 + 1) * (ly / 2 + 1) * nh;
+    if (tile < 1) return hipErrorInvalidValue;
     if (real_bytes == 8)
         hipLaunchKernelGGL(compress_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                           (const double2*)spec, (double*)table, (double*)nyq, term, lx, ly, nh);
+                           (const double2*)spec, (double*)table, (double*)nyq, term, lx, ly, nh, tile);
     else
         hipLaunchKernelGGL(compress_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                           (const double2*)spec, (float*)table, (float*)nyq, term, lx, ly, nh);
+                           (const double2*)spec, (float*)table, (float*)nyq, term, lx, ly, nh, tile);
+    return hipGetLastError();
+}
+
+hipError_t launch_untile(const void* table, const void* nyq, void* out, int real_bytes, int lx, int ly, int nh,
+                         int tile, hipStream_t st) {
+    const long n = (long)(lx / 2 + 1) * (ly / 2 + 1) * nh;
+    if (tile < 1) return hipErrorInvalidValue;
+    if (real_bytes == 8)
+        hipLaunchKernelGGL(untile_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const double*)table,
+                           (const double*)nyq, (double*)out, lx, ly, nh, tile);
+    else
+        hipLaunchKernelGGL(untile_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const float*)table,
+                           (const float*)nyq, (float*)out, lx, ly, nh, tile);
     return hipGetLastError();
 }
 

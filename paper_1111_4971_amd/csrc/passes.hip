@@ -172,9 +172,9 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
 // the nx nonzero rows, the mixed product on each orbit {+-kx} x {+-ky}, inverse
 // x transform, rows i < nx written back in place.
 //
-// Spectra table (plan precision), 9 planes over orbits (kx <= lx/2, ky <= ly/2, kz):
+// Spectra table (plan precision), 9 values per orbit (kx <= lx/2, ky <= ly/2, kz):
 //   0: T_cc (real)   1,2: T_cr   3,4: T_rc   5,6: T_rr(kx,ky)   7,8: T_rr(-kx,ky)
-// and the same 9 planes for kz = lz/2 in `nyq`.  Symmetries of real Green
+// stored tile-blocked (see xprod_tile), and the same 9 values for kz = lz/2 in `nyq`.  Symmetries of real Green
 // arrays: T_cc real and even in kx, ky; T_cr even in kx, T_cr(kx,-ky) = conj;
 // T_rc even in ky, T_rc(-kx,ky) = conj; T_rr(-kx,-ky) = conj T_rr(kx,ky).
 template <typename real> struct Orbit {
@@ -182,15 +182,16 @@ template <typename real> struct Orbit {
     cplx<real> cr, rc, rr, rr2;
 };
 
+// Nine values of one orbit, `stride` apart (T in the tiled table, 1 for kz = lz/2).
 template <typename real>
-__device__ __forceinline__ Orbit<real> load_orbit(const real* __restrict__ tab, long plane, long i) {
+__device__ __forceinline__ Orbit<real> load_orbit(const real* __restrict__ e, int stride) {
     using C = cplx<real>;
     Orbit<real> o;
-    o.cc = tab[i];
-    o.cr = cmake<C>(tab[plane + i], tab[2 * plane + i]);
-    o.rc = cmake<C>(tab[3 * plane + i], tab[4 * plane + i]);
-    o.rr = cmake<C>(tab[5 * plane + i], tab[6 * plane + i]);
-    o.rr2 = cmake<C>(tab[7 * plane + i], tab[8 * plane + i]);
+    o.cc = e[0];
+    o.cr = cmake<C>(e[stride], e[2 * stride]);
+    o.rc = cmake<C>(e[3 * stride], e[4 * stride]);
+    o.rr = cmake<C>(e[5 * stride], e[6 * stride]);
+    o.rr2 = cmake<C>(e[7 * stride], e[8 * stride]);
     return o;
 }
 
@@ -264,9 +265,10 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     __syncthreads();
 
     const int kyo = ky;
-    const long plane = (long)(N / 2 + 1) * (ly / 2 + 1) * nh;
-    const long nplane = (long)(N / 2 + 1) * (ly / 2 + 1);
-    for (int w = threadIdx.x; w < (N / 2 + 1) * T; w += NT) {
+    constexpr int NKX = N / 2 + 1;
+    const int ntiles = (nh + T - 1) / T;
+    const real* tblock = table + ((long)kyo * ntiles + blockIdx.x) * NKX * 9 * T;
+    for (int w = threadIdx.x; w < NKX * T; w += NT) {
         const int cc = w % T, o = w / T;
         const long kzz = (long)blockIdx.x * T + cc;
         if (kzz >= nh) continue;
@@ -275,8 +277,7 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
         C* L1 = lds + N * T + cc;
         C r[4] = {L0[o * T], L0[on * T], L1[o * T], L1[on * T]};
         C p[4];
-        const long ti = ((long)o * (ly / 2 + 1) + kyo) * nh + kzz;
-        const Orbit<real> ob = load_orbit(table, plane, ti);
+        const Orbit<real> ob = load_orbit(tblock + (long)o * 9 * T + cc, T);
         if (kzz != 0) {
             orbit_product<ADJ>(ob, r, p);
         } else {
@@ -290,7 +291,7 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
                 ra[q] = cscale(s, (real)0.5);
                 rb[q] = cscale(cmake<C>(d.y, -d.x), (real)0.5);
             }
-            const Orbit<real> obn = load_orbit(nyq, nplane, (long)o * (ly / 2 + 1) + kyo);
+            const Orbit<real> obn = load_orbit(nyq + ((long)kyo * NKX + o) * 9, 1);
             orbit_product<ADJ>(ob, ra, pa);
             orbit_product<ADJ>(obn, rb, pb);
 #pragma unroll
@@ -403,6 +404,16 @@ template <typename real, int N> constexpr int xprod_T() {
     int t = 16;
     while (t > 1 && (2 * N * t * bytes > 64 * 1024 || 2 * P * t > 1024)) t /= 2;
     return t;
+}
+
+int xprod_tile(int lx, int real_bytes) {
+    switch (lx) {
+#define X(N_) \
+    case N_: return real_bytes == 8 ? xprod_T<double, N_>() : xprod_T<float, N_>();
+        PIPE_FOR_EACH_N(X)
+#undef X
+    }
+    return 0;
 }
 
 template <typename real>

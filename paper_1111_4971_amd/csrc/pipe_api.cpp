@@ -142,9 +142,10 @@ struct pipe_plan_s {
     double hx, hy, hz, a, b;
     int device;
     DeviceCtx* ctx;
-    void* table = nullptr;   // 9 planes (lx/2+1)(ly/2+1) nh
-    void* nyq = nullptr;     // 9 planes (lx/2+1)(ly/2+1)
+    void* table = nullptr;   // tile-blocked spectra, 9 values per orbit (see xprod_tile)
+    void* nyq = nullptr;     // kz = lz/2 values, 9 per orbit (inside the table allocation)
     size_t table_elems = 0, nyq_elems = 0;
+    int tile = 0;            // kz tile of the table layout
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
     size_t ws_bytes = 0;
@@ -169,7 +170,8 @@ void plan_pass_bytes(const pipe_plan_s* p, double out[5]) {
     const double phys = (double)p->nx * p->ny * p->nz * rb;
     const double a1 = (double)p->nx * p->ny * p->nh * cb;
     const double a2 = (double)p->nx * p->ly * p->nh * cb;
-    const double tab = 9.0 * (p->table_elems / 9 + p->nyq_elems / 9) * rb;
+    const double orbits = (double)(p->lx / 2 + 1) * (p->ly / 2 + 1);
+    const double tab = 9.0 * orbits * (p->nh + 1) * rb;   // values read once per solve
     out[0] = phys + a1;
     out[1] = a1 + a2;
     out[2] = 2.0 * a2 + tab;
@@ -253,7 +255,7 @@ pipe_status_t build_spectra(pipe_plan_s* p, hipStream_t st, bool keep_green) {
         HIP_TRY(launch_strided<double>(lx, false, buf, buf, lx, lx, (long)ly * nh, (long)ly * nh, (long)ly * nh, 0, 0, 1,
                                        p->ctx->tw, st),
                 "spectra x transform");
-        HIP_TRY(launch_compress(buf, p->table, p->nyq, p->rb, term, lx, ly, nh, st), "spectra compression");
+        HIP_TRY(launch_compress(buf, p->table, p->nyq, p->rb, term, lx, ly, nh, p->tile, st), "spectra compression");
     }
     if (keep_green) {
         HIP_TRY(dev_alloc((void**)&p->green, sizeof(double) * (size_t)px * qy * rz), "allocation (kept Green table)");
@@ -270,7 +272,6 @@ void plan_free(pipe_plan_s* p) {
     (void)hipDeviceSynchronize();
     for (hipEvent_t e : p->tev) (void)hipEventDestroy(e);
     if (p->table) (void)hipFree(p->table);
-    if (p->nyq) (void)hipFree(p->nyq);
     if (p->green) (void)hipFree(p->green);
     delete p;
 }
@@ -380,14 +381,17 @@ pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, d
     p->hx = hx; p->hy = hy; p->hz = hz; p->a = a; p->b = b;
     p->device = dev; p->ctx = ctx;
     const size_t orbits = (size_t)(lx / 2 + 1) * (ly / 2 + 1);
-    p->table_elems = 9 * orbits * p->nh;
+    p->tile = xprod_tile(lx, p->rb);
+    const size_t ntiles = (p->nh + p->tile - 1) / p->tile;
+    p->table_elems = 9 * orbits * ntiles * p->tile;
     p->nyq_elems = 9 * orbits;
-    e = dev_alloc(&p->table, p->table_elems * p->rb);
-    if (e == hipSuccess) e = dev_alloc(&p->nyq, p->nyq_elems * p->rb);
+    e = dev_alloc(&p->table, (p->table_elems + p->nyq_elems) * p->rb);
+    if (e == hipSuccess) e = hipMemset(p->table, 0, (p->table_elems + p->nyq_elems) * p->rb);
     if (e != hipSuccess) {
         plan_free(p);
         return hip_fail(e, "allocation (Green spectra)");
     }
+    p->nyq = (char*)p->table + p->table_elems * p->rb;
     s = build_spectra(p, (hipStream_t)hip_stream, keep);
     if (s != PIPE_OK) {
         plan_free(p);
@@ -507,10 +511,8 @@ pipe_status_t pipe_plan_spectra(pipe_plan_t p, void* out, void* stream) {
     if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
     if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
     hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(hipMemcpyAsync(out, p->table, p->table_elems * p->rb, hipMemcpyDeviceToDevice, st), "copy");
-    HIP_TRY(hipMemcpyAsync((char*)out + p->table_elems * p->rb, p->nyq, p->nyq_elems * p->rb,
-                           hipMemcpyDeviceToDevice, st), "copy");
-    HIP_TRY(hipStreamSynchronize(st), "copy");
+    HIP_TRY(launch_untile(p->table, p->nyq, out, p->rb, p->lx, p->ly, p->nh, p->tile, st), "spectra copy");
+    HIP_TRY(hipStreamSynchronize(st), "spectra copy");
     return PIPE_OK;
 }
 

@@ -41,6 +41,14 @@ template <typename real>
 hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh,
                         const real* table, const real* nyq, const TwiddleBank& tw, hipStream_t s);
 
+// kz tile width of the fused x pass for padded length lx (0 if unsupported).
+// The Green spectra are stored tile-blocked to match: for orbit row kyo, kz tile
+// t, orbit kx = o, plane p (0..8) and column c < T the value sits at
+//   (((kyo * ntiles + t) * (lx/2 + 1) + o) * 9 + p) * T + c,   kz = t * T + c,
+// so one block of the fused pass reads one contiguous run.  The kz = lz/2
+// values sit at (kyo * (lx/2 + 1) + o) * 9 + p.
+int xprod_tile(int lx, int real_bytes);
+
 // Green evaluation (green.hip).
 hipError_t launch_cos_table(double* out, int np, int m, double s, hipStream_t st);
 hipError_t launch_modes(double* d, int mx, int my, int rz, double a, double b, double hz, int igf,
@@ -51,6 +59,8 @@ hipError_t launch_gemm_f64(const double* A, const double* B, double* C, int M, i
 hipError_t launch_arrange(double* xi, const double* rbar, int nx, int ny, int nz, int lx, int ly,
                           int lz, int xcorr, int ycorr, hipStream_t st);
 hipError_t launch_compress(const void* spec, void* table, void* nyq, int real_bytes, int term,
-                           int lx, int ly, int nh, hipStream_t st);
+                           int lx, int ly, int nh, int tile, hipStream_t st);
+hipError_t launch_untile(const void* table, const void* nyq, void* out, int real_bytes, int lx, int ly, int nh,
+                         int tile, hipStream_t st);
 
 }  // namespace pipe

@@ -165,3 +165,38 @@ def test_igf_long_bunch_full_field(torch_cuda):
     d = direct.solve_at(wl.rho, pts, **g)
     sel = np.array([got[p] for p in pts])
     assert np.max(np.abs(sel - d)) <= 1e-12 * np.max(np.abs(got))
+
+
+@pytest.fixture(scope="module")
+def three_bunch():
+    from paper_1111_4971_amd import workloads
+    log("generating three_bunch_cic")
+    return workloads.three_bunch_cic()
+
+
+@pytest.fixture(scope="module")
+def three_bunch_o3(three_bunch):
+    from oracle import modespace
+    log("oracle O3 on three_bunch_cic")
+    return modespace.solve(three_bunch.rho, **three_bunch.geometry())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_three_bunch_128x128x512_full_field(torch_cuda, three_bunch, three_bunch_o3, prec):
+    """The benchmark workload in the benchmark's launch configuration: whole field
+    against the mode-space oracle, and the direct sum at sampled nodes."""
+    from oracle import direct, modespace
+    from helpers import plan_for
+    wl = three_bunch
+    log("three_bunch_cic %s" % prec)
+    got = gpu_solve(plan_for(wl, prec), wl.rho)
+    if prec == "fp32":
+        ref = modespace.solve(oracle_input(wl.rho, prec), **wl.geometry())
+    else:
+        ref = three_bunch_o3
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
+    if prec == "fp64":
+        pts = _sample_points(wl.shape, 4, 3)
+        d = direct.solve_at(wl.rho, pts, **wl.geometry())
+        sel = np.array([got[p] for p in pts])
+        assert np.max(np.abs(sel - d)) <= 1e-12 * np.max(np.abs(got))
