@@ -52,19 +52,58 @@ template <typename C> struct LdsLine {
 
 constexpr int ce_max(int a, int b) { return a > b ? a : b; }
 
+// Launch-shape constants (overridable at build time for tuning sweeps).
+#ifndef PIPE_LDS_CAP
+#define PIPE_LDS_CAP 65536   // LDS bytes a y-pass or fused x-pass block may use
+#endif
+#ifndef PIPE_Z_THREADS
+#define PIPE_Z_THREADS 256   // threads per block of the z passes (lines per block = this / P)
+#endif
+#ifndef PIPE_XPROD_TMAX
+#define PIPE_XPROD_TMAX 8    // widest kz tile of the fused x pass
+#endif
+#ifndef PIPE_STRIDED_TMAX
+#define PIPE_STRIDED_TMAX 32 // widest column tile of the y passes
+#endif
+// lines per block of the z passes: PIPE_Z_THREADS / P, halved until the block's LDS fits PIPE_LDS_CAP
+#ifndef PIPE_TW_LDS
+#define PIPE_TW_LDS 1        // stage twiddle tables in LDS at block start
+#endif
+
+// Copy n twiddles into LDS (no barrier: every use follows a later barrier).
+template <typename C>
+__device__ __forceinline__ const C* stage_twiddles(C* s_tw, const C* __restrict__ tw, int n) {
+#if PIPE_TW_LDS
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s_tw[i] = tw[i];
+    return s_tw;
+#else
+    return tw;
+#endif
+}
+
+template <typename real, int NH> constexpr int z_lines() {
+    int l = ce_max(1, PIPE_Z_THREADS / (NH / Plan<NH>::E));
+    while (l > 1 && l * (NH + NH / 16 + 1) * 2 * (int)sizeof(real) > PIPE_LDS_CAP) l /= 2;
+    return l;
+}
+
 // P1 / spectra z pass: real lines of n_in values (zero-padded to 2*NH) -> NH packed bins.
 // A real line x of length L = 2 NH is read as z[m] = x[2m] + i x[2m+1]; with
 // Z = DFT_NH(z) the half spectrum is
 //   X[k] = (Z[k] + conj Z[NH-k]) / 2 - i W_L^k (Z[k] - conj Z[NH-k]) / 2,
 //   X[0] = Re Z[0] + Im Z[0],  X[NH] = Re Z[0] - Im Z[0]  (stored as slot 0 = (X[0], X[NH])).
+// vec2: n_in and in_pitch even and `in` 2-element aligned, so x[2m], x[2m+1] load as one pair.
 template <typename real, int NH>
-__global__ __launch_bounds__(ce_max(1, 256 / (NH / Plan<NH>::E)) * (NH / Plan<NH>::E))
+__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH>::E)))
 void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long out_pitch, long nlines,
-                  const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2) {
+                  const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2) {
     using C = cplx<real>;
-    constexpr int E = Plan<NH>::E, P = NH / E, LPW = ce_max(1, 256 / P);
+    constexpr int E = Plan<NH>::E, P = NH / E, LPW = z_lines<real, NH>();
     constexpr int PADN = NH + NH / 16 + 1;
     __shared__ C lds[LPW * PADN];
+    __shared__ C s_tw[NH], s_tw2[NH];
+    tw = stage_twiddles(s_tw, tw, NH);
+    tw2 = stage_twiddles(s_tw2, tw2, NH);
     const int t = threadIdx.x % P, l = threadIdx.x / P;
     const long line = (long)blockIdx.x * LPW + l;
     const bool active = line < nlines;
@@ -74,6 +113,9 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     fft_line<NH, false, false>(
         t, tw,
         [&](int m) -> C {
+            if (vec2) {
+                return (active && 2 * m < n_in) ? reinterpret_cast<const C*>(src)[m] : cmake<C>(0, 0);
+            }
             real x0 = 0, x1 = 0;
             if (active) {
                 if (2 * m < n_in) x0 = src[2 * m];
@@ -104,14 +146,18 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
 // P5: NH packed bins -> real line, unscaled inverse of length 2*NH times `scale`,
 // first n_out values kept.  Z'[k] = (X[k] + conj X[NH-k]) + i W_L^{-k} (X[k] - conj X[NH-k]),
 // then x[2m] + i x[2m+1] = IDFT_NH(Z')[m].
+// vec2: n_out and out_pitch even and `out` 2-element aligned (pairs stored at once).
 template <typename real, int NH>
-__global__ __launch_bounds__(ce_max(1, 256 / (NH / Plan<NH>::E)) * (NH / Plan<NH>::E))
+__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH>::E)))
 void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch, int n_out, long nlines,
-                  real scale, const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2) {
+                  real scale, const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2) {
     using C = cplx<real>;
-    constexpr int E = Plan<NH>::E, P = NH / E, LPW = ce_max(1, 256 / P);
+    constexpr int E = Plan<NH>::E, P = NH / E, LPW = z_lines<real, NH>();
     constexpr int PADN = NH + NH / 16 + 1;
     __shared__ C lds[LPW * PADN];
+    __shared__ C s_tw[NH], s_tw2[NH];
+    tw = stage_twiddles(s_tw, tw, NH);
+    tw2 = stage_twiddles(s_tw2, tw2, NH);
     const int t = threadIdx.x % P, l = threadIdx.x / P;
     const long line = (long)blockIdx.x * LPW + l;
     const bool active = line < nlines;
@@ -136,10 +182,13 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
             return cmake<C>(A.x - wb.y, A.y + wb.x);  // A + i W^{-k} B
         },
         [&](int m, C v) {
-            if (active) {
-                if (2 * m < n_out) dst[2 * m] = v.x * scale;
-                if (2 * m + 1 < n_out) dst[2 * m + 1] = v.y * scale;
+            if (!active) return;
+            if (vec2) {
+                if (2 * m < n_out) reinterpret_cast<C*>(dst)[m] = cmake<C>(v.x * scale, v.y * scale);
+                return;
             }
+            if (2 * m < n_out) dst[2 * m] = v.x * scale;
+            if (2 * m + 1 < n_out) dst[2 * m + 1] = v.y * scale;
         },
         view);
 }
@@ -153,6 +202,8 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
     using C = cplx<real>;
     constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
+    __shared__ C s_tw[N];
+    tw = stage_twiddles(s_tw, tw, N);
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -249,6 +300,8 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     using C = cplx<real>;
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T;
     __shared__ C lds[2 * N * T];
+    __shared__ C s_tw[N];
+    tw = stage_twiddles(s_tw, tw, N);
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const int ky = blockIdx.y;
     const int kyl = l == 0 ? ky : (ly - ky) % ly;
@@ -323,13 +376,14 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
     const C* tw = twb.get<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
     if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
+    const int vec2 = (n_in % 2 == 0) && (in_pitch % 2 == 0) && ((uintptr_t)in % (2 * sizeof(real)) == 0);
     switch (nh) {
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
-        constexpr int P = N_ / Plan<N_>::E, LPW = ce_max(1, 256 / P);                           \
+        constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
         dim3 grid((unsigned)((nlines + LPW - 1) / LPW));                                        \
         hipLaunchKernelGGL((z_r2c_kernel<real, N_>), grid, dim3(LPW * P), 0, s, in, in_pitch,   \
-                           n_in, (C*)out, out_pitch, nlines, tw, tw2);                          \
+                           n_in, (C*)out, out_pitch, nlines, tw, tw2, vec2);                    \
         return hipGetLastError();                                                               \
     }
         PIPE_FOR_EACH_N(X)
@@ -345,13 +399,14 @@ hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long o
     const C* tw = twb.get<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
     if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
+    const int vec2 = (n_out % 2 == 0) && (out_pitch % 2 == 0) && ((uintptr_t)out % (2 * sizeof(real)) == 0);
     switch (nh) {
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
-        constexpr int P = N_ / Plan<N_>::E, LPW = ce_max(1, 256 / P);                           \
+        constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
         dim3 grid((unsigned)((nlines + LPW - 1) / LPW));                                        \
         hipLaunchKernelGGL((z_c2r_kernel<real, N_>), grid, dim3(LPW * P), 0, s, (const C*)in,   \
-                           in_pitch, out, out_pitch, n_out, nlines, scale, tw, tw2);            \
+                           in_pitch, out, out_pitch, n_out, nlines, scale, tw, tw2, vec2);      \
         return hipGetLastError();                                                               \
     }
         PIPE_FOR_EACH_N(X)
@@ -363,8 +418,8 @@ hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long o
 // Column tile: up to 16 complex values (128 B in FP32, 256 B in FP64) per row
 // segment, halved until the block's LDS (N x T complex) fits in 64 KB.
 template <typename real, int N> constexpr int strided_T() {
-    int t = 16;
-    while (t > 1 && N * t * (int)sizeof(real) * 2 > 64 * 1024) t /= 2;
+    int t = PIPE_STRIDED_TMAX;
+    while (t > 1 && N * t * (int)sizeof(real) * 2 > PIPE_LDS_CAP) t /= 2;
     return t;
 }
 
@@ -401,8 +456,8 @@ hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_
 template <typename real, int N> constexpr int xprod_T() {
     constexpr int bytes = sizeof(real) * 2;
     constexpr int P = N / Plan<N>::E;
-    int t = 16;
-    while (t > 1 && (2 * N * t * bytes > 64 * 1024 || 2 * P * t > 1024)) t /= 2;
+    int t = PIPE_XPROD_TMAX;
+    while (t > 1 && (2 * N * t * bytes > PIPE_LDS_CAP || 2 * P * t > 1024)) t /= 2;
     return t;
 }
 
