@@ -125,6 +125,57 @@ def time_leg(pipe, torch, wl, precision, steps, warmup):
     return leg, out
 
 
+def batch_leg(pipe, torch, workloads, replays=20, warmup=3):
+    """96 uneven IGF solves (seeded manifest of four mesh shapes): one replay of
+    the captured batch graph vs the same solves issued one by one, FP32 and FP64."""
+    import numpy as np
+    man = workloads.batch_manifest()
+    members = [workloads.batch_member(d) for d in man]
+    log("[bench] batch: building %d FP32 and %d FP64 plans" % (len(members), len(members)))
+    mk = lambda w, prec: pipe.GreenPlan(w.nx, w.ny, w.nz, w.hx, w.hy, w.hz, w.a, w.b, kind=w.kind,
+                                        precision=prec, mx=w.mx, my=w.my)
+    p32 = [mk(w, "fp32") for w in members]
+    p64 = [mk(w, "fp64") for w in members]
+    r32 = [torch.from_numpy(w.rho).to("cuda", torch.float32) for w in members]
+    r64 = [torch.from_numpy(w.rho).to("cuda", torch.float64) for w in members]
+    o32 = [torch.empty_like(r) for r in r32]
+    o64 = [torch.empty_like(r) for r in r64]
+    ws32 = [p.workspace() for p in p32]
+    ws64 = [p.workspace() for p in p64]
+    b = pipe.Batch(p32)
+    bws = b.workspace()
+
+    def timed(fn, reps):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    t_batch = timed(lambda: b.solve(r32, o32, workspace=bws), replays)
+    got = [o.double().cpu().numpy() for o in o32]
+    t_seq32 = timed(lambda: [p.solve(r, out=o, workspace=w) for p, r, o, w in zip(p32, r32, o32, ws32)], replays)
+    t_seq64 = timed(lambda: [p.solve(r, out=o, workspace=w) for p, r, o, w in zip(p64, r64, o64, ws64)], replays)
+    ref = [o.double().cpu().numpy() for o in o64]
+    err = max(float(np.linalg.norm(g - r) / np.linalg.norm(r)) for g, r in zip(got, ref))
+    model = sum(p.info.model_bytes for p in p32)
+    n = len(members)
+    res = {"solves": n, "shapes": sorted({"%dx%dx%d" % w.shape for w in members}),
+           "batched_fp32_solves_per_s": n / t_batch, "batched_fp32_ms_per_batch": t_batch * 1e3,
+           "sequential_fp32_solves_per_s": n / t_seq32, "sequential_fp64_solves_per_s": n / t_seq64,
+           "speedup_batched_fp32_over_sequential_fp64": t_seq64 / t_batch,
+           "speedup_batched_fp32_over_sequential_fp32": t_seq32 / t_batch,
+           "model_bytes_per_batch": model, "batched_model_GBps": model / t_batch / 1e9,
+           "max_member_rel_l2_fp32_vs_fp64": err}
+    b.close()
+    for p in p32 + p64:
+        p.close()
+    return res
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -161,6 +212,7 @@ def main():
     ap.add_argument("--legs", default="fp32,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -218,6 +270,11 @@ def main():
         d = outs["fp32"] - outs["fp64"]
         res["fp32_vs_fp64_rel_l2"] = float(np.linalg.norm(d) / np.linalg.norm(outs["fp64"]))
         res["fp32_vs_fp64_rel_max"] = float(np.max(np.abs(d)) / np.max(np.abs(outs["fp64"])))
+    if not args.no_batch:
+        res["batch"] = batch_leg(pipe, torch, workloads)
+        log("[bench] batch: %.0f solves/s batched FP32, %.0f sequential FP32, %.0f sequential FP64" % (
+            res["batch"]["batched_fp32_solves_per_s"], res["batch"]["sequential_fp32_solves_per_s"],
+            res["batch"]["sequential_fp64_solves_per_s"]))
     if not args.no_cpu_baseline:
         cb, ophi = cpu_baseline(wl)
         res["cpu_baseline"] = cb

@@ -96,8 +96,13 @@ template <typename real, int NH> constexpr int z_lines() {
 template <typename real, int NH>
 __global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH>::E)))
 void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long out_pitch, long nlines,
-                  const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2) {
+                  const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2,
+                  const GroupArgs* __restrict__ group) {
     using C = cplx<real>;
+    if (group) {
+        in = (const real*)group[blockIdx.z].in;
+        out = (C*)group[blockIdx.z].out;
+    }
     constexpr int E = Plan<NH>::E, P = NH / E, LPW = z_lines<real, NH>();
     constexpr int PADN = NH + NH / 16 + 1;
     __shared__ C lds[LPW * PADN];
@@ -150,8 +155,14 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
 template <typename real, int NH>
 __global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH>::E)))
 void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch, int n_out, long nlines,
-                  real scale, const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2) {
+                  real scale, const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2,
+                  const GroupArgs* __restrict__ group) {
     using C = cplx<real>;
+    if (group) {
+        in = (const C*)group[blockIdx.z].in;
+        out = (real*)group[blockIdx.z].out;
+        scale = (real)group[blockIdx.z].scale;
+    }
     constexpr int E = Plan<NH>::E, P = NH / E, LPW = z_lines<real, NH>();
     constexpr int PADN = NH + NH / 16 + 1;
     __shared__ C lds[LPW * PADN];
@@ -198,8 +209,13 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
 template <typename real, int N, int T, bool INV>
 __global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N>::E) * T)) * (N / Plan<N>::E) * T)
 void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, long in_es, long out_es,
-                    long ncols, long in_ss, long out_ss, long nslabs, const cplx<real>* __restrict__ tw) {
+                    long ncols, long in_ss, long out_ss, long nslabs, const cplx<real>* __restrict__ tw,
+                    const GroupArgs* __restrict__ group) {
     using C = cplx<real>;
+    if (group) {
+        in = (const C*)group[blockIdx.z].in;
+        out = (C*)group[blockIdx.z].out;
+    }
     constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
@@ -296,8 +312,14 @@ __device__ __forceinline__ void orbit_product(const Orbit<real>& o, const cplx<r
 template <typename real, int N, int T, bool ADJ>
 __global__ __launch_bounds__(2 * (N / Plan<N>::E) * T)
 void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restrict__ table,
-                  const real* __restrict__ nyq, const cplx<real>* __restrict__ tw) {
+                  const real* __restrict__ nyq, const cplx<real>* __restrict__ tw,
+                  const GroupArgs* __restrict__ group) {
     using C = cplx<real>;
+    if (group) {
+        data = (C*)group[blockIdx.z].out;
+        table = (const real*)group[blockIdx.z].table;
+        nyq = (const real*)group[blockIdx.z].nyq;
+    }
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T;
     __shared__ C lds[2 * N * T];
     __shared__ C s_tw[N];
@@ -371,19 +393,21 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
 
 template <typename real>
 hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* out, long out_pitch,
-                        long nlines, const TwiddleBank& twb, hipStream_t s) {
+                        long nlines, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group, int ngroup,
+                        bool aligned) {
     using C = cplx<real>;
     const C* tw = twb.get<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
     if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
-    const int vec2 = (n_in % 2 == 0) && (in_pitch % 2 == 0) && ((uintptr_t)in % (2 * sizeof(real)) == 0);
+    const int vec2 = (n_in % 2 == 0) && (in_pitch % 2 == 0) && aligned &&
+                     (group || (uintptr_t)in % (2 * sizeof(real)) == 0);
     switch (nh) {
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
         constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
-        dim3 grid((unsigned)((nlines + LPW - 1) / LPW));                                        \
+        dim3 grid((unsigned)((nlines + LPW - 1) / LPW), 1, (unsigned)ngroup);                    \
         hipLaunchKernelGGL((z_r2c_kernel<real, N_>), grid, dim3(LPW * P), 0, s, in, in_pitch,   \
-                           n_in, (C*)out, out_pitch, nlines, tw, tw2, vec2);                    \
+                           n_in, (C*)out, out_pitch, nlines, tw, tw2, vec2, group);             \
         return hipGetLastError();                                                               \
     }
         PIPE_FOR_EACH_N(X)
@@ -394,19 +418,21 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
 
 template <typename real>
 hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long out_pitch, int n_out,
-                        long nlines, real scale, const TwiddleBank& twb, hipStream_t s) {
+                        long nlines, real scale, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
+                        int ngroup, bool aligned) {
     using C = cplx<real>;
     const C* tw = twb.get<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
     if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
-    const int vec2 = (n_out % 2 == 0) && (out_pitch % 2 == 0) && ((uintptr_t)out % (2 * sizeof(real)) == 0);
+    const int vec2 = (n_out % 2 == 0) && (out_pitch % 2 == 0) && aligned &&
+                     (group || (uintptr_t)out % (2 * sizeof(real)) == 0);
     switch (nh) {
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
         constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
-        dim3 grid((unsigned)((nlines + LPW - 1) / LPW));                                        \
+        dim3 grid((unsigned)((nlines + LPW - 1) / LPW), 1, (unsigned)ngroup);                    \
         hipLaunchKernelGGL((z_c2r_kernel<real, N_>), grid, dim3(LPW * P), 0, s, (const C*)in,   \
-                           in_pitch, out, out_pitch, n_out, nlines, scale, tw, tw2, vec2);      \
+                           in_pitch, out, out_pitch, n_out, nlines, scale, tw, tw2, vec2, group); \
         return hipGetLastError();                                                               \
     }
         PIPE_FOR_EACH_N(X)
@@ -426,7 +452,7 @@ template <typename real, int N> constexpr int strided_T() {
 template <typename real>
 hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_in, int n_out, long in_es,
                           long out_es, long ncols, long in_ss, long out_ss, long nslabs,
-                          const TwiddleBank& twb, hipStream_t s) {
+                          const TwiddleBank& twb, hipStream_t s, const GroupArgs* group, int ngroup) {
     using C = cplx<real>;
     const C* tw = twb.get<C>(n);
     if (!tw || ncols <= 0 || nslabs <= 0) return hipErrorInvalidValue;
@@ -435,15 +461,16 @@ hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_
     case N_: {                                                                                     \
         constexpr int T = strided_T<real, N_>();                                                   \
         constexpr int P = N_ / Plan<N_>::E, SPW = ce_max(1, 256 / (P * T));                        \
-        dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW));          \
+        dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW),           \
+                  (unsigned)ngroup);                                                               \
         if (inverse)                                                                               \
             hipLaunchKernelGGL((strided_kernel<real, N_, T, true>), grid, dim3(SPW * P * T), 0, s, \
                                (const C*)in, (C*)out, n_in, n_out, in_es, out_es, ncols, in_ss,     \
-                               out_ss, nslabs, tw);                                                \
+                               out_ss, nslabs, tw, group);                                         \
         else                                                                                       \
             hipLaunchKernelGGL((strided_kernel<real, N_, T, false>), grid, dim3(SPW * P * T), 0,   \
                                s, (const C*)in, (C*)out, n_in, n_out, in_es, out_es, ncols, in_ss,  \
-                               out_ss, nslabs, tw);                                                \
+                               out_ss, nslabs, tw, group);                                         \
         return hipGetLastError();                                                                  \
     }
         PIPE_FOR_EACH_N(X)
@@ -473,7 +500,8 @@ int xprod_tile(int lx, int real_bytes) {
 
 template <typename real>
 hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh, const real* table,
-                        const real* nyq, const TwiddleBank& twb, hipStream_t s) {
+                        const real* nyq, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
+                        int ngroup) {
     using C = cplx<real>;
     const C* tw = twb.get<C>(lx);
     if (!tw) return hipErrorInvalidValue;
@@ -482,13 +510,13 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
     case N_: {                                                                                    \
         constexpr int T = xprod_T<real, N_>();                                                    \
         constexpr int P = N_ / Plan<N_>::E;                                                       \
-        dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1));                          \
+        dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1), (unsigned)ngroup);        \
         if (adjoint)                                                                              \
             hipLaunchKernelGGL((xprod_kernel<real, N_, T, true>), grid, dim3(2 * P * T), 0, s,    \
-                               (C*)data, nx, ly, nh, table, nyq, tw);                             \
+                               (C*)data, nx, ly, nh, table, nyq, tw, group);                      \
         else                                                                                      \
             hipLaunchKernelGGL((xprod_kernel<real, N_, T, false>), grid, dim3(2 * P * T), 0, s,   \
-                               (C*)data, nx, ly, nh, table, nyq, tw);                             \
+                               (C*)data, nx, ly, nh, table, nyq, tw, group);                      \
         return hipGetLastError();                                                                 \
     }
         PIPE_FOR_EACH_N(X)
@@ -499,13 +527,14 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
 
 #define PIPE_INST(real)                                                                               \
     template hipError_t launch_z_r2c<real>(int, const real*, long, int, void*, long, long,             \
-                                           const TwiddleBank&, hipStream_t);                           \
+                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool); \
     template hipError_t launch_z_c2r<real>(int, const void*, long, real*, long, int, long, real,       \
-                                           const TwiddleBank&, hipStream_t);                           \
+                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool); \
     template hipError_t launch_strided<real>(int, bool, const void*, void*, int, int, long, long, long, \
-                                             long, long, long, const TwiddleBank&, hipStream_t);       \
+                                             long, long, long, const TwiddleBank&, hipStream_t,         \
+                                             const GroupArgs*, int);                                    \
     template hipError_t launch_xprod<real>(int, bool, void*, int, int, int, const real*, const real*,  \
-                                           const TwiddleBank&, hipStream_t);
+                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int);
 PIPE_INST(float)
 PIPE_INST(double)
 #undef PIPE_INST

@@ -543,11 +543,28 @@ pipe_status_t pipe_fft_lines(int real_bytes, int len, int n_in, int howmany, int
 }  // extern "C"
 
 // ---------------------------------------------------------------- batches
+//
+// Members with the same mesh (sizes and padded lengths) form a shape group;
+// each of the five passes runs once per group as a grouped launch
+// (blockIdx.z = member, per-member pointers from a device array of GroupArgs).
+// The groups are independent branches of one captured HIP graph, so the
+// passes of different shapes run concurrently.  Every member has its own
+// slice of the workspace.
 
 struct pipe_batch_s {
+    struct Group {
+        std::vector<int> members;
+        pipe_plan_t rep;   // representative plan (sizes, lengths, precision)
+    };
     std::vector<pipe_plan_t> plans;
+    std::vector<Group> groups;
+    std::vector<size_t> ws_off;
     int device = 0, rb = 8;
     size_t ws_bytes = 0;
+    GroupArgs* dargs = nullptr;          // device: per group, 5 passes x members
+    std::vector<size_t> args_off;        // entry offset of each group's first pass
+    std::vector<hipStream_t> streams;    // one per group (fork/join branches of the capture)
+    std::vector<hipEvent_t> events;      // fork + one join event per group
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -562,6 +579,38 @@ void batch_drop_graph(pipe_batch_s* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+}
+
+void batch_free(pipe_batch_s* b) {
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    batch_drop_graph(b);
+    for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->dargs) (void)hipFree(b->dargs);
+    delete b;
+}
+
+template <typename real>
+pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al_in, bool al_out, hipStream_t st) {
+    const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly, nh = p->nh;
+    const TwiddleBank& tw = p->ctx->tw;
+    const real scale = (real)0;  // taken from each member's GroupArgs
+    HIP_TRY(launch_z_r2c<real>(nh, nullptr, nz, nz, nullptr, nh, (long)nx * ny, tw, st, args, n, al_in),
+            "grouped z forward pass");
+    HIP_TRY(launch_strided<real>(ly, false, nullptr, nullptr, ny, ly, nh, nh, nh, (long)ny * nh, (long)ly * nh, nx,
+                                 tw, st, args + n, n),
+            "grouped y forward pass");
+    HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, nullptr, nullptr, tw, st, args + 2 * n, n),
+            "grouped x pass with spectral product");
+    HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, nh, nh, nh, (long)ly * nh, (long)ny * nh, nx,
+                                 tw, st, args + 3 * n, n),
+            "grouped y inverse pass");
+    HIP_TRY(launch_z_c2r<real>(nh, nullptr, nh, nullptr, nz, nz, (long)nx * ny, scale, tw, st, args + 4 * n, n,
+                               al_out),
+            "grouped z inverse pass");
+    return PIPE_OK;
 }
 }  // namespace
 
@@ -580,11 +629,47 @@ pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_
     b->plans.assign(plans, plans + count);
     b->device = plans[0]->device;
     b->rb = plans[0]->rb;
-    for (auto p : b->plans) b->ws_bytes = std::max(b->ws_bytes, p->ws_bytes);
-    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    for (int i = 0; i < count; ++i) {
+        pipe_plan_s* p = plans[i];
+        int g = -1;
+        for (size_t k = 0; k < b->groups.size(); ++k) {
+            pipe_plan_s* r = b->groups[k].rep;
+            if (r->nx == p->nx && r->ny == p->ny && r->nz == p->nz && r->lx == p->lx && r->ly == p->ly &&
+                r->lz == p->lz)
+                g = (int)k;
+        }
+        if (g < 0) {
+            b->groups.push_back({{}, p});
+            g = (int)b->groups.size() - 1;
+        }
+        b->groups[g].members.push_back(i);
+        b->ws_off.push_back(b->ws_bytes);
+        b->ws_bytes += align256(p->ws_bytes);
+    }
+    size_t entries = 0;
+    for (auto& g : b->groups) {
+        b->args_off.push_back(entries);
+        entries += 5 * g.members.size();
+    }
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != b->device) e = hipSetDevice(b->device);
+    if (e == hipSuccess) e = dev_alloc((void**)&b->dargs, entries * sizeof(GroupArgs));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    for (size_t k = 0; e == hipSuccess && k < b->groups.size(); ++k) {
+        hipStream_t st;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) b->streams.push_back(st);
+    }
+    for (size_t k = 0; e == hipSuccess && k < b->groups.size() + 1; ++k) {
+        hipEvent_t ev;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->events.push_back(ev);
+    }
+    if (cur >= 0 && cur != b->device) (void)hipSetDevice(cur);
     if (e != hipSuccess) {
-        delete b;
-        return hip_fail(e, "hipStreamCreate");
+        batch_free(b);
+        return hip_fail(e, "batch setup");
     }
     reg_add(b);
     *out = b;
@@ -601,47 +686,107 @@ pipe_status_t pipe_batch_workspace(pipe_batch_t b, size_t* bytes) {
 pipe_status_t pipe_batch_solve(pipe_batch_t b, const void* const* rho, void* const* phi, void* ws, void* stream) {
     if (!reg_has(b)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed batch handle");
     if (!rho || !phi || !ws) return fail(PIPE_ERR_INVALID_ARG, "null array");
+    if (((uintptr_t)ws) & 255) return fail(PIPE_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     const size_t n = b->plans.size();
     for (size_t i = 0; i < n; ++i) {
-        if (!reg_has(b->plans[i])) return fail(PIPE_ERR_INVALID_ARG, "member plan %zu was destroyed", i);
-        pipe_status_t s = check_solve_args(b->plans[i], rho[i], phi[i], ws);
-        if (s != PIPE_OK) return s;
+        pipe_plan_s* p = b->plans[i];
+        if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "member plan %zu was destroyed", i);
+        if (!rho[i] || !phi[i]) return fail(PIPE_ERR_INVALID_ARG, "member %zu: null rho or phi", i);
+        if (((uintptr_t)rho[i]) % p->rb || ((uintptr_t)phi[i]) % p->rb)
+            return fail(PIPE_ERR_INVALID_ARG, "member %zu: rho and phi must be aligned to the element size", i);
+        const size_t nb = (size_t)p->nx * p->ny * p->nz * p->rb;
+        if (overlaps(rho[i], nb, phi[i], nb)) return fail(PIPE_ERR_ALIASING, "member %zu: rho and phi overlap", i);
+        if (overlaps(rho[i], nb, ws, b->ws_bytes) || overlaps(phi[i], nb, ws, b->ws_bytes))
+            return fail(PIPE_ERR_ALIASING, "member %zu: workspace overlaps rho or phi", i);
     }
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != b->device) HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
     bool same = b->exec && b->last_ws == ws;
     for (size_t i = 0; same && i < n; ++i) same = b->last_rho[i] == rho[i] && b->last_phi[i] == phi[i];
+    pipe_status_t s = PIPE_OK;
     if (!same) {
         batch_drop_graph(b);
-        HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "graph capture");
-        pipe_status_t s = PIPE_OK;
-        for (size_t i = 0; i < n && s == PIPE_OK; ++i) s = solve_impl(b->plans[i], rho[i], phi[i], ws, b->cap, false, nullptr);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(b->cap, &g);
-        if (s != PIPE_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return s;
+        // per-member pointers of the five grouped passes
+        std::vector<GroupArgs> host;
+        for (auto& g : b->groups) {
+            const size_t m = g.members.size();
+            std::vector<GroupArgs> a(5 * m);
+            for (size_t k = 0; k < m; ++k) {
+                const int i = g.members[k];
+                pipe_plan_s* p = b->plans[i];
+                char* A1 = (char*)ws + b->ws_off[i];
+                char* A2 = A1 + align256((size_t)p->nx * p->ny * p->nh * 2 * p->rb);
+                const double scale = p->hx * p->hy * p->hz / ((double)p->lx * p->ly * p->lz);
+                a[0 * m + k] = {rho[i], A1, nullptr, nullptr, 0.0};
+                a[1 * m + k] = {A1, A2, nullptr, nullptr, 0.0};
+                a[2 * m + k] = {A2, A2, p->table, p->nyq, 0.0};
+                a[3 * m + k] = {A2, A1, nullptr, nullptr, 0.0};
+                a[4 * m + k] = {A1, phi[i], nullptr, nullptr, scale};
+            }
+            host.insert(host.end(), a.begin(), a.end());
         }
-        if (e != hipSuccess) return hip_fail(e, "graph capture");
-        b->graph = g;
-        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            batch_drop_graph(b);
-            return hip_fail(e, "graph instantiate");
+        // an earlier replay may still be reading the descriptors
+        hipError_t e = hipDeviceSynchronize();
+        if (e == hipSuccess)
+            e = hipMemcpy(b->dargs, host.data(), host.size() * sizeof(GroupArgs), hipMemcpyHostToDevice);
+        if (e != hipSuccess) s = hip_fail(e, "batch descriptor upload");
+        if (s == PIPE_OK) {
+            e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) s = hip_fail(e, "graph capture");
         }
-        b->last_rho.assign(rho, rho + n);
-        b->last_phi.assign(phi, phi + n);
-        b->last_ws = ws;
+        if (s == PIPE_OK) {
+            hipError_t ce = hipEventRecord(b->events[0], b->cap);
+            for (size_t k = 0; ce == hipSuccess && s == PIPE_OK && k < b->groups.size(); ++k) {
+                auto& g = b->groups[k];
+                hipStream_t st = b->streams[k];
+                ce = hipStreamWaitEvent(st, b->events[0], 0);
+                if (ce != hipSuccess) break;
+                bool al_in = true, al_out = true;
+                for (int i : g.members) {
+                    al_in = al_in && ((uintptr_t)rho[i] % (2 * b->rb) == 0);
+                    al_out = al_out && ((uintptr_t)phi[i] % (2 * b->rb) == 0);
+                }
+                const GroupArgs* args = b->dargs + b->args_off[k];
+                const int m = (int)g.members.size();
+                s = b->rb == 8 ? launch_group<double>(g.rep, args, m, al_in, al_out, st)
+                               : launch_group<float>(g.rep, args, m, al_in, al_out, st);
+                if (s != PIPE_OK) break;
+                ce = hipEventRecord(b->events[k + 1], st);
+                if (ce == hipSuccess) ce = hipStreamWaitEvent(b->cap, b->events[k + 1], 0);
+            }
+            hipGraph_t g = nullptr;
+            hipError_t ee = hipStreamEndCapture(b->cap, &g);
+            if (s == PIPE_OK && ce != hipSuccess) s = hip_fail(ce, "graph capture (fork/join)");
+            if (s == PIPE_OK && ee != hipSuccess) s = hip_fail(ee, "graph capture");
+            if (s != PIPE_OK) {
+                if (g) (void)hipGraphDestroy(g);
+            } else {
+                b->graph = g;
+                e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    batch_drop_graph(b);
+                    s = hip_fail(e, "graph instantiate");
+                }
+            }
+        }
+        if (s == PIPE_OK) {
+            b->last_rho.assign(rho, rho + n);
+            b->last_phi.assign(phi, phi + n);
+            b->last_ws = ws;
+        }
     }
-    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream), "graph launch");
-    return PIPE_OK;
+    if (s == PIPE_OK) {
+        hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+        if (e != hipSuccess) s = hip_fail(e, "graph launch");
+    }
+    if (cur != b->device) (void)hipSetDevice(cur);
+    return s;
 }
 
 pipe_status_t pipe_batch_destroy(pipe_batch_t b) {
     if (!reg_del(b)) return fail(PIPE_ERR_INVALID_ARG, "invalid or already destroyed batch handle");
-    (void)hipSetDevice(b->device);
-    (void)hipDeviceSynchronize();
-    batch_drop_graph(b);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
-    delete b;
+    batch_free(b);
     return PIPE_OK;
 }
 

@@ -26,20 +26,36 @@ struct TwiddleBank {
     template <typename C> const C* get(int n) const;
 };
 
+// Per-member pointers of a grouped launch: blockIdx.z selects the member and its
+// entry replaces the launch's own data pointers (in/out; table/nyq for the x
+// pass; scale for the z inverse).  All members share the launch's sizes.
+struct GroupArgs {
+    const void* in;
+    void* out;
+    const void* table;
+    const void* nyq;
+    double scale;
+};
+
 // Kernel launchers (passes.hip).  All return hipSuccess or the launch error.
+// group (device array of ngroup entries) may be null for a single solve.
 template <typename real>
 hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* out, long out_pitch,
-                        long nlines, const TwiddleBank& tw, hipStream_t s);
+                        long nlines, const TwiddleBank& tw, hipStream_t s,
+                        const GroupArgs* group = nullptr, int ngroup = 1, bool aligned = true);
 template <typename real>
 hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long out_pitch, int n_out,
-                        long nlines, real scale, const TwiddleBank& tw, hipStream_t s);
+                        long nlines, real scale, const TwiddleBank& tw, hipStream_t s,
+                        const GroupArgs* group = nullptr, int ngroup = 1, bool aligned = true);
 template <typename real>
 hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_in, int n_out,
                           long in_es, long out_es, long ncols, long in_ss, long out_ss, long nslabs,
-                          const TwiddleBank& tw, hipStream_t s);
+                          const TwiddleBank& tw, hipStream_t s, const GroupArgs* group = nullptr,
+                          int ngroup = 1);
 template <typename real>
 hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh,
-                        const real* table, const real* nyq, const TwiddleBank& tw, hipStream_t s);
+                        const real* table, const real* nyq, const TwiddleBank& tw, hipStream_t s,
+                        const GroupArgs* group = nullptr, int ngroup = 1);
 
 // kz tile width of the fused x pass for padded length lx (0 if unsupported).
 // The Green spectra are stored tile-blocked to match: for orbit row kyo, kz tile

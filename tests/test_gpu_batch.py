@@ -1,0 +1,105 @@
+"""Batched solves (pipe_batch_*): 96 uneven meshes in one replay of a captured HIP graph.
+
+Each member must equal its own single solve, and the oracle at sampled
+members; replaying the graph must give the same result every time, also
+with the program's own work between replays; new pointers rebuild it.
+"""
+import numpy as np
+import pytest
+
+from helpers import log, oracle_input, rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def batch_setup(torch_cuda):
+    torch = torch_cuda
+    from paper_1111_4971_amd import pipe, workloads
+    man = workloads.batch_manifest()
+    log("batch: building %d plans" % len(man))
+    members = [workloads.batch_member(d) for d in man]
+    plans = [pipe.GreenPlan(w.nx, w.ny, w.nz, w.hx, w.hy, w.hz, w.a, w.b, kind=w.kind, precision="fp32",
+                            mx=w.mx, my=w.my) for w in members]
+    rhos = [torch.from_numpy(w.rho).to("cuda", torch.float32) for w in members]
+    return members, plans, rhos
+
+
+def test_batch_equals_single_solves_and_replays(torch_cuda, batch_setup):
+    torch = torch_cuda
+    from paper_1111_4971_amd import pipe
+    members, plans, rhos = batch_setup
+    shapes = sorted({w.shape for w in members})
+    assert len(shapes) == 4
+    log("batch: single solves")
+    singles = [p.solve(r).double().cpu().numpy() for p, r in zip(plans, rhos)]
+    log("batch: graph create + solve")
+    b = pipe.Batch(plans)
+    outs = [torch.empty_like(r) for r in rhos]
+    b.solve(rhos, outs)
+    torch.cuda.synchronize()
+    first = [o.double().cpu().numpy() for o in outs]
+    for s, f in zip(singles, first):
+        assert rel_l2(f, s) <= 1e-6 and rel_max(f, s) <= 1e-6
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        _ = (rhos[0] * 2).sum().item()     # unrelated eager work between replays
+        b.solve(rhos, outs)
+        torch.cuda.synchronize()
+        for f, o in zip(first, outs):
+            assert np.array_equal(f, o.double().cpu().numpy())
+    # new output buffers: the graph is rebuilt with the new pointers
+    outs2 = [torch.empty_like(r) for r in rhos]
+    b.solve(rhos, outs2)
+    torch.cuda.synchronize()
+    for f, o in zip(first, outs2):
+        assert np.array_equal(f, o.double().cpu().numpy())
+    b.close()
+
+
+def test_batch_members_match_the_oracle(torch_cuda, batch_setup):
+    from oracle import modespace
+    members, plans, rhos = batch_setup
+    from paper_1111_4971_amd import pipe
+    b = pipe.Batch(plans)
+    outs = b.solve(rhos)
+    import torch
+    torch.cuda.synchronize()
+    seen = set()
+    for w, o in zip(members, outs):
+        if w.shape in seen:
+            continue
+        seen.add(w.shape)
+        log("batch: oracle check %s" % (w.shape,))
+        ref = modespace.solve(oracle_input(w.rho, "fp32"), **w.geometry())
+        got = o.double().cpu().numpy()
+        assert rel_l2(got, ref) <= 1e-5 and rel_max(got, ref) <= 1e-5
+    b.close()
+
+
+def test_batch_rejects_bad_arguments(torch_cuda, batch_setup):
+    torch = torch_cuda
+    import ctypes
+    from paper_1111_4971_amd import pipe
+    members, plans, rhos = batch_setup
+    L = pipe.lib()
+    h = ctypes.c_void_p()
+    mixed = pipe.GreenPlan(8, 8, 8, 0.1, 0.1, 0.1, 1.0, 1.0, precision="fp64")
+    arr = (ctypes.c_void_p * 2)(plans[0].handle, mixed.handle)
+    assert L.pipe_batch_create(arr, 2, ctypes.byref(h)) == 1     # mixed precision
+    b = pipe.Batch(plans[:2])
+    ws = b.workspace()
+    ra = (ctypes.c_void_p * 2)(rhos[0].data_ptr(), rhos[1].data_ptr())
+    pa = (ctypes.c_void_p * 2)(rhos[0].data_ptr(), rhos[1].data_ptr())   # phi aliases rho
+    assert L.pipe_batch_solve(b._h, ra, pa, ctypes.c_void_p(ws.data_ptr()), None) == 6
+    b.close()
+    assert L.pipe_batch_destroy(h) == 1
