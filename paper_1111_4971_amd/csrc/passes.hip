@@ -81,6 +81,19 @@ __device__ __forceinline__ const C* stage_twiddles(C* s_tw, const C* __restrict_
 #endif
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2) in
+// order of their linear id.  xcd_remap turns the linear id p < total into a
+// logical id such that consecutive logical ids run on the same XCD, one after
+// the other: XCD x takes the x-th contiguous share of logical ids.
+#ifndef PIPE_NUM_XCD
+#define PIPE_NUM_XCD 8
+#endif
+__device__ __forceinline__ unsigned xcd_remap(unsigned p, unsigned total) {
+    const unsigned q = total / PIPE_NUM_XCD, r = total % PIPE_NUM_XCD;
+    const unsigned xcd = p % PIPE_NUM_XCD, k = p / PIPE_NUM_XCD;
+    return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
 template <typename real, int NH> constexpr int z_lines() {
     int l = ce_max(1, PIPE_Z_THREADS / (NH / Plan<NH>::E));
     while (l > 1 && l * (NH + NH / 16 + 1) * 2 * (int)sizeof(real) > PIPE_LDS_CAP) l /= 2;
@@ -325,10 +338,15 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     __shared__ C s_tw[N];
     tw = stage_twiddles(s_tw, tw, N);
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
-    const int ky = blockIdx.y;
+    // logical (kz tile, ky): neighbouring kz tiles share 128-byte lines when
+    // T * sizeof(complex) < 128, so they are kept on one XCD, back to back
+    const unsigned ntile = gridDim.x;
+    const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
+    const int tile = (int)(lid % ntile);
+    const int ky = (int)(lid / ntile);
     const int kyl = l == 0 ? ky : (ly - ky) % ly;
     const bool self = (ky == 0) || (2 * ky == ly);
-    const long kz = (long)blockIdx.x * T + c;
+    const long kz = (long)tile * T + c;
     const bool active = kz < nh;
     const long xs = (long)ly * nh;
     C* line = data + (active ? (long)kyl * nh + kz : 0);
@@ -342,10 +360,10 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     const int kyo = ky;
     constexpr int NKX = N / 2 + 1;
     const int ntiles = (nh + T - 1) / T;
-    const real* tblock = table + ((long)kyo * ntiles + blockIdx.x) * NKX * 9 * T;
+    const real* tblock = table + ((long)kyo * ntiles + tile) * NKX * 9 * T;
     for (int w = threadIdx.x; w < NKX * T; w += NT) {
         const int cc = w % T, o = w / T;
-        const long kzz = (long)blockIdx.x * T + cc;
+        const long kzz = (long)tile * T + cc;
         if (kzz >= nh) continue;
         const int on = (N - o) % N;
         C* L0 = lds + cc;
