@@ -218,18 +218,14 @@ __device__ __forceinline__ void stage_store(const C* v, int t, Dst dst) {
     }
 }
 
-// Whole transform.  src/dst are element accessors for the first load and the
-// last store; lds.get(e) / lds.set(e, v) address this thread's line in LDS.
-// SRC_LDS: the first load reads the same LDS line that later stages overwrite,
-// so a barrier separates it from the first store.
-// Every thread of the block must call this (it contains barriers).
-template <int N, bool INV, bool SRC_LDS, typename C, typename Src, typename Dst, typename Lds>
-__device__ __forceinline__ void fft_line(int t, const C* __restrict__ tw, Src src, Dst dst, Lds lds) {
+// Whole transform from stage-0 inputs already in registers (v, loaded by
+// stage_load<N, radix(0)>).  dst is the element accessor of the last store;
+// lds.get(e) / lds.set(e, v) address this thread's line in LDS.  Every thread
+// of the block must call this (it contains barriers).
+template <int N, bool INV, typename C, typename Dst, typename Lds>
+__device__ __forceinline__ void fft_line_regs(C* v, int t, const C* __restrict__ tw, Dst dst, Lds lds) {
     constexpr int S = Plan<N>::S;
-    C v[Plan<N>::E];
     constexpr int R0 = Plan<N>::radix(0);
-    stage_load<N, R0>(v, t, src);
-    if constexpr (SRC_LDS && S > 1) __syncthreads();
     stage_compute<N, R0, 1, INV>(v, t, tw);
     if constexpr (S == 1) {
         stage_store<N, R0, plan_ns<N>(0)>(v, t, dst);
@@ -262,6 +258,17 @@ __device__ __forceinline__ void fft_line(int t, const C* __restrict__ tw, Src sr
             }
         }
     }
+}
+
+// Whole transform.  src/dst are element accessors for the first load and the
+// last store.  SRC_LDS: the first load reads the same LDS line that later
+// stages overwrite, so a barrier separates it from the first store.
+template <int N, bool INV, bool SRC_LDS, typename C, typename Src, typename Dst, typename Lds>
+__device__ __forceinline__ void fft_line(int t, const C* __restrict__ tw, Src src, Dst dst, Lds lds) {
+    C v[Plan<N>::E];
+    stage_load<N, Plan<N>::radix(0)>(v, t, src);
+    if constexpr (SRC_LDS && Plan<N>::S > 1) __syncthreads();
+    fft_line_regs<N, INV>(v, t, tw, dst, lds);
 }
 
 }  // namespace pipe

@@ -100,6 +100,11 @@ template <typename real, int NH> constexpr int z_lines() {
     return l;
 }
 
+// The z passes are persistent: block b handles line groups b, b + gridDim.x, ...
+// (LPW lines per group) and issues the global loads of its next group before
+// transforming the current one, so each block keeps reads in flight while it
+// computes.  Twiddles are staged into LDS once per block.
+
 // P1 / spectra z pass: real lines of n_in values (zero-padded to 2*NH) -> NH packed bins.
 // A real line x of length L = 2 NH is read as z[m] = x[2m] + i x[2m+1]; with
 // Z = DFT_NH(z) the half spectrum is
@@ -117,47 +122,57 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
         out = (C*)group[blockIdx.z].out;
     }
     constexpr int E = Plan<NH>::E, P = NH / E, LPW = z_lines<real, NH>();
+    constexpr int R0 = Plan<NH>::radix(0);
     constexpr int PADN = NH + NH / 16 + 1;
     __shared__ C lds[LPW * PADN];
     __shared__ C s_tw[NH], s_tw2[NH];
     tw = stage_twiddles(s_tw, tw, NH);
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     const int t = threadIdx.x % P, l = threadIdx.x / P;
-    const long line = (long)blockIdx.x * LPW + l;
-    const bool active = line < nlines;
-    const real* src = in + (active ? line : 0) * in_pitch;
-    C* L = lds + l * PADN;
-    LdsLine<C> view{L};
-    fft_line<NH, false, false>(
-        t, tw,
-        [&](int m) -> C {
-            if (vec2) {
-                return (active && 2 * m < n_in) ? reinterpret_cast<const C*>(src)[m] : cmake<C>(0, 0);
-            }
+    LdsLine<C> view{lds + l * PADN};
+    const long ngroups = (nlines + LPW - 1) / LPW;
+    // stage-0 inputs of line `line` (zero beyond n_in or past the last line)
+    auto load = [&](C* v, long line) {
+        const bool active = line < nlines;
+        const real* src = in + (active ? line : 0) * in_pitch;
+        stage_load<NH, R0>(v, t, [&](int m) -> C {
+            if (vec2) return (active && 2 * m < n_in) ? reinterpret_cast<const C*>(src)[m] : cmake<C>(0, 0);
             real x0 = 0, x1 = 0;
             if (active) {
                 if (2 * m < n_in) x0 = src[2 * m];
                 if (2 * m + 1 < n_in) x1 = src[2 * m + 1];
             }
             return cmake<C>(x0, x1);
-        },
-        [&](int k, C v) { view.set(k, v); }, view);
-    __syncthreads();
-    if (!active) return;
-    C* dst = out + line * out_pitch;
+        });
+    };
+    C cur[E], nxt[E];
+    long g = blockIdx.x;
+    if (g < ngroups) load(cur, g * LPW + l);
+    for (; g < ngroups; g += gridDim.x) {
+        const long gn = g + gridDim.x;
+        if (gn < ngroups) load(nxt, gn * LPW + l);
+        fft_line_regs<NH, false>(cur, t, tw, [&](int k, C v) { view.set(k, v); }, view);
+        __syncthreads();
+        const long line = g * LPW + l;
+        if (line < nlines) {
+            C* dst = out + line * out_pitch;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int k = t + q * P;
-        const C zk = view.get(k);
-        if (k == 0) {
-            dst[0] = cmake<C>(zk.x + zk.y, zk.x - zk.y);
-        } else {
-            const C zn = cconj(view.get(NH - k));
-            const C A = cadd(zk, zn), B = csub(zk, zn);
-            // -i * W^k * B
-            const C wb = cmul(B, tw2[k]);
-            dst[k] = cscale(cmake<C>(A.x + wb.y, A.y - wb.x), (real)0.5);
+            for (int q = 0; q < E; ++q) {
+                const int k = t + q * P;
+                const C zk = view.get(k);
+                if (k == 0) {
+                    dst[0] = cmake<C>(zk.x + zk.y, zk.x - zk.y);
+                } else {
+                    const C zn = cconj(view.get(NH - k));
+                    const C A = cadd(zk, zn), B = csub(zk, zn);
+                    const C wb = cmul(B, tw2[k]);  // W^k B;  X = (A - i W^k B) / 2
+                    dst[k] = cscale(cmake<C>(A.x + wb.y, A.y - wb.x), (real)0.5);
+                }
+            }
         }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < E; ++q) cur[q] = nxt[q];
     }
 }
 
@@ -183,38 +198,51 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
     tw = stage_twiddles(s_tw, tw, NH);
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     const int t = threadIdx.x % P, l = threadIdx.x / P;
-    const long line = (long)blockIdx.x * LPW + l;
-    const bool active = line < nlines;
-    C* L = lds + l * PADN;
-    LdsLine<C> view{L};
-    const C* src = in + (active ? line : 0) * in_pitch;
+    LdsLine<C> view{lds + l * PADN};
+    const long ngroups = (nlines + LPW - 1) / LPW;
+    // the packed bins of line `line`, element k = t + q P in slot q
+    auto load = [&](C* v, long line) {
+        const bool active = line < nlines;
+        const C* src = in + (active ? line : 0) * in_pitch;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int k = t + q * P;
-        view.set(k, active ? src[k] : cmake<C>(0, 0));
+        for (int q = 0; q < E; ++q) v[q] = active ? src[t + q * P] : cmake<C>(0, 0);
+    };
+    C cur[E], nxt[E];
+    long g = blockIdx.x;
+    if (g < ngroups) load(cur, g * LPW + l);
+    for (; g < ngroups; g += gridDim.x) {
+        const long gn = g + gridDim.x;
+#pragma unroll
+        for (int q = 0; q < E; ++q) view.set(t + q * P, cur[q]);
+        __syncthreads();
+        if (gn < ngroups) load(nxt, gn * LPW + l);
+        const long line = g * LPW + l;
+        const bool active = line < nlines;
+        real* dst = out + (active ? line : 0) * out_pitch;
+        fft_line<NH, true, true>(
+            t, tw,
+            [&](int k) -> C {
+                const C xk = view.get(k);
+                if (k == 0) return cmake<C>(xk.x + xk.y, xk.x - xk.y);
+                const C xn = cconj(view.get(NH - k));
+                const C A = cadd(xk, xn), B = csub(xk, xn);
+                const C wb = cmulc(B, tw2[k]);  // W^{-k} B
+                return cmake<C>(A.x - wb.y, A.y + wb.x);  // A + i W^{-k} B
+            },
+            [&](int m, C v) {
+                if (!active) return;
+                if (vec2) {
+                    if (2 * m < n_out) reinterpret_cast<C*>(dst)[m] = cmake<C>(v.x * scale, v.y * scale);
+                    return;
+                }
+                if (2 * m < n_out) dst[2 * m] = v.x * scale;
+                if (2 * m + 1 < n_out) dst[2 * m + 1] = v.y * scale;
+            },
+            view);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < E; ++q) cur[q] = nxt[q];
     }
-    __syncthreads();
-    real* dst = out + (active ? line : 0) * out_pitch;
-    fft_line<NH, true, true>(
-        t, tw,
-        [&](int k) -> C {
-            const C xk = view.get(k);
-            if (k == 0) return cmake<C>(xk.x + xk.y, xk.x - xk.y);
-            const C xn = cconj(view.get(NH - k));
-            const C A = cadd(xk, xn), B = csub(xk, xn);
-            const C wb = cmulc(B, tw2[k]);  // W^{-k} B
-            return cmake<C>(A.x - wb.y, A.y + wb.x);  // A + i W^{-k} B
-        },
-        [&](int m, C v) {
-            if (!active) return;
-            if (vec2) {
-                if (2 * m < n_out) reinterpret_cast<C*>(dst)[m] = cmake<C>(v.x * scale, v.y * scale);
-                return;
-            }
-            if (2 * m < n_out) dst[2 * m] = v.x * scale;
-            if (2 * m + 1 < n_out) dst[2 * m + 1] = v.y * scale;
-        },
-        view);
 }
 
 // P2 / P4 / spectra y and x passes: lines along a strided dimension.
@@ -407,6 +435,17 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
 
 // ---------------------------------------------------------------- launchers
 
+// Persistent grid of the z passes: at most PIPE_Z_BLOCKS blocks in total (over
+// all members of a grouped launch), each looping over its share of line groups.
+#ifndef PIPE_Z_BLOCKS
+#define PIPE_Z_BLOCKS 2048
+#endif
+static unsigned z_grid(long ngroups, int nmembers) {
+    long cap = PIPE_Z_BLOCKS / (nmembers > 0 ? nmembers : 1);
+    if (cap < 1) cap = 1;
+    return (unsigned)(ngroups < cap ? ngroups : cap);
+}
+
 #define PIPE_FOR_EACH_N(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
 template <typename real>
@@ -423,7 +462,7 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
         constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
-        dim3 grid((unsigned)((nlines + LPW - 1) / LPW), 1, (unsigned)ngroup);                    \
+        dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup), 1, (unsigned)ngroup);               \
         hipLaunchKernelGGL((z_r2c_kernel<real, N_>), grid, dim3(LPW * P), 0, s, in, in_pitch,   \
                            n_in, (C*)out, out_pitch, nlines, tw, tw2, vec2, group);             \
         return hipGetLastError();                                                               \
@@ -448,7 +487,7 @@ hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long o
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
         constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
-        dim3 grid((unsigned)((nlines + LPW - 1) / LPW), 1, (unsigned)ngroup);                    \
+        dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup), 1, (unsigned)ngroup);               \
         hipLaunchKernelGGL((z_c2r_kernel<real, N_>), grid, dim3(LPW * P), 0, s, (const C*)in,   \
                            in_pitch, out, out_pitch, n_out, nlines, scale, tw, tw2, vec2, group); \
         return hipGetLastError();                                                               \
