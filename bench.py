@@ -132,8 +132,12 @@ def batch_leg(pipe, torch, workloads, replays=20, warmup=3):
     man = workloads.batch_manifest()
     members = [workloads.batch_member(d) for d in man]
     log("[bench] batch: building %d FP32 and %d FP64 plans" % (len(members), len(members)))
+    # batch members: padded lengths per mesh shape chosen by the plan-time
+    # autotuner in throughput mode (timed once per shape); the FP64 plans of
+    # the plain sequential comparison keep the default lengths
     mk = lambda w, prec: pipe.GreenPlan(w.nx, w.ny, w.nz, w.hx, w.hy, w.hz, w.a, w.b, kind=w.kind,
-                                        precision=prec, mx=w.mx, my=w.my)
+                                        precision=prec, mx=w.mx, my=w.my,
+                                        autotune="batch" if prec == "fp32" else False)
     p32 = [mk(w, "fp32") for w in members]
     p64 = [mk(w, "fp64") for w in members]
     r32 = [torch.from_numpy(w.rho).to("cuda", torch.float32) for w in members]
@@ -163,7 +167,11 @@ def batch_leg(pipe, torch, workloads, replays=20, warmup=3):
     err = max(float(np.linalg.norm(g - r) / np.linalg.norm(r)) for g, r in zip(got, ref))
     model = sum(p.info.model_bytes for p in p32)
     n = len(members)
+    tuned = {}
+    for w, p in zip(members, p32):
+        tuned["%dx%dx%d" % w.shape] = "%dx%dx%d" % (p.info.lx, p.info.ly, p.info.lz)
     res = {"solves": n, "shapes": sorted({"%dx%dx%d" % w.shape for w in members}),
+           "autotuned_padded_lengths_fp32": tuned,
            "batched_fp32_solves_per_s": n / t_batch, "batched_fp32_ms_per_batch": t_batch * 1e3,
            "sequential_fp32_solves_per_s": n / t_seq32, "sequential_fp64_solves_per_s": n / t_seq64,
            "speedup_batched_fp32_over_sequential_fp64": t_seq64 / t_batch,

@@ -67,7 +67,9 @@ enum {
     PIPE_GREEN_IGF_Z = 1,   /* R_int of Eq. 16: z-factor g_z(w) of Eq. 15 (hat basis)     */
     PIPE_PREC_FP64 = 0x00,  /* transforms, products, rho and phi in double                */
     PIPE_PREC_FP32 = 0x10,  /* transforms, products, rho and phi in float                 */
-    PIPE_KEEP_GREEN = 0x100 /* keep the on-mesh Green table for pipe_plan_green_table     */
+    PIPE_KEEP_GREEN = 0x100,/* keep the on-mesh Green table for pipe_plan_green_table     */
+    PIPE_AUTOTUNE = 0x200,  /* time the candidate padded lengths, keep the fastest        */
+    PIPE_AUTOTUNE_BATCH = 0x400 /* as PIPE_AUTOTUNE, timing 16 concurrent solves (batches) */
 };
 
 typedef struct pipe_plan_info {
@@ -84,6 +86,8 @@ typedef struct pipe_plan_info {
     double pass_bytes[5];    /* the same per pass: z-forward, y-forward, x+product,         */
                              /* y-inverse, z-inverse                                        */
     double build_ms;         /* wall time of the plan build (Green evaluation + spectra)    */
+    double tune_ms;          /* PIPE_AUTOTUNE: the chosen lengths' measured ms per solve  */
+                             /* (0 = taken from the cache; -1 = not tuned)                */
 } pipe_plan_info_t;
 
 /*
@@ -110,6 +114,15 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
  * UNSUPPORTED_SIZE.  The physical result does not depend on the padded
  * lengths.  hip_stream (a hipStream_t, may be NULL) orders the build's GPU
  * work; the call still returns only when the build has finished.
+ * With PIPE_AUTOTUNE in kind and all lengths 0, the plan times the five
+ * passes for each candidate factorisation per dimension (the smallest
+ * supported length >= 2n, the smallest power of two, the smallest 3 * 2^k)
+ * on scratch buffers and keeps the fastest: one solve at a time (latency)
+ * with PIPE_AUTOTUNE, one grouped launch of 16 concurrent solves (throughput,
+ * the batched form) with PIPE_AUTOTUNE_BATCH.  The choice is cached for the
+ * process per (mesh, precision, mode) and appended to the file named by the
+ * environment variable PIPE_TUNE_CACHE, if set, which later processes read
+ * (one line per entry: nx ny nz real_bytes members lx ly lz).
  */
 pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, double hz,
                                  double a, double b, int kind, int mx, int my,

@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -148,6 +150,7 @@ struct pipe_plan_s {
     int tile = 0;            // kz tile of the table layout
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
+    double tune_ms = -1;     // autotuner: best candidate's time per solve, 0 if cached, -1 if not tuned
     size_t ws_bytes = 0;
     // event timing (pipe_plan_timing): 6 events per recorded solve
     std::vector<hipEvent_t> tev;
@@ -340,6 +343,195 @@ pipe_status_t solve_impl(pipe_plan_t plan, const void* rho, void* phi, void* ws,
 
 }  // namespace
 
+// ---------------------------------------------------------------- autotuner
+//
+// For a mesh with default padded lengths, the plan can time the five passes
+// for each candidate factorisation of the padded lengths (smallest supported
+// 2^p 3^q length >= 2n, smallest power of two, smallest 3 * 2^k) and keep the
+// fastest.  Pass timing does not depend on the values, so candidates run on
+// scratch buffers with a zero table.  Results are cached per (mesh,
+// precision) for the process and, if PIPE_TUNE_CACHE names a file, on disk.
+namespace {
+
+struct TuneKey {
+    int nx, ny, nz, rb, members;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(nx, ny, nz, rb, members) < std::tie(o.nx, o.ny, o.nz, o.rb, o.members);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::array<int, 3>> g_tune;
+bool g_tune_loaded = false;
+
+void tune_cache_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("PIPE_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    int nx, ny, nz, rb, mem, lx, ly, lz;
+    while (fscanf(f, "%d %d %d %d %d %d %d %d", &nx, &ny, &nz, &rb, &mem, &lx, &ly, &lz) == 8)
+        g_tune[{nx, ny, nz, rb, mem}] = {lx, ly, lz};
+    fclose(f);
+}
+
+void tune_cache_store(const TuneKey& k, const std::array<int, 3>& v) {
+    const char* path = getenv("PIPE_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%d %d %d %d %d %d %d %d\n", k.nx, k.ny, k.nz, k.rb, k.members, v[0], v[1], v[2]);
+    fclose(f);
+}
+
+// supported lengths >= need: the smallest, the smallest power of two, the smallest 3 * 2^k
+std::vector<int> length_candidates(int need) {
+    std::vector<int> out;
+    int best = -1, pow2 = -1, three = -1;
+    for (int v : kFftLengths) {
+        if (v < need) continue;
+        if (best < 0) best = v;
+        if (pow2 < 0 && (v & (v - 1)) == 0) pow2 = v;
+        if (three < 0 && v % 3 == 0) three = v;
+    }
+    for (int v : {best, pow2, three})
+        if (v > 0 && std::find(out.begin(), out.end(), v) == out.end()) out.push_back(v);
+    return out;
+}
+
+template <typename real>
+pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, hipStream_t st, bool adjoint,
+                         hipEvent_t* ev);
+template <typename real>
+pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al_in, bool al_out, hipStream_t st);
+
+// members = 1: time one solve at a time (latency); members > 1: time one grouped
+// launch of that many concurrent solves (throughput, as in a batch).
+pipe_status_t autotune_lengths(pipe_plan_s* tmpl, int members, hipStream_t st, int* lx, int* ly, int* lz,
+                               double* ms_out) {
+    const TuneKey key{tmpl->nx, tmpl->ny, tmpl->nz, tmpl->rb, members};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_load();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *lx = it->second[0];
+            *ly = it->second[1];
+            *lz = it->second[2];
+            *ms_out = 0.0;
+            return PIPE_OK;
+        }
+    }
+    const std::vector<int> cx = length_candidates(2 * tmpl->nx), cy = length_candidates(2 * tmpl->ny),
+                           cz = length_candidates(tmpl->nz);
+    struct Cand { int lx, ly, lz; };
+    std::vector<Cand> cands;
+    for (int a : cx)
+        for (int b : cy)
+            for (int c : cz) cands.push_back({a, b, 2 * c});
+    if (cands.size() == 1) {
+        *lx = cands[0].lx; *ly = cands[0].ly; *lz = cands[0].lz;
+        *ms_out = 0.0;
+        return PIPE_OK;
+    }
+    // scratch sized for the largest candidate
+    size_t ws_max = 0, tab_max = 0;
+    std::vector<pipe_plan_s> plans(cands.size(), *tmpl);
+    for (size_t i = 0; i < cands.size(); ++i) {
+        pipe_plan_s& q = plans[i];
+        q.lx = cands[i].lx; q.ly = cands[i].ly; q.lz = cands[i].lz; q.nh = q.lz / 2;
+        q.tile = xprod_tile(q.lx, q.rb);
+        const size_t orbits = (size_t)(q.lx / 2 + 1) * (q.ly / 2 + 1);
+        q.table_elems = 9 * orbits * ((q.nh + q.tile - 1) / q.tile) * q.tile;
+        q.nyq_elems = 9 * orbits;
+        q.ws_bytes = plan_ws_bytes(&q);
+        ws_max = std::max(ws_max, q.ws_bytes);
+        tab_max = std::max(tab_max, (q.table_elems + q.nyq_elems) * q.rb);
+    }
+    const size_t field = align256((size_t)tmpl->nx * tmpl->ny * tmpl->nz * tmpl->rb);
+    ws_max = align256(ws_max);
+    Scratch s;
+    void *ws, *tab, *rho, *phi;
+    GroupArgs* dargs = nullptr;
+    HIP_TRY(s.get(&ws, ws_max * members), "autotune allocation");
+    HIP_TRY(s.get(&tab, tab_max), "autotune allocation");
+    HIP_TRY(s.get(&rho, field), "autotune allocation");
+    HIP_TRY(s.get(&phi, field * members), "autotune allocation");
+    if (members > 1) HIP_TRY(s.get((void**)&dargs, sizeof(GroupArgs) * 5 * members), "autotune allocation");
+    HIP_TRY(hipMemsetAsync(tab, 0, tab_max, st), "autotune fill");
+    HIP_TRY(hipMemsetAsync(rho, 0, field, st), "autotune fill");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    double best = 1e30;
+    size_t bi = 0;
+    pipe_status_t rs = PIPE_OK;
+    for (size_t i = 0; i < cands.size() && rs == PIPE_OK; ++i) {
+        pipe_plan_s& q = plans[i];
+        q.table = tab;
+        q.nyq = (char*)tab + q.table_elems * q.rb;
+        q.tev.clear(); q.tmax = 0; q.tn = 0;
+        if (members > 1) {
+            std::vector<GroupArgs> a(5 * members);
+            for (int k = 0; k < members; ++k) {
+                char* A1 = (char*)ws + ws_max * k;
+                char* A2 = A1 + align256((size_t)q.nx * q.ny * q.nh * 2 * q.rb);
+                char* ph = (char*)phi + field * k;
+                a[0 * members + k] = {rho, A1, nullptr, nullptr, 0.0};
+                a[1 * members + k] = {A1, A2, nullptr, nullptr, 0.0};
+                a[2 * members + k] = {A2, A2, q.table, q.nyq, 0.0};
+                a[3 * members + k] = {A2, A1, nullptr, nullptr, 0.0};
+                a[4 * members + k] = {A1, ph, nullptr, nullptr, 1.0};
+            }
+            he = hipMemcpyAsync(dargs, a.data(), a.size() * sizeof(GroupArgs), hipMemcpyHostToDevice, st);
+            if (he == hipSuccess) he = hipStreamSynchronize(st);
+            if (he != hipSuccess) {
+                rs = hip_fail(he, "autotune descriptors");
+                break;
+            }
+        }
+        const int reps = 5;
+        for (int r = 0; r < 2 + reps && rs == PIPE_OK; ++r) {
+            if (r == 2) he = hipEventRecord(e0, st);
+            if (members > 1)
+                rs = q.rb == 8 ? launch_group<double>(&q, dargs, members, true, true, st)
+                               : launch_group<float>(&q, dargs, members, true, true, st);
+            else
+                rs = q.rb == 8 ? run_passes<double>(&q, rho, phi, ws, st, false, nullptr)
+                               : run_passes<float>(&q, rho, phi, ws, st, false, nullptr);
+        }
+        if (rs != PIPE_OK) break;
+        float ms = 0.f;
+        he = hipEventRecord(e1, st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) rs = hip_fail(he, "autotune timing");
+        else if (ms / (reps * members) < best) {
+            best = ms / (reps * members);
+            bi = i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rs != PIPE_OK) return rs;
+    *lx = cands[bi].lx; *ly = cands[bi].ly; *lz = cands[bi].lz;
+    *ms_out = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const std::array<int, 3> v{*lx, *ly, *lz};
+        g_tune[key] = v;
+        tune_cache_store(key, v);
+    }
+    return PIPE_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pipe_status_string(pipe_status_t s) {
@@ -362,7 +554,9 @@ pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, d
                                  pipe_plan_t* out) {
     if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
     *out = nullptr;
-    const bool keep = (kind & 0x100) != 0;
+    const bool keep = (kind & PIPE_KEEP_GREEN) != 0;
+    const bool tune = (kind & (PIPE_AUTOTUNE | PIPE_AUTOTUNE_BATCH)) != 0 && lx == 0 && ly == 0 && lz == 0;
+    const int tune_members = (kind & PIPE_AUTOTUNE_BATCH) ? 16 : 1;
     kind &= 0xff;
     pipe_status_t s = validate(nx, ny, nz, hx, hy, hz, a, b, kind, mx, my, &lx, &ly, &lz);
     if (s != PIPE_OK) return s;
@@ -375,6 +569,15 @@ pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, d
     if ((s = device_ctx(dev, &ctx)) != PIPE_OK) return s;
 
     auto t0 = std::chrono::steady_clock::now();
+    double tune_ms = -1.0;
+    if (tune) {
+        pipe_plan_s tmpl;
+        tmpl.nx = nx; tmpl.ny = ny; tmpl.nz = nz; tmpl.kind = kind; tmpl.rb = (kind & PIPE_PREC_FP32) ? 4 : 8;
+        tmpl.hx = hx; tmpl.hy = hy; tmpl.hz = hz; tmpl.a = a; tmpl.b = b; tmpl.mx = mx; tmpl.my = my;
+        tmpl.device = dev; tmpl.ctx = ctx;
+        if ((s = autotune_lengths(&tmpl, tune_members, (hipStream_t)hip_stream, &lx, &ly, &lz, &tune_ms)) != PIPE_OK)
+            return s;
+    }
     pipe_plan_s* p = new pipe_plan_s();
     p->nx = nx; p->ny = ny; p->nz = nz; p->lx = lx; p->ly = ly; p->lz = lz; p->nh = lz / 2;
     p->mx = mx; p->my = my; p->kind = kind; p->rb = (kind & PIPE_PREC_FP32) ? 4 : 8;
@@ -398,6 +601,7 @@ pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, d
         return s;
     }
     p->ws_bytes = plan_ws_bytes(p);
+    p->tune_ms = tune_ms;
     p->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     reg_add(p);
     *out = p;
@@ -424,6 +628,7 @@ pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     out->model_bytes = 0;
     for (double v : out->pass_bytes) out->model_bytes += v;
     out->build_ms = p->build_ms;
+    out->tune_ms = p->tune_ms;
     return PIPE_OK;
 }
 

@@ -22,6 +22,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pipe_poisson.h")
 POINT, IGF_Z = 0, 1
 PREC_FP64, PREC_FP32 = 0x00, 0x10
 KEEP_GREEN = 0x100
+AUTOTUNE = 0x200
+AUTOTUNE_BATCH = 0x400
 
 STATUS = {0: "PIPE_OK", 1: "PIPE_ERR_INVALID_ARG", 2: "PIPE_ERR_UNSUPPORTED_SIZE", 3: "PIPE_ERR_OUT_OF_MEMORY",
           4: "PIPE_ERR_NO_DEVICE", 5: "PIPE_ERR_HIP", 6: "PIPE_ERR_ALIASING"}
@@ -43,7 +45,7 @@ class PlanInfo(ctypes.Structure):
                 ("a", ctypes.c_double), ("b", ctypes.c_double), ("norm", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("spectra_bytes", ctypes.c_size_t),
                 ("model_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double * 5),
-                ("build_ms", ctypes.c_double)]
+                ("build_ms", ctypes.c_double), ("tune_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -126,12 +128,14 @@ class GreenPlan:
 
     kind: POINT or IGF_Z; precision: 'fp64' or 'fp32'.  mx, my default to
     2 nx, 2 ny; L = (lx, ly, lz) defaults to the smallest supported even
-    lengths >= 2n.
+    lengths >= 2n.  autotune: False, True (time single solves) or "batch"
+    (time 16 concurrent solves) to pick the padded lengths.
     """
 
     def __init__(self, nx, ny, nz, hx, hy, hz, a, b, kind=IGF_Z, precision="fp64", mx=None, my=None,
-                 L=None, keep_green=False, stream=None):
+                 L=None, keep_green=False, autotune=False, stream=None):
         flags = int(kind) | (PREC_FP32 if precision == "fp32" else PREC_FP64) | (KEEP_GREEN if keep_green else 0)
+        flags |= {False: 0, True: AUTOTUNE, "batch": AUTOTUNE_BATCH}[autotune]
         lx, ly, lz = L if L is not None else (0, 0, 0)
         h = _P()
         st = _stream_ptr(stream) if stream is not None else None
