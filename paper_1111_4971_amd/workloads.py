@@ -246,3 +246,23 @@ def batch_member(d):
     rho = _unit_charge(rho, d["hx"], d["hy"], d["hz"])
     return Workload("batch_%d" % d["index"], d["nx"], d["ny"], d["nz"], d["hx"], d["hy"], d["hz"],
                     d["a"], d["b"], d["kind"], d["mx"], d["my"], rho)
+
+
+def accuracy_study_bunch(n, nz, sigma_z, a=4.0, kind=IGF_Z, modes=20):
+    """The numerical example of Sec. 4 (lengths in cm): pipe a = b = 4, modes
+    m, n = 1..20, Gaussian with sigma_x = sigma_y = 0.15 a = 0.6 and the given
+    sigma_z, centred on the pipe axis, set to zero outside the 3-sigma
+    ellipsoid.  Transverse mesh: n nodes at X_i = (i+1) a/n (the last node on
+    the wall), so the axis x = a/2 is node n/2 - 1; z spans +-3 sigma_z with nz
+    nodes.  Returns the workload and the on-axis node index (i, j)."""
+    b = a
+    hx = hy = a / n
+    hz = 6.0 * sigma_z / (nz - 1)
+    X, Y, Z = coords(n, n, nz, hx, hy, hz)
+    sx = sy = 0.15 * a
+    q = (((X - a / 2) / sx) ** 2)[:, None, None] + (((Y - b / 2) / sy) ** 2)[None, :, None] \
+        + ((Z / sigma_z) ** 2)[None, None, :]
+    rho = np.exp(-0.5 * q) * (q <= 9.0)
+    wl = Workload("accuracy_study_n%d_nz%d_sz%g" % (n, nz, sigma_z), n, n, nz, hx, hy, hz, a, b, kind,
+                  modes, modes, rho)
+    return wl, (n // 2 - 1, n // 2 - 1)
