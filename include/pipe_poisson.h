@@ -92,8 +92,8 @@ typedef struct pipe_plan_info {
 
 /*
  * pipe_green_plan -- evaluate the Green function on the mesh and cache its
- * spectra (the "computed once, transformed 4 ways, stored and reused" step of
- * Sec. 5 and the tabulation after Eq. 10).
+ * spectra: the one-time tabulation and transformation that Sec. 2 (after
+ * Eq. 10) describes and Sec. 5 argues is amortised over many solves.
  *
  * nx, ny, nz >= 1 nodes; hx, hy, hz > 0 spacings; a, b > 0 pipe widths with
  * nx*hx <= a and ny*hy <= b (1e-12 relative slack, so a node may sit on a
