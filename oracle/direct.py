@@ -17,12 +17,12 @@ def _unique_table(vals):
     return uniq, inv.reshape(vals.shape)
 
 
-def green_tensor(nx, ny, nz, hx, hy, hz, a, b, mx, my, kind):
+def green_tensor(nx, ny, nz, hx, hy, hz, a, b, mx, my, kind, x0=0.0, y0=0.0):
     """G[i, i', j, j', d] for d = (k - k') + (nz - 1), from the node coordinates.
 
     Each distinct transverse distance is evaluated once by ``green.R_table``.
     """
-    X, Y = green.node_coords(nx, ny, hx, hy)
+    X, Y = green.node_coords(nx, ny, hx, hy, x0, y0)
     um = np.subtract.outer(X, X)
     up = np.add.outer(X, X)
     vm = np.subtract.outer(Y, Y)
@@ -39,11 +39,12 @@ def green_tensor(nx, ny, nz, hx, hy, hz, a, b, mx, my, kind):
     return term(0, 0) - term(0, 1) - term(1, 0) + term(1, 1)
 
 
-def solve(rho, hx, hy, hz, a, b, mx, my, kind):
-    """Direct O(n^2) sum of the definition above.  rho has shape (nx, ny, nz), FP64."""
+def solve(rho, hx, hy, hz, a, b, mx, my, kind, x0=0.0, y0=0.0):
+    """Direct O(n^2) sum of the definition above.  rho has shape (nx, ny, nz), FP64;
+    the mesh may be offset by (x0, y0) inside the pipe (node i at x0 + (i+1) hx)."""
     rho = np.asarray(rho, dtype=np.float64)
     nx, ny, nz = rho.shape
-    G = green_tensor(nx, ny, nz, hx, hy, hz, a, b, mx, my, kind)
+    G = green_tensor(nx, ny, nz, hx, hy, hz, a, b, mx, my, kind, x0, y0)
     phi = np.empty_like(rho)
     kp = np.arange(nz)
     for k in range(nz):
@@ -52,7 +53,7 @@ def solve(rho, hx, hy, hz, a, b, mx, my, kind):
     return hx * hy * hz * phi
 
 
-def solve_at(rho, points, hx, hy, hz, a, b, mx, my, kind):
+def solve_at(rho, points, hx, hy, hz, a, b, mx, my, kind, x0=0.0, y0=0.0):
     """The same direct sum, evaluated only at the listed output nodes (i, j, k).
 
     For full-size meshes: the mode factor g(kappa_mn, w)/kappa_mn is computed
@@ -62,7 +63,7 @@ def solve_at(rho, points, hx, hy, hz, a, b, mx, my, kind):
     """
     rho = np.asarray(rho, dtype=np.float64)
     nx, ny, nz = rho.shape
-    X, Y = green.node_coords(nx, ny, hx, hy)
+    X, Y = green.node_coords(nx, ny, hx, hy, x0, y0)
     r = np.arange(-(nz - 1), nz)
     d = green.mode_coefficients(r, hz, a, b, mx, my, kind)     # (mx, my, 2nz-1)
     kp = np.arange(nz)

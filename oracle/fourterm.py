@@ -51,22 +51,23 @@ def conv_slots(n, N, h):
     return d
 
 
-def corr_slots(n, N, h):
-    """Distances held by the correlation slots (X_i + X_i' = (m+2) h); NaN = zero slot."""
+def corr_slots(n, N, h, x0=0.0):
+    """Distances held by the correlation slots, X_i + X_i' = 2 x0 + (m+2) h with
+    m = i + i' (nodes at x0 + (i+1) h); NaN = zero slot."""
     d = np.full(N, np.nan)
     for m in range(0, 2 * n - 1):
-        d[m] = (m + 2) * h
+        d[m] = 2.0 * x0 + (m + 2) * h
     return d
 
 
-def green_array(shape, L, h, geom, kind, x_corr, y_corr):
+def green_array(shape, L, h, geom, kind, x_corr, y_corr, offset=(0.0, 0.0)):
     """xi_ab[p, q, r] for one term of Eq. 10, zero in unused slots."""
     nx, ny, nz = shape
     Lx, Ly, Lz = L
     hx, hy, hz = h
     a, b, mx, my = geom
-    ux = corr_slots(nx, Lx, hx) if x_corr else conv_slots(nx, Lx, hx)
-    vy = corr_slots(ny, Ly, hy) if y_corr else conv_slots(ny, Ly, hy)
+    ux = corr_slots(nx, Lx, hx, offset[0]) if x_corr else conv_slots(nx, Lx, hx)
+    vy = corr_slots(ny, Ly, hy, offset[1]) if y_corr else conv_slots(ny, Ly, hy)
     rz = np.zeros(Lz, dtype=np.int64)
     okz = np.zeros(Lz, dtype=bool)
     for m in range(-(nz - 1), nz):
@@ -88,20 +89,22 @@ TERMS = (
 )
 
 
-def green_spectra(shape, L, h, geom, kind):
+def green_spectra(shape, L, h, geom, kind, offset=(0.0, 0.0)):
     """The four mixed-direction transforms of the Green arrays (the stored, reused spectra)."""
     out = []
     for sign, xc, yc, gdir, fdir in TERMS:
-        xi = green_array(shape, L, h, geom, kind, xc, yc)
+        xi = green_array(shape, L, h, geom, kind, xc, yc, offset)
         out.append(_F3(xi.astype(np.complex128), gdir))
     return out
 
 
-def solve(rho, hx, hy, hz, a, b, mx, my, kind, L=None, spectra=None, return_imag=False):
+def solve(rho, hx, hy, hz, a, b, mx, my, kind, L=None, spectra=None, return_imag=False, x0=0.0, y0=0.0):
     """Eq. 10: phi on the physical nodes for rho of shape (nx, ny, nz), FP64.
 
     L = (Lx, Ly, Lz) defaults to (2nx, 2ny, 2nz); any L >= 2n - 1 per axis is
-    valid (Appendix, Eq. A.3 and the remark on N >= M).
+    valid (Appendix, Eq. A.3 and the remark on N >= M).  (x0, y0) offsets the
+    mesh inside the pipe (node i at x0 + (i+1) hx); only the correlation
+    slots see it.
     """
     rho = np.asarray(rho, dtype=np.float64)
     nx, ny, nz = rho.shape
@@ -111,7 +114,7 @@ def solve(rho, hx, hy, hz, a, b, mx, my, kind, L=None, spectra=None, return_imag
     if Lx < 2 * nx - 1 or Ly < 2 * ny - 1 or Lz < 2 * nz - 1:
         raise ValueError("padded length must be at least 2n-1 in every dimension")
     if spectra is None:
-        spectra = green_spectra(rho.shape, L, (hx, hy, hz), (a, b, mx, my), kind)
+        spectra = green_spectra(rho.shape, L, (hx, hy, hz), (a, b, mx, my), kind, (x0, y0))
     pad = np.zeros((Lx, Ly, Lz), dtype=np.complex128)
     pad[:nx, :ny, :nz] = rho
     rho_hat = _F3(pad, 'fff')

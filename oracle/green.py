@@ -198,7 +198,11 @@ def G_sine_series(x, xp, y, yp, r, hz, a, b, mx, my, kind):
     return np.einsum('im,jm,kn,ln,mnr->ijklr', sx, sxp, sy, syp, d)
 
 
-def node_coords(nx, ny, hx, hy):
-    """Transverse node positions X_i = (i+1) h_x, Y_j = (j+1) h_y (0-based i, j)."""
-    return (np.arange(1, nx + 1, dtype=np.float64) * hx,
-            np.arange(1, ny + 1, dtype=np.float64) * hy)
+def node_coords(nx, ny, hx, hy, x0=0.0, y0=0.0):
+    """Transverse node positions X_i = x0 + (i+1) h_x, Y_j = y0 + (j+1) h_y (0-based i, j).
+
+    x0 = y0 = 0 is the mesh anchored one cell inside the walls x = 0, y = 0;
+    a positive offset places the mesh on a sub-region of the cross-section
+    (Sec. 5: only the region around the beam needs to be meshed)."""
+    return (x0 + np.arange(1, nx + 1, dtype=np.float64) * hx,
+            y0 + np.arange(1, ny + 1, dtype=np.float64) * hy)

@@ -363,3 +363,38 @@ def test_sampled_direct_sum_equals_full_direct_sum():
         pts = [(0, 0, 0), (4, 3, 5), (2, 1, 3), (1, 2, 0)]
         got = direct.solve_at(rho, pts, hx, hy, 0.1, a, b, 9, 7, kind)
         assert np.allclose(got, [full[p] for p in pts], rtol=1e-13, atol=1e-15 * np.max(np.abs(full)))
+
+
+# ---------------------------------------------------------------- transverse sub-region mesh (Sec. 5)
+
+@pytest.mark.parametrize("kind", [POINT, IGF])
+def test_offset_mesh_equals_full_mesh_restricted(kind):
+    """A mesh offset by (k0 h, l0 h) is the block k0.., l0.. of the full mesh with the
+    same spacing: with charge only in that block both give the same potential there."""
+    nx, ny, nz = 4, 3, 5
+    k0, l0 = 2, 1
+    NX, NY = 8, 6
+    a, b = (NX + 1) * 0.1, (NY + 1) * 0.12
+    hx, hy = 0.1, 0.12
+    rng = np.random.default_rng(51)
+    rho = rng.standard_normal((nx, ny, nz))
+    full = np.zeros((NX, NY, nz))
+    full[k0:k0 + nx, l0:l0 + ny] = rho
+    ref = fourterm.solve(full, hx, hy, 0.1, a, b, 11, 9, kind)[k0:k0 + nx, l0:l0 + ny]
+    got2 = fourterm.solve(rho, hx, hy, 0.1, a, b, 11, 9, kind, x0=k0 * hx, y0=l0 * hy)
+    got1 = direct.solve(rho, hx, hy, 0.1, a, b, 11, 9, kind, x0=k0 * hx, y0=l0 * hy)
+    assert rel_l2(got2, ref) <= 1e-13 and rel_l2(got1, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("kind", [POINT, IGF])
+def test_offset_mesh_centred_is_mirror_symmetric(kind):
+    nx, ny, nz = 5, 4, 6
+    a, b = 1.0, 1.2
+    hx, hy = 0.1, 0.11
+    x0, y0 = (a - (nx + 1) * hx) / 2, (b - (ny + 1) * hy) / 2
+    rng = np.random.default_rng(52)
+    rho = rng.standard_normal((nx, ny, nz))
+    A = lambda r: fourterm.solve(r, hx, hy, 0.1, a, b, 13, 11, kind, x0=x0, y0=y0)
+    base = A(rho)
+    assert rel_l2(A(rho[::-1].copy()), base[::-1]) <= 1e-13
+    assert rel_l2(A(rho[:, ::-1].copy()), base[:, ::-1]) <= 1e-13
