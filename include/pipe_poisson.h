@@ -79,6 +79,7 @@ typedef struct pipe_plan_info {
     int kind;                /* as passed                                                   */
     int real_bytes;          /* 8 (FP64) or 4 (FP32)                                        */
     double hx, hy, hz, a, b;
+    double x0, y0;           /* mesh offset (pipe_green_plan_region; 0 otherwise)           */
     double norm;             /* the R prefactor 1/(2 pi a b)                                */
     size_t workspace_bytes;  /* device bytes a solve needs as scratch                       */
     size_t spectra_bytes;    /* device bytes held by the plan's Green spectra               */
@@ -127,6 +128,18 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
 pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, double hz,
                                  double a, double b, int kind, int mx, int my,
                                  int lx, int ly, int lz, void* hip_stream, pipe_plan_t* out);
+
+/*
+ * pipe_green_plan_region -- as pipe_green_plan_ex for a mesh covering only a
+ * sub-region of the pipe cross-section (Sec. 5: a thin beam needs only the
+ * area around it meshed): node i at x0 + (i+1) hx, node j at y0 + (j+1) hy,
+ * with x0, y0 >= 0, x0 + nx hx <= a and y0 + ny hy <= b.  The Green function
+ * is still that of the whole pipe; only the distances X_i + X_i' of the image
+ * terms change (to 2 x0 + (i+i'+2) hx).  Errors as pipe_green_plan_ex.
+ */
+pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double hy, double hz,
+                                     double a, double b, double x0, double y0, int kind, int mx, int my,
+                                     int lx, int ly, int lz, void* hip_stream, pipe_plan_t* out);
 
 /* pipe_plan_info -- sizes and constants of a plan.  Errors: INVALID_ARG. */
 pipe_status_t pipe_plan_info(pipe_plan_t plan, pipe_plan_info_t* out);
@@ -187,7 +200,9 @@ const char* pipe_last_error(void);
 /*
  * pipe_plan_green_table -- copy the on-mesh Green table the plan evaluated
  * (Eq. 9 or Eq. 16 at the distances the four terms need) to out_device:
- * FP64 array [2nx+1][2ny+1][nz], element [p][q][r] = R(p hx, q hy, r hz).
+ * FP64 array [3nx-1][3ny-1][nz], element [p][q][r] = R(u_p, v_q, r hz) with
+ * u_p = p hx for p < nx (differences X_i - X_i') and u_p = 2 x0 + (p - nx + 2) hx
+ * for nx <= p < 3nx - 1 (sums X_i + X_i'); v_q likewise in y.
  * Returns INVALID_ARG unless the plan was built with PIPE_KEEP_GREEN in kind.
  */
 pipe_status_t pipe_plan_green_table(pipe_plan_t plan, void* out_device, void* hip_stream);

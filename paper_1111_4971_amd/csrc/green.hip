@@ -3,9 +3,10 @@
 //
 // R(u, v, w) = 1/(2 pi a b) sum_{m<=mx, n<=my} kappa_mn^{-1} cos(m pi u/a) cos(n pi v/b) g(kappa_mn, w)
 // (Eq. 9; Eq. 16 for the z-integrated kind), kappa_mn^2 = (m pi/a)^2 + (n pi/b)^2,
-// is needed at u = p hx (p <= 2nx), v = q hy (q <= 2ny), w = r hz (r < nz):
+// is needed at the differences u = p hx (p < nx) and sums u = 2 x0 + (p + 2) hx
+// (p <= 2nx - 2) of node positions x0 + (i+1) hx, likewise in y, and w = r hz (r < nz):
 //   Rbar[p][q][r] = sum_m Cx[p][m] sum_n Cy[q][n] D[m][n][r],
-//   Cx[p][m] = cos(pi m p hx / a),  Cy[q][n] = cos(pi n q hy / b),
+//   Cx[p][m] = cos(pi m u_p / a),  Cy[q][n] = cos(pi n v_q / b),
 //   D[m][n][r] = g(kappa_mn, r hz) / (2 pi a b kappa_mn),
 // computed as two FP64 matrix products (y contraction per m, then x).
 // g is e^{-kappa |w|} (Eq. 9) or the IGF z-kernel of Eq. 15, evaluated in a form
@@ -28,11 +29,27 @@ __device__ __forceinline__ double cospi_prod(double t, double s) {
     return cospi(red + lo);
 }
 
-__global__ void cos_table_kernel(double* out, int np, int m, double s) {
+// t * s reduced modulo 2 (exactly, then the rounding error of the product added back)
+__device__ __forceinline__ double red2_prod(double t, double s) {
+    const double hi = t * s;
+    const double lo = fma(t, s, -hi);
+    return (hi - 2.0 * rint(0.5 * hi)) + lo;
+}
+
+// Cosines of the distances the four terms need along one axis, for modes m = 1..M:
+// rows p < nconv:  cos(pi m p h / a)                        (differences, p h)
+// rows nconv + p:  cos(pi m (2 x0 + (p + 2) h) / a), p < ncorr  (sums X_i + X_i')
+// with s = h / a and off = 2 x0 / a.
+__global__ void cos_table_kernel(double* out, int nconv, int ncorr, int m, double s, double off) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long)np * m) return;
+    if (i >= (long)(nconv + ncorr) * m) return;
     const int p = (int)(i / m), mm = (int)(i % m) + 1;
-    out[i] = cospi_prod((double)p * (double)mm, s);
+    if (p < nconv) {
+        out[i] = cospi_prod((double)p * (double)mm, s);
+    } else {
+        const double t = red2_prod((double)(p - nconv + 2) * (double)mm, s) + red2_prod((double)mm, off);
+        out[i] = cospi(t);
+    }
 }
 
 __device__ __forceinline__ double igf_g(double x, int r) {
@@ -123,15 +140,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 }
 
 // xi[p][q][s] = Rbar at term ab's distance for slot (p, q, s), zero in unused slots
-// (Appendix, Eq. A.3 for convolution slots, remark A.9 for correlation slots):
-//   convolution slot p: m = p (p <= L/2) or p - L; used when |m| <= n - 1, distance |m| h;
-//   correlation slot p: used when p <= 2n - 2, distance (p + 2) h  (X_i + X_i' = (i + i' + 2) h).
+// (Appendix, Eq. A.3 for convolution slots, remark A.9 for correlation slots).
+// Rbar rows along x: 0..n-1 the differences |m| h, n..3n-2 the sums 2 x0 + (p + 2) h:
+//   convolution slot p: m = p (p <= L/2) or p - L; used when |m| <= n - 1 -> row |m|;
+//   correlation slot p: used when p <= 2n - 2 (p = i + i') -> row n + p.
 __device__ __forceinline__ int conv_slot(int p, int L, int n) {
     const int m = (p <= L / 2) ? p : p - L;
     const int am = m < 0 ? -m : m;
     return am <= n - 1 ? am : -1;
 }
-__device__ __forceinline__ int corr_slot(int p, int n) { return p <= 2 * n - 2 ? p + 2 : -1; }
+__device__ __forceinline__ int corr_slot(int p, int n) { return p <= 2 * n - 2 ? n + p : -1; }
 
 __global__ void arrange_kernel(double* xi, const double* __restrict__ rbar, int nx, int ny, int nz, int lx,
                                int ly, int lz, int xcorr, int ycorr) {
@@ -145,7 +163,7 @@ __global__ void arrange_kernel(double* xi, const double* __restrict__ rbar, int 
     const int iq = ycorr ? corr_slot(q, ny) : conv_slot(q, ly, ny);
     const int is = conv_slot(s, lz, nz);
     double v = 0.0;
-    if (ip >= 0 && iq >= 0 && is >= 0) v = rbar[((long)ip * (2 * ny + 1) + iq) * nz + is];
+    if (ip >= 0 && iq >= 0 && is >= 0) v = rbar[((long)ip * (3 * ny - 1) + iq) * nz + is];
     xi[i] = v;
 }
 
@@ -224,9 +242,9 @@ __global__ void untile_kernel(const T_* __restrict__ table, const T_* __restrict
 
 static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-hipError_t launch_cos_table(double* out, int np, int m, double s, hipStream_t st) {
-    const long n = (long)np * m;
-    hipLaunchKernelGGL(cos_table_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, out, np, m, s);
+hipError_t launch_cos_table(double* out, int nconv, int ncorr, int m, double s, double off, hipStream_t st) {
+    const long n = (long)(nconv + ncorr) * m;
+    hipLaunchKernelGGL(cos_table_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, out, nconv, ncorr, m, s, off);
     return hipGetLastError();
 }
 

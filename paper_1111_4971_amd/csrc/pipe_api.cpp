@@ -142,6 +142,7 @@ int pick_length(int need) {
 struct pipe_plan_s {
     int nx, ny, nz, lx, ly, lz, nh, mx, my, kind, rb;
     double hx, hy, hz, a, b;
+    double x0 = 0, y0 = 0;   // mesh offset: node i at x0 + (i+1) hx, node j at y0 + (j+1) hy
     int device;
     DeviceCtx* ctx;
     void* table = nullptr;   // tile-blocked spectra, 9 values per orbit (see xprod_tile)
@@ -182,14 +183,18 @@ void plan_pass_bytes(const pipe_plan_s* p, double out[5]) {
     out[4] = a1 + phys;
 }
 
-pipe_status_t validate(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b, int kind,
-                       int mx, int my, int* lx, int* ly, int* lz) {
+pipe_status_t validate(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b, double x0,
+                       double y0, int kind, int mx, int my, int* lx, int* ly, int* lz) {
     if (nx < 1 || ny < 1 || nz < 1) return fail(PIPE_ERR_INVALID_ARG, "mesh sizes must be >= 1 (got %d,%d,%d)", nx, ny, nz);
     const double v[5] = {hx, hy, hz, a, b};
     for (double t : v)
         if (!(t > 0.0) || !std::isfinite(t)) return fail(PIPE_ERR_INVALID_ARG, "spacings and pipe sizes must be finite and > 0");
-    if (nx * hx > a * (1.0 + 1e-12)) return fail(PIPE_ERR_INVALID_ARG, "nx*hx = %g exceeds the pipe width a = %g", nx * hx, a);
-    if (ny * hy > b * (1.0 + 1e-12)) return fail(PIPE_ERR_INVALID_ARG, "ny*hy = %g exceeds the pipe height b = %g", ny * hy, b);
+    if (!(x0 >= 0.0) || !(y0 >= 0.0) || !std::isfinite(x0) || !std::isfinite(y0))
+        return fail(PIPE_ERR_INVALID_ARG, "mesh offsets must be finite and >= 0");
+    if (x0 + nx * hx > a * (1.0 + 1e-12))
+        return fail(PIPE_ERR_INVALID_ARG, "x0 + nx*hx = %g exceeds the pipe width a = %g", x0 + nx * hx, a);
+    if (y0 + ny * hy > b * (1.0 + 1e-12))
+        return fail(PIPE_ERR_INVALID_ARG, "y0 + ny*hy = %g exceeds the pipe height b = %g", y0 + ny * hy, b);
     const int g = kind & 0x0f, pr = kind & ~0x0f;
     if (g != PIPE_GREEN_POINT && g != PIPE_GREEN_IGF_Z) return fail(PIPE_ERR_INVALID_ARG, "unknown Green kind %d", g);
     if (pr != PIPE_PREC_FP64 && pr != PIPE_PREC_FP32) return fail(PIPE_ERR_INVALID_ARG, "unknown precision flag 0x%x", pr);
@@ -227,7 +232,8 @@ struct Scratch {
 };
 
 pipe_status_t build_spectra(pipe_plan_s* p, hipStream_t st, bool keep_green) {
-    const int px = 2 * p->nx + 1, qy = 2 * p->ny + 1, rz = p->nz;
+    // Rbar rows: nx differences then 2nx - 1 sums along x, likewise along y
+    const int px = 3 * p->nx - 1, qy = 3 * p->ny - 1, rz = p->nz;
     const int lx = p->lx, ly = p->ly, lz = p->lz, nh = p->nh;
     Scratch s;
     double *cx, *cy, *d, *u, *rbar, *buf;
@@ -239,8 +245,8 @@ pipe_status_t build_spectra(pipe_plan_s* p, hipStream_t st, bool keep_green) {
     HIP_TRY(s.get((void**)&buf, sizeof(double) * (size_t)lx * ly * lz), "allocation (spectrum buffer)");
 
     const double norm = 1.0 / (2.0 * M_PI * p->a * p->b);
-    HIP_TRY(launch_cos_table(cx, px, p->mx, p->hx / p->a, st), "cos table");
-    HIP_TRY(launch_cos_table(cy, qy, p->my, p->hy / p->b, st), "cos table");
+    HIP_TRY(launch_cos_table(cx, p->nx, 2 * p->nx - 1, p->mx, p->hx / p->a, 2.0 * p->x0 / p->a, st), "cos table");
+    HIP_TRY(launch_cos_table(cy, p->ny, 2 * p->ny - 1, p->my, p->hy / p->b, 2.0 * p->y0 / p->b, st), "cos table");
     HIP_TRY(launch_modes(d, p->mx, p->my, rz, p->a, p->b, p->hz, (p->kind & 0x0f) == PIPE_GREEN_IGF_Z, norm, st), "mode table");
     // U[m] (qy x rz) = Cy (qy x my) * D[m] (my x rz)
     HIP_TRY(launch_gemm_f64(cy, d, u, qy, rz, p->my, p->my, rz, rz, 0, (long)p->my * rz, (long)qy * rz, p->mx, st),
@@ -549,16 +555,16 @@ const char* pipe_status_string(pipe_status_t s) {
 
 const char* pipe_last_error(void) { return g_err.c_str(); }
 
-pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b,
-                                 int kind, int mx, int my, int lx, int ly, int lz, void* hip_stream,
-                                 pipe_plan_t* out) {
+pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b,
+                                     double x0, double y0, int kind, int mx, int my, int lx, int ly, int lz,
+                                     void* hip_stream, pipe_plan_t* out) {
     if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
     *out = nullptr;
     const bool keep = (kind & PIPE_KEEP_GREEN) != 0;
     const bool tune = (kind & (PIPE_AUTOTUNE | PIPE_AUTOTUNE_BATCH)) != 0 && lx == 0 && ly == 0 && lz == 0;
     const int tune_members = (kind & PIPE_AUTOTUNE_BATCH) ? 16 : 1;
     kind &= 0xff;
-    pipe_status_t s = validate(nx, ny, nz, hx, hy, hz, a, b, kind, mx, my, &lx, &ly, &lz);
+    pipe_status_t s = validate(nx, ny, nz, hx, hy, hz, a, b, x0, y0, kind, mx, my, &lx, &ly, &lz);
     if (s != PIPE_OK) return s;
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -582,6 +588,7 @@ pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, d
     p->nx = nx; p->ny = ny; p->nz = nz; p->lx = lx; p->ly = ly; p->lz = lz; p->nh = lz / 2;
     p->mx = mx; p->my = my; p->kind = kind; p->rb = (kind & PIPE_PREC_FP32) ? 4 : 8;
     p->hx = hx; p->hy = hy; p->hz = hz; p->a = a; p->b = b;
+    p->x0 = x0; p->y0 = y0;
     p->device = dev; p->ctx = ctx;
     const size_t orbits = (size_t)(lx / 2 + 1) * (ly / 2 + 1);
     p->tile = xprod_tile(lx, p->rb);
@@ -608,6 +615,12 @@ pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, d
     return PIPE_OK;
 }
 
+pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b,
+                                 int kind, int mx, int my, int lx, int ly, int lz, void* hip_stream,
+                                 pipe_plan_t* out) {
+    return pipe_green_plan_region(nx, ny, nz, hx, hy, hz, a, b, 0.0, 0.0, kind, mx, my, lx, ly, lz, hip_stream, out);
+}
+
 pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b, int kind,
                               pipe_plan_t* out) {
     return pipe_green_plan_ex(nx, ny, nz, hx, hy, hz, a, b, kind, 2 * nx, 2 * ny, 0, 0, 0, nullptr, out);
@@ -621,6 +634,7 @@ pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     out->lx = p->lx; out->ly = p->ly; out->lz = p->lz;
     out->mx = p->mx; out->my = p->my; out->kind = p->kind; out->real_bytes = p->rb;
     out->hx = p->hx; out->hy = p->hy; out->hz = p->hz; out->a = p->a; out->b = p->b;
+    out->x0 = p->x0; out->y0 = p->y0;
     out->norm = 1.0 / (2.0 * M_PI * p->a * p->b);
     out->workspace_bytes = p->ws_bytes;
     out->spectra_bytes = (p->table_elems + p->nyq_elems) * p->rb;
@@ -706,7 +720,7 @@ pipe_status_t pipe_plan_green_table(pipe_plan_t p, void* out, void* stream) {
     if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
     if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
     if (!p->green) return fail(PIPE_ERR_INVALID_ARG, "plan was built without keeping its Green table");
-    const size_t n = (size_t)(2 * p->nx + 1) * (2 * p->ny + 1) * p->nz;
+    const size_t n = (size_t)(3 * p->nx - 1) * (3 * p->ny - 1) * p->nz;
     HIP_TRY(hipMemcpyAsync(out, p->green, n * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream), "copy");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "copy");
     return PIPE_OK;

@@ -66,7 +66,7 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
 int xprod_tile(int lx, int real_bytes);
 
 // Green evaluation (green.hip).
-hipError_t launch_cos_table(double* out, int np, int m, double s, hipStream_t st);
+hipError_t launch_cos_table(double* out, int nconv, int ncorr, int m, double s, double off, hipStream_t st);
 hipError_t launch_modes(double* d, int mx, int my, int rz, double a, double b, double hz, int igf,
                         double norm, hipStream_t st);
 hipError_t launch_gemm_f64(const double* A, const double* B, double* C, int M, int N, int K,

@@ -42,7 +42,8 @@ class PlanInfo(ctypes.Structure):
                 ("mx", ctypes.c_int), ("my", ctypes.c_int), ("kind", ctypes.c_int),
                 ("real_bytes", ctypes.c_int),
                 ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
-                ("a", ctypes.c_double), ("b", ctypes.c_double), ("norm", ctypes.c_double),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("norm", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("spectra_bytes", ctypes.c_size_t),
                 ("model_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double * 5),
                 ("build_ms", ctypes.c_double), ("tune_ms", ctypes.c_double)]
@@ -71,6 +72,8 @@ def lib():
         "pipe_green_plan": ([_I, _I, _I, _D, _D, _D, _D, _D, _I, ctypes.POINTER(_P)], _I),
         "pipe_green_plan_ex": ([_I, _I, _I, _D, _D, _D, _D, _D, _I, _I, _I, _I, _I, _I, _P,
                                 ctypes.POINTER(_P)], _I),
+        "pipe_green_plan_region": ([_I, _I, _I, _D, _D, _D, _D, _D, _D, _D, _I, _I, _I, _I, _I, _I, _P,
+                                    ctypes.POINTER(_P)], _I),
         "pipe_plan_info": ([_P, ctypes.POINTER(PlanInfo)], _I),
         "pipe_poisson_solve": ([_P, _P, _P, _P, _P], _I),
         "pipe_poisson_adjoint": ([_P, _P, _P, _P, _P], _I),
@@ -129,18 +132,20 @@ class GreenPlan:
     kind: POINT or IGF_Z; precision: 'fp64' or 'fp32'.  mx, my default to
     2 nx, 2 ny; L = (lx, ly, lz) defaults to the smallest supported even
     lengths >= 2n.  autotune: False, True (time single solves) or "batch"
-    (time 16 concurrent solves) to pick the padded lengths.
+    (time 16 concurrent solves) to pick the padded lengths.  offset = (x0, y0)
+    places the mesh on a sub-region of the cross-section (node i at
+    x0 + (i+1) hx).
     """
 
     def __init__(self, nx, ny, nz, hx, hy, hz, a, b, kind=IGF_Z, precision="fp64", mx=None, my=None,
-                 L=None, keep_green=False, autotune=False, stream=None):
+                 L=None, keep_green=False, autotune=False, stream=None, offset=(0.0, 0.0)):
         flags = int(kind) | (PREC_FP32 if precision == "fp32" else PREC_FP64) | (KEEP_GREEN if keep_green else 0)
         flags |= {False: 0, True: AUTOTUNE, "batch": AUTOTUNE_BATCH}[autotune]
         lx, ly, lz = L if L is not None else (0, 0, 0)
         h = _P()
         st = _stream_ptr(stream) if stream is not None else None
-        check(lib().pipe_green_plan_ex(nx, ny, nz, hx, hy, hz, a, b, flags, mx or 2 * nx, my or 2 * ny,
-                                       lx, ly, lz, st, ctypes.byref(h)))
+        check(lib().pipe_green_plan_region(nx, ny, nz, hx, hy, hz, a, b, float(offset[0]), float(offset[1]), flags,
+                                           mx or 2 * nx, my or 2 * ny, lx, ly, lz, st, ctypes.byref(h)))
         self._h = h
         info = PlanInfo()
         check(lib().pipe_plan_info(h, ctypes.byref(info)))
@@ -212,9 +217,10 @@ class GreenPlan:
         return list(ms), n.value
 
     def green_table(self):
+        """R at [differences p hx (p < nx), sums 2 x0 + (p + 2) hx (p <= 2nx - 2)] x [same in y] x [r hz]."""
         torch = _torch()
         nx, ny, nz = self.shape
-        out = torch.empty((2 * nx + 1, 2 * ny + 1, nz), dtype=torch.float64, device="cuda")
+        out = torch.empty((3 * nx - 1, 3 * ny - 1, nz), dtype=torch.float64, device="cuda")
         check(lib().pipe_plan_green_table(self.handle, _P(out.data_ptr()), _stream_ptr()))
         return out
 

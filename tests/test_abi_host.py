@@ -118,3 +118,14 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pipe, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         pipe.lib()
+
+
+@needs_lib
+@pytest.mark.parametrize("x0,y0", [(-0.1, 0.0), (0.0, float("nan")), (0.65, 0.0), (0.0, 0.8), (float("inf"), 0.0)])
+def test_region_offsets_are_validated(x0, y0):
+    """4 nodes of spacing 0.1 in a 1 x 1 pipe: offsets must be finite, >= 0 and keep x0 + 0.4 <= 1."""
+    L = pipe.lib()
+    h = ctypes.c_void_p()
+    st = L.pipe_green_plan_region(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, x0, y0, 0, 8, 8, 0, 0, 0, None,
+                                  ctypes.byref(h))
+    assert st == 1 and not h.value, pipe.lib().pipe_last_error().decode()

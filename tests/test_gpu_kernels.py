@@ -51,14 +51,33 @@ def _small_plan(kind, prec, nx=7, ny=5, nz=9, a=1.0, b=1.3, keep=True, **kw):
                           keep_green=keep, **kw), (nx, ny, nz, hx, hy, 0.11, a, b)
 
 
+def table_distances(n, h, x0=0.0):
+    """The rows of the plan's Green table: differences p h (p < n), then sums 2 x0 + (p + 2) h."""
+    return np.concatenate([np.arange(n) * h, 2.0 * x0 + (np.arange(2 * n - 1) + 2) * h])
+
+
 @pytest.mark.parametrize("kind", [0, 1])
 def test_green_table_matches_oracle_small(torch_cuda, kind):
     from oracle import green
     log("green table small kind=%d" % kind)
     plan, (nx, ny, nz, hx, hy, hz, a, b) = _small_plan(kind, "fp64", mx=13, my=9)
     got = plan.green_table().cpu().numpy()
-    ref = green.R_table(np.arange(2 * nx + 1) * hx, np.arange(2 * ny + 1) * hy, np.arange(nz), hz,
-                        a, b, 13, 9, kind)
+    ref = green.R_table(table_distances(nx, hx), table_distances(ny, hy), np.arange(nz), hz, a, b, 13, 9, kind)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_green_table_with_offset_matches_oracle(torch_cuda, kind):
+    from oracle import green
+    from paper_1111_4971_amd import pipe
+    nx, ny, nz, a, b = 6, 5, 7, 1.0, 1.3
+    hx, hy, x0, y0 = 0.1, 0.12, 0.17, 0.31
+    log("green table offset kind=%d" % kind)
+    plan = pipe.GreenPlan(nx, ny, nz, hx, hy, 0.1, a, b, kind=kind, precision="fp64", mx=13, my=9,
+                          keep_green=True, offset=(x0, y0))
+    got = plan.green_table().cpu().numpy()
+    ref = green.R_table(table_distances(nx, hx, x0), table_distances(ny, hy, y0), np.arange(nz), 0.1, a, b,
+                        13, 9, kind)
     assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
 
 
@@ -71,7 +90,7 @@ def test_green_table_matches_oracle_full_size(torch_cuda, which):
     plan = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind,
                           precision="fp64", mx=wl.mx, my=wl.my, keep_green=True)
     got = plan.green_table().cpu().numpy()
-    ref = green.R_table(np.arange(2 * wl.nx + 1) * wl.hx, np.arange(2 * wl.ny + 1) * wl.hy,
+    ref = green.R_table(table_distances(wl.nx, wl.hx), table_distances(wl.ny, wl.hy),
                         np.arange(wl.nz), wl.hz, wl.a, wl.b, wl.mx, wl.my, wl.kind)
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     assert err <= 1e-13, err
