@@ -39,12 +39,19 @@ def green_tensor(nx, ny, nz, hx, hy, hz, a, b, mx, my, kind, x0=0.0, y0=0.0):
     return term(0, 0) - term(0, 1) - term(1, 0) + term(1, 1)
 
 
-def solve(rho, hx, hy, hz, a, b, mx, my, kind, x0=0.0, y0=0.0):
+def solve(rho, hx, hy, hz, a, b, mx, my, kind, x0=0.0, y0=0.0, band=None):
     """Direct O(n^2) sum of the definition above.  rho has shape (nx, ny, nz), FP64;
-    the mesh may be offset by (x0, y0) inside the pipe (node i at x0 + (i+1) hx)."""
+    the mesh may be offset by (x0, y0) inside the pipe (node i at x0 + (i+1) hx).
+
+    band = N restricts the z sum to |k - k'| <= N (Eq. 17 for N = 0, Eq. 18 in
+    general: the neighbouring-plane approximation when the z-kernel is
+    negligible beyond N planes); None keeps every plane."""
     rho = np.asarray(rho, dtype=np.float64)
     nx, ny, nz = rho.shape
     G = green_tensor(nx, ny, nz, hx, hy, hz, a, b, mx, my, kind, x0, y0)
+    if band is not None:
+        d = np.arange(-(nz - 1), nz)
+        G[..., np.abs(d) > band] = 0.0
     phi = np.empty_like(rho)
     kp = np.arange(nz)
     for k in range(nz):

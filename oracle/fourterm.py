@@ -60,8 +60,9 @@ def corr_slots(n, N, h, x0=0.0):
     return d
 
 
-def green_array(shape, L, h, geom, kind, x_corr, y_corr, offset=(0.0, 0.0)):
-    """xi_ab[p, q, r] for one term of Eq. 10, zero in unused slots."""
+def green_array(shape, L, h, geom, kind, x_corr, y_corr, offset=(0.0, 0.0), band=None):
+    """xi_ab[p, q, r] for one term of Eq. 10, zero in unused slots (and, with
+    band = N, zero for z distances beyond N planes: Eq. 18)."""
     nx, ny, nz = shape
     Lx, Ly, Lz = L
     hx, hy, hz = h
@@ -71,6 +72,8 @@ def green_array(shape, L, h, geom, kind, x_corr, y_corr, offset=(0.0, 0.0)):
     rz = np.zeros(Lz, dtype=np.int64)
     okz = np.zeros(Lz, dtype=bool)
     for m in range(-(nz - 1), nz):
+        if band is not None and abs(m) > band:
+            continue
         rz[m % Lz] = m
         okz[m % Lz] = True
     okx, oky = ~np.isnan(ux), ~np.isnan(vy)
@@ -89,22 +92,23 @@ TERMS = (
 )
 
 
-def green_spectra(shape, L, h, geom, kind, offset=(0.0, 0.0)):
+def green_spectra(shape, L, h, geom, kind, offset=(0.0, 0.0), band=None):
     """The four mixed-direction transforms of the Green arrays (the stored, reused spectra)."""
     out = []
     for sign, xc, yc, gdir, fdir in TERMS:
-        xi = green_array(shape, L, h, geom, kind, xc, yc, offset)
+        xi = green_array(shape, L, h, geom, kind, xc, yc, offset, band)
         out.append(_F3(xi.astype(np.complex128), gdir))
     return out
 
 
-def solve(rho, hx, hy, hz, a, b, mx, my, kind, L=None, spectra=None, return_imag=False, x0=0.0, y0=0.0):
+def solve(rho, hx, hy, hz, a, b, mx, my, kind, L=None, spectra=None, return_imag=False, x0=0.0, y0=0.0,
+          band=None):
     """Eq. 10: phi on the physical nodes for rho of shape (nx, ny, nz), FP64.
 
     L = (Lx, Ly, Lz) defaults to (2nx, 2ny, 2nz); any L >= 2n - 1 per axis is
     valid (Appendix, Eq. A.3 and the remark on N >= M).  (x0, y0) offsets the
     mesh inside the pipe (node i at x0 + (i+1) hx); only the correlation
-    slots see it.
+    slots see it.  band = N keeps only z distances |k - k'| <= N (Eq. 18).
     """
     rho = np.asarray(rho, dtype=np.float64)
     nx, ny, nz = rho.shape
@@ -114,7 +118,7 @@ def solve(rho, hx, hy, hz, a, b, mx, my, kind, L=None, spectra=None, return_imag
     if Lx < 2 * nx - 1 or Ly < 2 * ny - 1 or Lz < 2 * nz - 1:
         raise ValueError("padded length must be at least 2n-1 in every dimension")
     if spectra is None:
-        spectra = green_spectra(rho.shape, L, (hx, hy, hz), (a, b, mx, my), kind, (x0, y0))
+        spectra = green_spectra(rho.shape, L, (hx, hy, hz), (a, b, mx, my), kind, (x0, y0), band)
     pad = np.zeros((Lx, Ly, Lz), dtype=np.complex128)
     pad[:nx, :ny, :nz] = rho
     rho_hat = _F3(pad, 'fff')

@@ -398,3 +398,27 @@ def test_offset_mesh_centred_is_mirror_symmetric(kind):
     base = A(rho)
     assert rel_l2(A(rho[::-1].copy()), base[::-1]) <= 1e-13
     assert rel_l2(A(rho[:, ::-1].copy()), base[:, ::-1]) <= 1e-13
+
+
+# ---------------------------------------------------------------- neighbouring-plane sums (Eq. 17-18)
+
+@pytest.mark.parametrize("kind", [POINT, IGF])
+def test_band_limits_of_the_z_sum(kind):
+    """band = nz - 1 is the full sum; band = 0 decouples the planes (Eq. 17): each
+    plane is its own one-plane problem; Eq. 10 with the banded Green array equals
+    the banded direct sum."""
+    nx, ny, nz = 5, 4, 6
+    a, b = 1.0, 1.2
+    hx, hy, hz = 0.9 * a / (nx + 1), b / (ny + 1), 0.1
+    rng = np.random.default_rng(71)
+    rho = rng.standard_normal((nx, ny, nz))
+    full = direct.solve(rho, hx, hy, hz, a, b, 9, 8, kind)
+    assert rel_l2(direct.solve(rho, hx, hy, hz, a, b, 9, 8, kind, band=nz - 1), full) <= 1e-15
+    b0 = direct.solve(rho, hx, hy, hz, a, b, 9, 8, kind, band=0)
+    planes = np.stack([fourterm.solve(rho[:, :, k:k + 1], hx, hy, hz, a, b, 9, 8, kind)[:, :, 0]
+                       for k in range(nz)], axis=2)
+    assert rel_l2(b0, planes) <= 1e-13
+    for band in (0, 1, 2):
+        d = direct.solve(rho, hx, hy, hz, a, b, 9, 8, kind, band=band)
+        f = fourterm.solve(rho, hx, hy, hz, a, b, 9, 8, kind, band=band)
+        assert rel_l2(f, d) <= 1e-13
