@@ -89,6 +89,8 @@ typedef struct pipe_plan_info {
     double build_ms;         /* wall time of the plan build (Green evaluation + spectra)    */
     double tune_ms;          /* PIPE_AUTOTUNE: the chosen lengths' measured ms per solve  */
                              /* (0 = taken from the cache; -1 = not tuned)                */
+    int band;                /* pipe_green_plan_banded: planes kept each side (N of Eq. 18);*/
+                             /* -1 for the full 3-D plans                                 */
 } pipe_plan_info_t;
 
 /*
@@ -140,6 +142,30 @@ pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, d
 pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double hy, double hz,
                                      double a, double b, double x0, double y0, int kind, int mx, int my,
                                      int lx, int ly, int lz, void* hip_stream, pipe_plan_t* out);
+
+/*
+ * pipe_green_plan_banded -- a plan that keeps only the z distances |k - k'| <= N
+ * of the sum (Eq. 18; N = 0 is the set of independent 2-D problems of Eq. 17),
+ * for long bunches whose Green function falls off within a few planes (Sec. 4,
+ * end).  The z transform disappears: each plane is transformed in x and y
+ * only (padded lengths lx, ly as in pipe_green_plan_ex; lz is reported as 0),
+ * each output plane sums 2N + 1 transverse spectral products, and the plan
+ * holds N + 1 two-dimensional Green spectra.  Solving is otherwise the same
+ * call (pipe_poisson_solve / pipe_poisson_adjoint with info.workspace_bytes
+ * of workspace); phi then equals the full solve with R set to zero beyond N
+ * planes.  nband >= 0 sets N (values above nz - 1 are reduced to nz - 1, which
+ * gives the full z sum); nband < 0 chooses the smallest N with
+ *   B(d) <= tol * B(0) for every plane distance N < d < nz,
+ * B(d) = sum over the kept modes (m, n) of |the mode's z factor at d hz|
+ * times the Eq. 9 prefactor, an upper bound on |R| over the cross-section at
+ * that distance.  tol must then be in (0, 1).  Other arguments, ownership and
+ * errors as pipe_green_plan_region; PIPE_AUTOTUNE flags are ignored.  Banded
+ * plans cannot join a batch (pipe_batch_create returns INVALID_ARG).
+ */
+pipe_status_t pipe_green_plan_banded(int nx, int ny, int nz, double hx, double hy, double hz,
+                                     double a, double b, double x0, double y0, int kind, int mx, int my,
+                                     int lx, int ly, int nband, double tol, void* hip_stream,
+                                     pipe_plan_t* out);
 
 /* pipe_plan_info -- sizes and constants of a plan.  Errors: INVALID_ARG. */
 pipe_status_t pipe_plan_info(pipe_plan_t plan, pipe_plan_info_t* out);
@@ -216,6 +242,9 @@ pipe_status_t pipe_plan_green_table(pipe_plan_t plan, void* out_device, void* hi
  *   plane 0 = Re T_cc(kx,ky,kz); planes 1,2 = T_cr(kx,ky,kz);
  *   planes 3,4 = T_rc(kx,ky,kz); planes 5,6 = T_rr(kx,ky,kz);
  *   planes 7,8 = T_rr(lx-kx,ky,kz)   (re, im pairs).
+ * For a banded plan (pipe_green_plan_banded) the copy is the plan's own
+ * table: 9 values (same order, T_ab now the 2-D DFT of the slice at plane
+ * distance d) per (ky, d, kx) at ((ky (N+1) + d)(lx/2+1) + kx) 9.
  */
 pipe_status_t pipe_plan_spectra(pipe_plan_t plan, void* out_device, void* hip_stream);
 

@@ -151,8 +151,10 @@ __device__ __forceinline__ int conv_slot(int p, int L, int n) {
 }
 __device__ __forceinline__ int corr_slot(int p, int n) { return p <= 2 * n - 2 ? n + p : -1; }
 
+// zid: the z index is the plane distance itself (lz = nz planes, no mirror
+// slots), for the banded spectra, which are transformed in x and y only.
 __global__ void arrange_kernel(double* xi, const double* __restrict__ rbar, int nx, int ny, int nz, int lx,
-                               int ly, int lz, int xcorr, int ycorr) {
+                               int ly, int lz, int xcorr, int ycorr, int zid) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long total = (long)lx * ly * lz;
     if (i >= total) return;
@@ -161,7 +163,7 @@ __global__ void arrange_kernel(double* xi, const double* __restrict__ rbar, int 
     const int p = (int)(i / ((long)lz * ly));
     const int ip = xcorr ? corr_slot(p, nx) : conv_slot(p, lx, nx);
     const int iq = ycorr ? corr_slot(q, ny) : conv_slot(q, ly, ny);
-    const int is = conv_slot(s, lz, nz);
+    const int is = zid ? s : conv_slot(s, lz, nz);
     double v = 0.0;
     if (ip >= 0 && iq >= 0 && is >= 0) v = rbar[((long)ip * (3 * ny - 1) + iq) * nz + is];
     xi[i] = v;
@@ -264,10 +266,11 @@ hipError_t launch_gemm_f64(const double* A, const double* B, double* C, int M, i
 }
 
 hipError_t launch_arrange(double* xi, const double* rbar, int nx, int ny, int nz, int lx, int ly, int lz, int xcorr,
-                          int ycorr, hipStream_t st) {
+                          int ycorr, hipStream_t st, bool z_identity) {
     const long n = (long)lx * ly * lz;
+    if (z_identity && lz != nz) return hipErrorInvalidValue;
     hipLaunchKernelGGL(arrange_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, xi, rbar, nx, ny, nz, lx, ly,
-                       lz, xcorr, ycorr);
+                       lz, xcorr, ycorr, (int)z_identity);
     return hipGetLastError();
 }
 

@@ -1,0 +1,165 @@
+// pass_common.h -- device helpers shared by the pass kernels (passes.hip, band.hip).
+#pragma once
+#include "fft_engine.h"
+#include "pipe_internal.h"
+
+namespace pipe {
+
+// LDS views ----------------------------------------------------------------
+
+// Column-interleaved: element e of column c at base[e * T] (base = lds + c).
+template <typename C, int T> struct LdsCol {
+    C* base;
+    __device__ __forceinline__ C get(int e) const { return base[e * T]; }
+    __device__ __forceinline__ void set(int e, C v) const { base[e * T] = v; }
+};
+
+// Contiguous line padded by one slot every 16 (breaks power-of-two strides).
+__device__ __forceinline__ int lpad(int e) { return e + (e >> 4); }
+template <typename C> struct LdsLine {
+    C* base;
+    __device__ __forceinline__ C get(int e) const { return base[lpad(e)]; }
+    __device__ __forceinline__ void set(int e, C v) const { base[lpad(e)] = v; }
+};
+
+constexpr int ce_max(int a, int b) { return a > b ? a : b; }
+
+// Launch-shape constants (overridable at build time for tuning sweeps).
+#ifndef PIPE_LDS_CAP
+#define PIPE_LDS_CAP 65536   // LDS bytes a y-pass or fused x-pass block may use
+#endif
+#ifndef PIPE_Z_THREADS
+#define PIPE_Z_THREADS 256   // threads per block of the z passes (lines per block = this / P)
+#endif
+#ifndef PIPE_XPROD_TMAX
+#define PIPE_XPROD_TMAX 8    // widest kz tile of the fused x pass
+#endif
+#ifndef PIPE_STRIDED_TMAX
+#define PIPE_STRIDED_TMAX 32 // widest column tile of the y passes
+#endif
+// lines per block of the z passes: PIPE_Z_THREADS / P, halved until the block's LDS fits PIPE_LDS_CAP
+#ifndef PIPE_TW_LDS
+#define PIPE_TW_LDS 1        // stage twiddle tables in LDS at block start
+#endif
+
+// Every supported FFT length, for the launchers' switch statements.
+#define PIPE_FOR_EACH_N(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+// Column tile of the y passes: PIPE_STRIDED_TMAX columns per row segment,
+// halved until the block's LDS (N x T complex) fits in PIPE_LDS_CAP.
+template <typename real, int N> constexpr int strided_T() {
+    int t = PIPE_STRIDED_TMAX;
+    while (t > 1 && N * t * (int)sizeof(real) * 2 > PIPE_LDS_CAP) t /= 2;
+    return t;
+}
+
+// Copy n twiddles into LDS (no barrier: every use follows a later barrier).
+template <typename C>
+__device__ __forceinline__ const C* stage_twiddles(C* s_tw, const C* __restrict__ tw, int n) {
+#if PIPE_TW_LDS
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s_tw[i] = tw[i];
+    return s_tw;
+#else
+    return tw;
+#endif
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2) in
+// order of their linear id.  xcd_remap turns the linear id p < total into a
+// logical id such that consecutive logical ids run on the same XCD, one after
+// the other: XCD x takes the x-th contiguous share of logical ids.
+#ifndef PIPE_NUM_XCD
+#define PIPE_NUM_XCD 8
+#endif
+__device__ __forceinline__ unsigned xcd_remap(unsigned p, unsigned total) {
+    const unsigned q = total / PIPE_NUM_XCD, r = total % PIPE_NUM_XCD;
+    const unsigned xcd = p % PIPE_NUM_XCD, k = p / PIPE_NUM_XCD;
+    return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+template <typename real, int NH> constexpr int z_lines() {
+    int l = ce_max(1, PIPE_Z_THREADS / (NH / Plan<NH>::E));
+    while (l > 1 && l * (NH + NH / 16 + 1) * 2 * (int)sizeof(real) > PIPE_LDS_CAP) l /= 2;
+    return l;
+}
+
+
+// Spectra table (plan precision), 9 values per orbit (kx <= lx/2, ky <= ly/2, kz):
+//   0: T_cc (real)   1,2: T_cr   3,4: T_rc   5,6: T_rr(kx,ky)   7,8: T_rr(-kx,ky)
+// Symmetries of real Green arrays: T_cc real and even in kx, ky; T_cr even in kx,
+// T_cr(kx,-ky) = conj; T_rc even in ky, T_rc(-kx,ky) = conj; T_rr(-kx,-ky) = conj T_rr(kx,ky).
+template <typename real> struct Orbit {
+    real cc;
+    cplx<real> cr, rc, rr, rr2;
+};
+
+// Nine values of one orbit, `stride` apart (T in the tiled table, 1 for kz = lz/2).
+template <typename real>
+__device__ __forceinline__ Orbit<real> load_orbit(const real* __restrict__ e, int stride) {
+    using C = cplx<real>;
+    Orbit<real> o;
+    o.cc = e[0];
+    o.cr = cmake<C>(e[stride], e[2 * stride]);
+    o.rc = cmake<C>(e[3 * stride], e[4 * stride]);
+    o.rr = cmake<C>(e[5 * stride], e[6 * stride]);
+    o.rr2 = cmake<C>(e[7 * stride], e[8 * stride]);
+    return o;
+}
+
+// T_ab at (sx kx, sy ky) from the orbit entry (sx, sy = +1 or -1).
+template <typename real> struct OrbitView {
+    const Orbit<real>& o;
+    __device__ __forceinline__ cplx<real> cc(int, int) const { return cmake<cplx<real>>(o.cc, (real)0); }
+    __device__ __forceinline__ cplx<real> cr(int, int sy) const { return sy > 0 ? o.cr : cconj(o.cr); }
+    __device__ __forceinline__ cplx<real> rc(int sx, int) const { return sx > 0 ? o.rc : cconj(o.rc); }
+    __device__ __forceinline__ cplx<real> rr(int sx, int sy) const {
+        if (sx > 0 && sy > 0) return o.rr;
+        if (sx < 0 && sy < 0) return cconj(o.rr);
+        if (sx < 0) return o.rr2;            // (-kx, ky)
+        return cconj(o.rr2);                 // (kx, -ky)
+    }
+};
+
+// r[q] = rho at point q of the orbit: q = 0 (kx,ky), 1 (-kx,ky), 2 (kx,-ky), 3 (-kx,-ky).
+// Forward: Phi(p) = sum_ab sigma_ab T_ab(p) rho(S_ab p).
+// Adjoint: Phi(p) = sum_ab sigma_ab conj(T_ab(S_ab p)) g(S_ab p)  (transposed gather).
+template <bool ADJ, typename real>
+__device__ __forceinline__ void orbit_product(const Orbit<real>& o, const cplx<real>* r, cplx<real>* out) {
+    using C = cplx<real>;
+    OrbitView<real> T{o};
+    const int SX[4] = {1, -1, 1, -1}, SY[4] = {1, 1, -1, -1};
+    auto idx = [](int sx, int sy) { return (sx > 0 ? 0 : 1) + (sy > 0 ? 0 : 2); };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int sx = SX[q], sy = SY[q];
+        const int qcr = idx(sx, -sy), qrc = idx(-sx, sy), qrr = idx(-sx, -sy);
+        C tcc, tcr, trc, trr;
+        if constexpr (!ADJ) {
+            tcc = T.cc(sx, sy);
+            tcr = T.cr(sx, sy);
+            trc = T.rc(sx, sy);
+            trr = T.rr(sx, sy);
+        } else {
+            tcc = cconj(T.cc(sx, sy));
+            tcr = cconj(T.cr(sx, -sy));
+            trc = cconj(T.rc(-sx, sy));
+            trr = cconj(T.rr(-sx, -sy));
+        }
+        C acc = cmul(tcc, r[q]);
+        acc = csub(acc, cmul(tcr, r[qcr]));
+        acc = csub(acc, cmul(trc, r[qrc]));
+        acc = cadd(acc, cmul(trr, r[qrr]));
+        out[q] = acc;
+    }
+}
+
+
+// Column-interleaved LDS view with a runtime column stride.
+template <typename C> struct LdsColR {
+    C* base;
+    int stride;
+    __device__ __forceinline__ C get(int e) const { return base[e * stride]; }
+    __device__ __forceinline__ void set(int e, C v) const { base[e * stride] = v; }
+};
+
+}  // namespace pipe

@@ -149,6 +149,7 @@ struct pipe_plan_s {
     void* nyq = nullptr;     // kz = lz/2 values, 9 per orbit (inside the table allocation)
     size_t table_elems = 0, nyq_elems = 0;
     int tile = 0;            // kz tile of the table layout
+    int band = -1;           // banded plan: planes kept each side of the z sum (Eq. 18); -1 = 3-D plan
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
     double tune_ms = -1;     // autotuner: best candidate's time per solve, 0 if cached, -1 if not tuned
@@ -164,6 +165,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t plan_ws_bytes(const pipe_plan_s* p) {
     const size_t cb = 2 * (size_t)p->rb;
+    if (p->band >= 0) return 2 * align256((size_t)p->nx * p->ly * p->nz * cb);   // A and B of the banded passes
     const size_t a1 = (size_t)p->nx * p->ny * p->nh * cb;
     const size_t a2 = (size_t)p->nx * p->ly * p->nh * cb;
     return align256(a1) + align256(a2);
@@ -176,6 +178,15 @@ void plan_pass_bytes(const pipe_plan_s* p, double out[5]) {
     const double a2 = (double)p->nx * p->ly * p->nh * cb;
     const double orbits = (double)(p->lx / 2 + 1) * (p->ly / 2 + 1);
     const double tab = 9.0 * orbits * (p->nh + 1) * rb;   // values read once per solve
+    if (p->band >= 0) {
+        // banded: y forward (real in), x + banded product, y inverse (real out)
+        const double A = (double)p->nx * p->ly * p->nz * cb;
+        out[0] = phys + A;
+        out[1] = 2.0 * A + 9.0 * orbits * (p->band + 1) * rb;
+        out[2] = A + phys;
+        out[3] = out[4] = 0.0;
+        return;
+    }
     out[0] = phys + a1;
     out[1] = a1 + a2;
     out[2] = 2.0 * a2 + tab;
@@ -215,7 +226,7 @@ pipe_status_t validate(int nx, int ny, int nz, double hx, double hy, double hz, 
     pipe_status_t st;
     if ((st = choose(nx, lx, false, "lx")) != PIPE_OK) return st;
     if ((st = choose(ny, ly, false, "ly")) != PIPE_OK) return st;
-    if ((st = choose(nz, lz, true, "lz")) != PIPE_OK) return st;
+    if (lz && (st = choose(nz, lz, true, "lz")) != PIPE_OK) return st;   // lz null: no z transform
     return PIPE_OK;
 }
 
@@ -269,6 +280,71 @@ pipe_status_t build_spectra(pipe_plan_s* p, hipStream_t st, bool keep_green) {
     if (keep_green) {
         HIP_TRY(dev_alloc((void**)&p->green, sizeof(double) * (size_t)px * qy * rz), "allocation (kept Green table)");
         HIP_TRY(hipMemcpyAsync(p->green, rbar, sizeof(double) * (size_t)px * qy * rz, hipMemcpyDeviceToDevice, st),
+                "Green table copy");
+    }
+    HIP_TRY(hipStreamSynchronize(st), "plan build");
+    return PIPE_OK;
+}
+
+// Banded spectra (Eq. 18): the Green table at plane distances 0..N, each
+// slice arranged in x and y and transformed in x and y only.  nband < 0: N
+// from the decay bound B(d) = sum_mn |D_mn(d)| of the mode table (|R| <= B).
+pipe_status_t build_band_spectra(pipe_plan_s* p, hipStream_t st, int nband, double tol, bool keep_green) {
+    const int px = 3 * p->nx - 1, qy = 3 * p->ny - 1;
+    const int lx = p->lx, ly = p->ly, mx = p->mx, my = p->my;
+    const int rfull = nband < 0 ? p->nz : std::min(nband, p->nz - 1) + 1;   // planes of the mode table
+    Scratch s;
+    double *cx, *cy, *d, *u, *rbar, *buf, *cbuf;
+    HIP_TRY(s.get((void**)&cx, sizeof(double) * px * mx), "allocation (cos table)");
+    HIP_TRY(s.get((void**)&cy, sizeof(double) * qy * my), "allocation (cos table)");
+    HIP_TRY(s.get((void**)&d, sizeof(double) * (size_t)mx * my * rfull), "allocation (mode table)");
+    const double norm = 1.0 / (2.0 * M_PI * p->a * p->b);
+    HIP_TRY(launch_cos_table(cx, p->nx, 2 * p->nx - 1, mx, p->hx / p->a, 2.0 * p->x0 / p->a, st), "cos table");
+    HIP_TRY(launch_cos_table(cy, p->ny, 2 * p->ny - 1, my, p->hy / p->b, 2.0 * p->y0 / p->b, st), "cos table");
+    HIP_TRY(launch_modes(d, mx, my, rfull, p->a, p->b, p->hz, (p->kind & 0x0f) == PIPE_GREEN_IGF_Z, norm, st),
+            "mode table");
+    int nb = rfull - 1;
+    if (nband < 0) {
+        std::vector<double> h((size_t)mx * my * rfull);
+        HIP_TRY(hipMemcpyAsync(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost, st), "mode table copy");
+        HIP_TRY(hipStreamSynchronize(st), "mode table copy");
+        std::vector<double> B(rfull, 0.0);
+        for (size_t i = 0; i < h.size(); ++i) B[i % rfull] += std::fabs(h[i]);
+        // smallest N with B(d) <= tol B(0) for every N < d < nz
+        while (nb > 0 && B[nb] <= tol * B[0]) --nb;
+    }
+    p->band = nb;
+    const int D = nb + 1;
+    const size_t orbits = (size_t)(lx / 2 + 1) * (ly / 2 + 1);
+    p->table_elems = 9 * orbits * D;
+    p->nyq_elems = 0;
+    HIP_TRY(dev_alloc(&p->table, p->table_elems * p->rb), "allocation (Green spectra)");
+    p->nyq = nullptr;
+    HIP_TRY(hipMemsetAsync(p->table, 0, p->table_elems * p->rb, st), "spectra clear");
+    HIP_TRY(s.get((void**)&u, sizeof(double) * (size_t)mx * qy * D), "allocation (partial sums)");
+    HIP_TRY(s.get((void**)&rbar, sizeof(double) * (size_t)px * qy * D), "allocation (Green table)");
+    HIP_TRY(s.get((void**)&buf, sizeof(double) * (size_t)lx * ly * D), "allocation (spectrum buffer)");
+    HIP_TRY(s.get((void**)&cbuf, 2 * sizeof(double) * (size_t)lx * ly * D), "allocation (spectrum buffer)");
+    // U[m] (qy x D) = Cy (qy x my) * D[m] (my x D, rows rfull apart)
+    HIP_TRY(launch_gemm_f64(cy, d, u, qy, D, my, my, rfull, D, 0, (long)my * rfull, (long)qy * D, mx, st),
+            "mode contraction (y)");
+    // Rbar (px x qy*D) = Cx (px x mx) * U (mx x qy*D)
+    HIP_TRY(launch_gemm_f64(cx, u, rbar, px, qy * D, mx, mx, (long)qy * D, (long)qy * D, 0, 0, 0, 1, st),
+            "mode contraction (x)");
+    for (int term = 0; term < 4; ++term) {
+        const int xcorr = (term == 2 || term == 3), ycorr = (term == 1 || term == 3);
+        HIP_TRY(launch_arrange(buf, rbar, p->nx, p->ny, D, lx, ly, D, xcorr, ycorr, st, true), "Green arrangement");
+        HIP_TRY(launch_strided_real<double>(ly, false, buf, cbuf, ly, ly, D, D, D, (long)ly * D, (long)ly * D, lx, 1.0,
+                                            p->ctx->tw, st),
+                "spectra y transform");
+        HIP_TRY(launch_strided<double>(lx, false, cbuf, cbuf, lx, lx, (long)ly * D, (long)ly * D, (long)ly * D, 0, 0, 1,
+                                       p->ctx->tw, st),
+                "spectra x transform");
+        HIP_TRY(launch_compress_band(cbuf, p->table, p->rb, term, lx, ly, D, st), "spectra compression");
+    }
+    if (keep_green) {
+        HIP_TRY(dev_alloc((void**)&p->green, sizeof(double) * (size_t)px * qy * D), "allocation (kept Green table)");
+        HIP_TRY(hipMemcpyAsync(p->green, rbar, sizeof(double) * (size_t)px * qy * D, hipMemcpyDeviceToDevice, st),
                 "Green table copy");
     }
     HIP_TRY(hipStreamSynchronize(st), "plan build");
@@ -332,6 +408,33 @@ pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, h
     return PIPE_OK;
 }
 
+// Banded solve (Eq. 18): three kernels; the timing events of the two absent
+// passes are recorded back to back.
+template <typename real>
+pipe_status_t run_band_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, hipStream_t st, bool adjoint,
+                              hipEvent_t* ev) {
+    const size_t cb = 2 * sizeof(real);
+    char* A = (char*)ws;
+    char* B = A + align256((size_t)p->nx * p->ly * p->nz * cb);
+    const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly;
+    const TwiddleBank& tw = p->ctx->tw;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event");
+    HIP_TRY(launch_strided_real<real>(ly, false, rho, A, ny, ly, nz, nz, nz, (long)ny * nz, (long)ly * nz, nx, (real)1,
+                                      tw, st),
+            "y forward pass");
+    if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
+    HIP_TRY(launch_xband<real>(p->lx, adjoint, A, B, nx, ly, nz, p->band, (const real*)p->table, tw, st),
+            "x pass with banded product");
+    if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
+    const real scale = (real)(p->hx * p->hy * p->hz / ((double)p->lx * p->ly));
+    HIP_TRY(launch_strided_real<real>(ly, true, B, phi, ly, ny, nz, nz, nz, (long)ly * nz, (long)ny * nz, nx, scale,
+                                      tw, st),
+            "y inverse pass");
+    if (ev)
+        for (int i = 3; i < 6; ++i) HIP_TRY(hipEventRecord(ev[i], st), "event");
+    return PIPE_OK;
+}
+
 pipe_status_t solve_impl(pipe_plan_t plan, const void* rho, void* phi, void* ws, void* stream, bool adjoint,
                          hipEvent_t* ev) {
     pipe_status_t s = check_solve_args(plan, rho, phi, ws);
@@ -341,8 +444,12 @@ pipe_status_t solve_impl(pipe_plan_t plan, const void* rho, void* phi, void* ws,
     if (cur != plan->device) HIP_TRY(hipSetDevice(plan->device), "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
     if (!ev && plan->tn < plan->tmax) ev = &plan->tev[6 * (size_t)plan->tn++];
-    s = plan->rb == 8 ? run_passes<double>(plan, rho, phi, ws, st, adjoint, ev)
-                      : run_passes<float>(plan, rho, phi, ws, st, adjoint, ev);
+    if (plan->band >= 0)
+        s = plan->rb == 8 ? run_band_passes<double>(plan, rho, phi, ws, st, adjoint, ev)
+                          : run_band_passes<float>(plan, rho, phi, ws, st, adjoint, ev);
+    else
+        s = plan->rb == 8 ? run_passes<double>(plan, rho, phi, ws, st, adjoint, ev)
+                          : run_passes<float>(plan, rho, phi, ws, st, adjoint, ev);
     if (cur != plan->device) (void)hipSetDevice(cur);
     return s;
 }
@@ -621,6 +728,45 @@ pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, d
     return pipe_green_plan_region(nx, ny, nz, hx, hy, hz, a, b, 0.0, 0.0, kind, mx, my, lx, ly, lz, hip_stream, out);
 }
 
+pipe_status_t pipe_green_plan_banded(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b,
+                                     double x0, double y0, int kind, int mx, int my, int lx, int ly, int nband,
+                                     double tol, void* hip_stream, pipe_plan_t* out) {
+    if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
+    *out = nullptr;
+    const bool keep = (kind & PIPE_KEEP_GREEN) != 0;
+    kind &= 0xff;
+    pipe_status_t s = validate(nx, ny, nz, hx, hy, hz, a, b, x0, y0, kind, mx, my, &lx, &ly, nullptr);
+    if (s != PIPE_OK) return s;
+    if (nband < 0 && !(tol > 0.0 && tol < 1.0))
+        return fail(PIPE_ERR_INVALID_ARG, "automatic band selection needs 0 < tol < 1 (got %g)", tol);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return fail(PIPE_ERR_NO_DEVICE, "no HIP device available");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    DeviceCtx* ctx = nullptr;
+    if ((s = device_ctx(dev, &ctx)) != PIPE_OK) return s;
+    auto t0 = std::chrono::steady_clock::now();
+    pipe_plan_s* p = new pipe_plan_s();
+    p->nx = nx; p->ny = ny; p->nz = nz; p->lx = lx; p->ly = ly; p->lz = 0; p->nh = 0;
+    p->mx = mx; p->my = my; p->kind = kind; p->rb = (kind & PIPE_PREC_FP32) ? 4 : 8;
+    p->hx = hx; p->hy = hy; p->hz = hz; p->a = a; p->b = b;
+    p->x0 = x0; p->y0 = y0;
+    p->device = dev; p->ctx = ctx;
+    p->tile = band_tile(lx, p->rb);
+    s = build_band_spectra(p, (hipStream_t)hip_stream, nband, tol, keep);
+    if (s != PIPE_OK) {
+        plan_free(p);
+        return s;
+    }
+    p->ws_bytes = plan_ws_bytes(p);
+    p->tune_ms = -1.0;
+    p->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    reg_add(p);
+    *out = p;
+    return PIPE_OK;
+}
+
 pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b, int kind,
                               pipe_plan_t* out) {
     return pipe_green_plan_ex(nx, ny, nz, hx, hy, hz, a, b, kind, 2 * nx, 2 * ny, 0, 0, 0, nullptr, out);
@@ -643,6 +789,7 @@ pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     for (double v : out->pass_bytes) out->model_bytes += v;
     out->build_ms = p->build_ms;
     out->tune_ms = p->tune_ms;
+    out->band = p->band;
     return PIPE_OK;
 }
 
@@ -720,7 +867,7 @@ pipe_status_t pipe_plan_green_table(pipe_plan_t p, void* out, void* stream) {
     if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
     if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
     if (!p->green) return fail(PIPE_ERR_INVALID_ARG, "plan was built without keeping its Green table");
-    const size_t n = (size_t)(3 * p->nx - 1) * (3 * p->ny - 1) * p->nz;
+    const size_t n = (size_t)(3 * p->nx - 1) * (3 * p->ny - 1) * (p->band >= 0 ? p->band + 1 : p->nz);
     HIP_TRY(hipMemcpyAsync(out, p->green, n * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream), "copy");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "copy");
     return PIPE_OK;
@@ -730,7 +877,10 @@ pipe_status_t pipe_plan_spectra(pipe_plan_t p, void* out, void* stream) {
     if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
     if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
     hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(launch_untile(p->table, p->nyq, out, p->rb, p->lx, p->ly, p->nh, p->tile, st), "spectra copy");
+    if (p->band >= 0)
+        HIP_TRY(hipMemcpyAsync(out, p->table, p->table_elems * p->rb, hipMemcpyDeviceToDevice, st), "spectra copy");
+    else
+        HIP_TRY(launch_untile(p->table, p->nyq, out, p->rb, p->lx, p->ly, p->nh, p->tile, st), "spectra copy");
     HIP_TRY(hipStreamSynchronize(st), "spectra copy");
     return PIPE_OK;
 }
@@ -841,6 +991,8 @@ pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_
     if (!plans || count < 1) return fail(PIPE_ERR_INVALID_ARG, "need at least one plan");
     for (int i = 0; i < count; ++i)
         if (!reg_has(plans[i])) return fail(PIPE_ERR_INVALID_ARG, "plan %d is not a live plan", i);
+    for (int i = 0; i < count; ++i)
+        if (plans[i]->band >= 0) return fail(PIPE_ERR_INVALID_ARG, "plan %d is banded; batches take 3-D plans", i);
     for (int i = 1; i < count; ++i)
         if (plans[i]->rb != plans[0]->rb || plans[i]->device != plans[0]->device)
             return fail(PIPE_ERR_INVALID_ARG, "batch members must share precision and device");

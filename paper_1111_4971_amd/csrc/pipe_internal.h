@@ -72,11 +72,32 @@ hipError_t launch_modes(double* d, int mx, int my, int rz, double a, double b, d
 hipError_t launch_gemm_f64(const double* A, const double* B, double* C, int M, int N, int K,
                            long lda, long ldb, long ldc, long sA, long sB, long sC, int batch,
                            hipStream_t st);
+// Green arrangement of one term (Appendix A.3 / A.9 slots) into xi[lx][ly][lz];
+// z_identity (lz == nz): slot s holds plane distance s (banded spectra).
 hipError_t launch_arrange(double* xi, const double* rbar, int nx, int ny, int nz, int lx, int ly,
-                          int lz, int xcorr, int ycorr, hipStream_t st);
+                          int lz, int xcorr, int ycorr, hipStream_t st, bool z_identity = false);
 hipError_t launch_compress(const void* spec, void* table, void* nyq, int real_bytes, int term,
                            int lx, int ly, int nh, int tile, hipStream_t st);
 hipError_t launch_untile(const void* table, const void* nyq, void* out, int real_bytes, int lx, int ly, int nh,
                          int tile, hipStream_t st);
+
+// Neighbouring-plane (banded z) path (band.hip).
+// y pass with real input (forward) or real output (inverse, times scale);
+// arguments as launch_strided.
+template <typename real>
+hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, int n_in, int n_out, long in_es,
+                               long out_es, long ncols, long in_ss, long out_ss, long nslabs, real scale,
+                               const TwiddleBank& tw, hipStream_t s);
+// x forward, sum over plane distances |d| <= nb of the orbit products, x
+// inverse: in, out (nx, ly, nz) complex (distinct buffers); table banded
+// ((ly/2+1) (nb+1) (lx/2+1) 9 values).
+template <typename real>
+hipError_t launch_xband(int lx, bool adjoint, const void* in, void* out, int nx, int ly, int nz, int nb,
+                        const real* table, const TwiddleBank& tw, hipStream_t s);
+// Output planes per block of the banded x pass (0 if lx unsupported).
+int band_tile(int lx, int real_bytes);
+// Banded orbit table from the 2-D spectra S[lx][ly][D] (FP64 complex) of one term.
+hipError_t launch_compress_band(const void* spec, void* table, int real_bytes, int term, int lx, int ly, int D,
+                                hipStream_t st);
 
 }  // namespace pipe

@@ -46,7 +46,7 @@ class PlanInfo(ctypes.Structure):
                 ("norm", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("spectra_bytes", ctypes.c_size_t),
                 ("model_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double * 5),
-                ("build_ms", ctypes.c_double), ("tune_ms", ctypes.c_double)]
+                ("build_ms", ctypes.c_double), ("tune_ms", ctypes.c_double), ("band", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -73,6 +73,8 @@ def lib():
         "pipe_green_plan_ex": ([_I, _I, _I, _D, _D, _D, _D, _D, _I, _I, _I, _I, _I, _I, _P,
                                 ctypes.POINTER(_P)], _I),
         "pipe_green_plan_region": ([_I, _I, _I, _D, _D, _D, _D, _D, _D, _D, _I, _I, _I, _I, _I, _I, _P,
+                                    ctypes.POINTER(_P)], _I),
+        "pipe_green_plan_banded": ([_I, _I, _I, _D, _D, _D, _D, _D, _D, _D, _I, _I, _I, _I, _I, _I, _D, _P,
                                     ctypes.POINTER(_P)], _I),
         "pipe_plan_info": ([_P, ctypes.POINTER(PlanInfo)], _I),
         "pipe_poisson_solve": ([_P, _P, _P, _P, _P], _I),
@@ -134,18 +136,30 @@ class GreenPlan:
     lengths >= 2n.  autotune: False, True (time single solves) or "batch"
     (time 16 concurrent solves) to pick the padded lengths.  offset = (x0, y0)
     places the mesh on a sub-region of the cross-section (node i at
-    x0 + (i+1) hx).
+    x0 + (i+1) hx).  band = N keeps only plane distances |k - k'| <= N
+    (pipe_green_plan_banded, Eq. 18); band = "auto" picks N from the decay
+    of the mode sum with tolerance band_tol.  L is then (lx, ly).
     """
 
     def __init__(self, nx, ny, nz, hx, hy, hz, a, b, kind=IGF_Z, precision="fp64", mx=None, my=None,
-                 L=None, keep_green=False, autotune=False, stream=None, offset=(0.0, 0.0)):
+                 L=None, keep_green=False, autotune=False, stream=None, offset=(0.0, 0.0), band=None,
+                 band_tol=1e-6):
         flags = int(kind) | (PREC_FP32 if precision == "fp32" else PREC_FP64) | (KEEP_GREEN if keep_green else 0)
-        flags |= {False: 0, True: AUTOTUNE, "batch": AUTOTUNE_BATCH}[autotune]
-        lx, ly, lz = L if L is not None else (0, 0, 0)
         h = _P()
         st = _stream_ptr(stream) if stream is not None else None
-        check(lib().pipe_green_plan_region(nx, ny, nz, hx, hy, hz, a, b, float(offset[0]), float(offset[1]), flags,
-                                           mx or 2 * nx, my or 2 * ny, lx, ly, lz, st, ctypes.byref(h)))
+        if band is not None:
+            lx, ly = L[:2] if L is not None else (0, 0)
+            nb = -1 if band == "auto" else int(band)
+            if nb < 0 and band != "auto":
+                raise ValueError("band must be >= 0 or 'auto'")
+            check(lib().pipe_green_plan_banded(nx, ny, nz, hx, hy, hz, a, b, float(offset[0]), float(offset[1]),
+                                               flags, mx or 2 * nx, my or 2 * ny, lx, ly, nb, float(band_tol), st,
+                                               ctypes.byref(h)))
+        else:
+            flags |= {False: 0, True: AUTOTUNE, "batch": AUTOTUNE_BATCH}[autotune]
+            lx, ly, lz = L if L is not None else (0, 0, 0)
+            check(lib().pipe_green_plan_region(nx, ny, nz, hx, hy, hz, a, b, float(offset[0]), float(offset[1]),
+                                               flags, mx or 2 * nx, my or 2 * ny, lx, ly, lz, st, ctypes.byref(h)))
         self._h = h
         info = PlanInfo()
         check(lib().pipe_plan_info(h, ctypes.byref(info)))
@@ -153,6 +167,11 @@ class GreenPlan:
         self.shape = (nx, ny, nz)
         self.dtype = _dtype(info.real_bytes)
         self._ws = None
+
+    @property
+    def band(self):
+        """Planes kept on each side of the z sum (banded plans), else None."""
+        return self.info.band if self.info.band >= 0 else None
 
     @property
     def handle(self):
@@ -217,18 +236,25 @@ class GreenPlan:
         return list(ms), n.value
 
     def green_table(self):
-        """R at [differences p hx (p < nx), sums 2 x0 + (p + 2) hx (p <= 2nx - 2)] x [same in y] x [r hz]."""
+        """R at [differences p hx (p < nx), sums 2 x0 + (p + 2) hx (p <= 2nx - 2)] x [same in y] x [r hz]
+        (r < nz; r <= N for a banded plan)."""
         torch = _torch()
         nx, ny, nz = self.shape
-        out = torch.empty((3 * nx - 1, 3 * ny - 1, nz), dtype=torch.float64, device="cuda")
+        nr = self.band + 1 if self.band is not None else nz
+        out = torch.empty((3 * nx - 1, 3 * ny - 1, nr), dtype=torch.float64, device="cuda")
         check(lib().pipe_plan_green_table(self.handle, _P(out.data_ptr()), _stream_ptr()))
         return out
 
     def spectra(self):
-        """(table, nyquist) as tensors of shape (9, lx/2+1, ly/2+1, lz/2) and (9, lx/2+1, ly/2+1)."""
+        """(table, nyquist) as tensors of shape (9, lx/2+1, ly/2+1, lz/2) and (9, lx/2+1, ly/2+1);
+        for a banded plan the one table of shape (ly/2+1, N+1, lx/2+1, 9)."""
         torch = _torch()
         i = self.info
         kx, ky, nh = i.lx // 2 + 1, i.ly // 2 + 1, i.lz // 2
+        if self.band is not None:
+            out = torch.empty((ky, self.band + 1, kx, 9), dtype=self.dtype, device="cuda")
+            check(lib().pipe_plan_spectra(self.handle, _P(out.data_ptr()), _stream_ptr()))
+            return out
         flat = torch.empty(9 * kx * ky * (nh + 1), dtype=self.dtype, device="cuda")
         check(lib().pipe_plan_spectra(self.handle, _P(flat.data_ptr()), _stream_ptr()))
         n1 = 9 * kx * ky * nh

@@ -129,3 +129,30 @@ def test_region_offsets_are_validated(x0, y0):
     st = L.pipe_green_plan_region(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, x0, y0, 0, 8, 8, 0, 0, 0, None,
                                   ctypes.byref(h))
     assert st == 1 and not h.value, pipe.lib().pipe_last_error().decode()
+
+
+@needs_lib
+@pytest.mark.parametrize("nband,tol,expect", [(-1, 0.0, 1), (-1, 1.0, 1), (-1, float("nan"), 1), (2, 0.0, 4),
+                                              (-1, 1e-6, 4)])
+def test_banded_plan_validation(nband, tol, expect):
+    """Automatic band selection needs 0 < tol < 1; a fixed N ignores tol.  Valid
+    arguments then fail only for lack of a device."""
+    if expect == 4 and _has_device():
+        pytest.skip("would build a plan on the device")
+    L = pipe.lib()
+    h = ctypes.c_void_p()
+    st = L.pipe_green_plan_banded(4, 4, 4000, 0.1, 0.1, 0.1, 1.0, 1.0, 0.0, 0.0, 0, 8, 8, 0, 0, nband, tol, None,
+                                  ctypes.byref(h))
+    assert st == expect and not h.value, L.pipe_last_error().decode()
+
+
+@needs_lib
+def test_banded_plan_rejects_bad_geometry():
+    L = pipe.lib()
+    h = ctypes.c_void_p()
+    st = L.pipe_green_plan_banded(4, 4, 4, 0.3, 0.1, 0.1, 1.0, 1.0, 0.0, 0.0, 0, 8, 8, 0, 0, 1, 0.0, None,
+                                  ctypes.byref(h))
+    assert st == 1 and not h.value
+    st = L.pipe_green_plan_banded(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0.0, 0.0, 0, 8, 8, 10, 0, 1, 0.0, None,
+                                  ctypes.byref(h))
+    assert st == 2 and not h.value

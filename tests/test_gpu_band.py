@@ -1,0 +1,199 @@
+"""Neighbouring-plane z sums (pipe_green_plan_banded, Eq. 17-18).
+
+A banded plan keeps only the plane distances |k - k'| <= N of the z sum.
+Checked against the oracle's Eq. 10 with the Green array cut the same way,
+against the ordinary 3-D plan when N covers the whole mesh, through its
+adjoint, its Green spectra and table, and through the automatic choice of N,
+whose truncation error has a rigorous bound from the mode sum.
+"""
+import numpy as np
+import pytest
+
+from helpers import TOL, gpu_solve, log, oracle_input, rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+
+A, B = 1.3, 1.1
+H = (0.07, 0.06, 0.05)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _plan(shape, prec, kind, band, **kw):
+    from paper_1111_4971_amd import pipe
+    nx, ny, nz = shape
+    return pipe.GreenPlan(nx, ny, nz, *H, A, B, kind=kind, precision=prec, mx=2 * nx + 3, my=2 * ny + 1,
+                          band=band, **kw)
+
+
+# (shape, N, offset): nz spans several 16-plane tiles with a ragged tail; N = 20
+# needs four chunks of input planes per tile; N = nz - 1 is the full z sum.
+CASES = [((6, 5, 12), 0, (0.0, 0.0)), ((9, 7, 20), 1, (0.0, 0.0)), ((13, 10, 33), 3, (0.2, 0.1)),
+         ((6, 5, 40), 20, (0.0, 0.0)), ((5, 6, 9), 8, (0.0, 0.0))]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape,nb,offset", CASES)
+def test_band_matches_eq18_oracle(torch_cuda, kind, prec, shape, nb, offset):
+    from oracle import fourterm
+    nx, ny, nz = shape
+    rho = np.random.default_rng(nx * 11 + nz).standard_normal(shape)
+    log("band %s kind=%d shape=%s N=%d offset=%s" % (prec, kind, shape, nb, offset))
+    plan = _plan(shape, prec, kind, nb, offset=offset)
+    assert plan.band == nb and plan.info.lz == 0
+    got = gpu_solve(plan, rho)
+    ref = fourterm.solve(oracle_input(rho, prec), *H, A, B, 2 * nx + 3, 2 * ny + 1, kind, x0=offset[0],
+                         y0=offset[1], band=nb)
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec]
+
+
+def test_band_cut_changes_the_result(torch_cuda):
+    """The cut is real: N = 1 differs from N = 2 by far more than rounding."""
+    shape = (7, 6, 16)
+    rho = np.random.default_rng(3).standard_normal(shape)
+    log("band N=1 vs N=2")
+    p1, p2 = _plan(shape, "fp64", 1, 1), _plan(shape, "fp64", 1, 2)
+    assert rel_l2(gpu_solve(p1, rho), gpu_solve(p2, rho)) > 1e-6
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_full_band_equals_3d_plan(torch_cuda, kind):
+    """N >= nz - 1 keeps every plane: the same potential as the z-transformed plan
+    (N above nz - 1 is reduced to nz - 1)."""
+    from paper_1111_4971_amd import pipe
+    shape = (10, 9, 24)
+    nx, ny, nz = shape
+    rho = np.random.default_rng(17).standard_normal(shape)
+    log("full band vs 3-D plan kind=%d" % kind)
+    full = pipe.GreenPlan(nx, ny, nz, *H, A, B, kind=kind, precision="fp64", mx=2 * nx + 3, my=2 * ny + 1)
+    ref = gpu_solve(full, rho)
+    for nb in (nz - 1, 1000):
+        plan = _plan(shape, "fp64", kind, nb)
+        assert plan.band == nz - 1
+        got = gpu_solve(plan, rho)
+        assert rel_l2(got, ref) <= 1e-12 and rel_max(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_band_adjoint(torch_cuda, prec):
+    """<A x, y> = <x, A^T y>, and A^T x equals the oracle's A x (A is symmetric)."""
+    torch = torch_cuda
+    from oracle import fourterm
+    shape = (11, 8, 37)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(23)
+    x, y = rng.standard_normal(shape), rng.standard_normal(shape)
+    log("band adjoint %s" % prec)
+    plan = _plan(shape, prec, 1, 2)
+    dt = plan.dtype
+    xt, yt = torch.tensor(x, device="cuda", dtype=dt), torch.tensor(y, device="cuda", dtype=dt)
+    ax = plan.solve(xt).double()
+    aty = plan.adjoint(yt).double()
+    lhs = float((ax * yt.double()).sum())
+    rhs = float((xt.double() * aty).sum())
+    assert abs(lhs - rhs) <= 10 * TOL[prec] * float(ax.norm() * yt.double().norm())
+    ref = fourterm.solve(oracle_input(y, prec), *H, A, B, 2 * nx + 3, 2 * ny + 1, 1, band=2)
+    got = aty.cpu().numpy()
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec]
+
+
+def test_band_spectra_and_table(torch_cuda):
+    """The plan's N + 1 two-dimensional spectra are the 2-D DFTs of the four terms'
+    arrangements of the Green slices at plane distances 0..N (Appendix A.3, A.9),
+    and its kept Green table is R at those distances."""
+    from oracle import fourterm, green
+    shape = (7, 6, 10)
+    nx, ny, nz = shape
+    nb, offset = 3, (0.15, 0.05)
+    mx, my = 2 * nx + 3, 2 * ny + 1
+    log("band spectra")
+    plan = _plan(shape, "fp64", 1, nb, offset=offset, keep_green=True)
+    lx, ly = plan.info.lx, plan.info.ly
+    got = plan.spectra().cpu().numpy()            # (ly/2+1, N+1, lx/2+1, 9)
+    assert got.shape == (ly // 2 + 1, nb + 1, lx // 2 + 1, 9)
+    L3 = (lx, ly, 2 * nz)
+    S = {}
+    for name, xc, yc in (("cc", False, False), ("cr", False, True), ("rc", True, False), ("rr", True, True)):
+        xi = fourterm.green_array(shape, L3, H, (A, B, mx, my), 1, xc, yc, offset)
+        S[name] = np.fft.fft2(xi[:, :, :nb + 1], axes=(0, 1))     # (lx, ly, N+1)
+    kx = np.arange(lx // 2 + 1)
+    ky = np.arange(ly // 2 + 1)
+    sel = lambda a, kxs: a[np.ix_(kxs, ky)].transpose(1, 2, 0)    # -> (ky, d, kx)
+    ref = np.stack([sel(S["cc"], kx).real,
+                    sel(S["cr"], kx).real, sel(S["cr"], kx).imag,
+                    sel(S["rc"], kx).real, sel(S["rc"], kx).imag,
+                    sel(S["rr"], kx).real, sel(S["rr"], kx).imag,
+                    sel(S["rr"], (lx - kx) % lx).real, sel(S["rr"], (lx - kx) % lx).imag], axis=-1)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # T_cc of a real, even arrangement is real
+    assert np.max(np.abs(sel(S["cc"], kx).imag)) <= 1e-12 * np.max(np.abs(ref))
+    # kept table: R at the difference and sum distances, planes 0..N
+    x0, y0 = offset
+    u = np.concatenate([np.arange(nx) * H[0], 2 * x0 + (np.arange(2 * nx - 1) + 2) * H[0]])
+    v = np.concatenate([np.arange(ny) * H[1], 2 * y0 + (np.arange(2 * ny - 1) + 2) * H[1]])
+    tab = plan.green_table().cpu().numpy()
+    rt = green.R_table(u, v, np.arange(nb + 1), H[2], A, B, mx, my, 1)
+    assert tab.shape == rt.shape
+    assert np.max(np.abs(tab - rt)) <= 1e-12 * np.max(np.abs(rt))
+
+
+def _auto_band(shape, kind, tol, mx, my, hz, a, b):
+    """Smallest N with B(d) <= tol B(0) for N < d < nz, B(d) = sum_mn |D_mn(d)| (oracle)."""
+    from oracle import green
+    nz = shape[2]
+    D = green.mode_coefficients(np.arange(nz), hz, a, b, mx, my, kind)
+    Bd = np.abs(D).sum(axis=(0, 1))
+    n = nz - 1
+    while n > 0 and Bd[n] <= tol * Bd[0]:
+        n -= 1
+    return n, Bd
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("tol", [1e-3, 1e-8])
+def test_auto_band_and_truncation_bound(torch_cuda, kind, tol):
+    """The automatic N is the oracle's, and the banded potential differs from the
+    full one by at most hx hy hz sum|rho| 4 max_{d > N} B(d): each of the four
+    terms of Eq. 8 is bounded by B(d) at plane distance d."""
+    from paper_1111_4971_amd import pipe
+    shape = (12, 10, 64)
+    nx, ny, nz = shape
+    hz = 0.12
+    mx, my = 2 * nx, 2 * ny
+    hx, hy = 0.9 * A / nx, 0.9 * B / ny
+    rho = np.random.default_rng(41).standard_normal(shape)
+    log("auto band kind=%d tol=%g" % (kind, tol))
+    plan = pipe.GreenPlan(nx, ny, nz, hx, hy, hz, A, B, kind=kind, precision="fp64", mx=mx, my=my,
+                          band="auto", band_tol=tol)
+    n_ref, Bd = _auto_band(shape, kind, tol, mx, my, hz, A, B)
+    assert plan.band == n_ref
+    assert 0 < n_ref < nz - 1
+    full = pipe.GreenPlan(nx, ny, nz, hx, hy, hz, A, B, kind=kind, precision="fp64", mx=mx, my=my)
+    ref = gpu_solve(full, rho)
+    diff = np.max(np.abs(gpu_solve(plan, rho) - ref))
+    bound = hx * hy * hz * np.abs(rho).sum() * 4.0 * Bd[n_ref + 1:].max()
+    assert diff <= bound + 1e-12 * np.max(np.abs(ref))   # plus FP64 rounding of the two solves
+
+
+def test_long_bunch_banded_matches_full(torch_cuda):
+    """The paper's long bunch (sigma_z = 1.2 m, pipe 4 cm, 20 x 20 modes) on
+    64 x 64 x 256: the IGF falls off within a few planes, and the banded solve
+    with the automatic N agrees with the full 3-D solve."""
+    from paper_1111_4971_amd import pipe, workloads
+    wl, _ = workloads.accuracy_study_bunch(64, 256, 120.0, kind=pipe.IGF_Z)
+    log("long bunch banded vs full")
+    full = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind, precision="fp64",
+                          mx=wl.mx, my=wl.my)
+    band = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind, precision="fp64",
+                          mx=wl.mx, my=wl.my, band="auto", band_tol=1e-10)
+    log("long bunch: N = %d" % band.band)
+    assert band.band <= 12
+    ref = gpu_solve(full, wl.rho)
+    got = gpu_solve(band, wl.rho)
+    assert rel_max(got, ref) <= 1e-9
