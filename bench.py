@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0
 PASS_NAMES = ["z_forward", "y_forward", "x_product", "y_inverse", "z_inverse"]
 KERNEL_NAMES = ["z_r2c_kernel", "strided_kernel<fwd>", "xprod_kernel", "strided_kernel<inv>", "z_c2r_kernel"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_three_bunch_cic.json")
-KERNEL_SOURCES = ["paper_1111_4971_amd/csrc/passes.hip", "paper_1111_4971_amd/csrc/fft_engine.h"]
+KERNEL_SOURCES = ["paper_1111_4971_amd/csrc/passes.hip", "paper_1111_4971_amd/csrc/pass_common.h",
+                  "paper_1111_4971_amd/csrc/fft_engine.h"]
 
 
 def log(*a):
@@ -227,6 +228,65 @@ def subregion_leg(pipe, torch, steps=50):
     return res
 
 
+def band_leg(pipe, torch, steps=50, tol=1e-6):
+    """Eq. 17-18 on the paper's long bunch (Sec. 4: pipe 4 cm, 20 x 20 modes,
+    sigma_z = 1.2 m, IGF): banded plans keeping the plane distances up to N
+    (N = 0 is Eq. 17; "auto" is the N chosen from the mode-sum decay bound at
+    tol) timed beside the full 3-D plan of the same mesh, per precision, with
+    their deviation from the full FP64 solve."""
+    import numpy as np
+    from paper_1111_4971_amd import workloads
+
+    def timed(plan, x):
+        y = torch.empty_like(x)
+        ws = plan.workspace()
+        for _ in range(5):
+            plan.solve(x, out=y, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            plan.solve(x, out=y, workspace=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / steps * 1e3
+        plan.timing_start(steps)
+        for _ in range(steps):
+            plan.solve(x, out=y, workspace=ws)
+        pass_ms, _ = plan.timing_stop()
+        return ms, pass_ms, y.double().cpu().numpy()
+
+    res = {"tol": tol}
+    for n, nz, bands in ((128, 256, (0, 1, 2, "auto")), (256, 1024, (0, 1, "auto"))):
+        wl, _ = workloads.accuracy_study_bunch(n, nz, 120.0, kind=pipe.IGF_Z)
+        key = "%dx%dx%d" % (n, n, nz)
+        r = {}
+        ref = None
+        for prec in ("fp64", "fp32"):
+            dt = torch.float32 if prec == "fp32" else torch.float64
+            x = torch.from_numpy(wl.rho).to("cuda", dt)
+            log("[bench] band %s %s: full plan" % (key, prec))
+            plan = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind,
+                                  precision=prec, mx=wl.mx, my=wl.my)
+            ms_full, pm, y = timed(plan, x)
+            plan.close()
+            if ref is None:
+                ref = y
+            r.setdefault("full", {})[prec] = {"ms_per_solve": ms_full, "kernel_ms": pm}
+            for nb in bands:
+                log("[bench] band %s %s: N = %s" % (key, prec, nb))
+                plan = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind,
+                                      precision=prec, mx=wl.mx, my=wl.my, band=nb, band_tol=tol)
+                ms, pm, y = timed(plan, x)
+                pb = plan.info.pass_bytes
+                e = r.setdefault("N_auto" if nb == "auto" else "N%d" % nb, {})
+                e["N"] = plan.band
+                e[prec] = {"ms_per_solve": ms, "kernel_ms": pm[:3], "speedup_over_full": ms_full / ms,
+                           "x_pass_GBps": pb[1] / (pm[1] * 1e-3) / 1e9,
+                           "rel_max_vs_full_fp64": float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))}
+                plan.close()
+        res[key] = r
+    return res
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -330,6 +390,16 @@ def main():
         res["subregion"] = subregion_leg(pipe, torch)
         log("[bench] subregion: %.1fx faster than the full cross-section, max rel diff %.1e" % (
             res["subregion"]["speedup_subregion_over_full"], res["subregion"]["rel_max_diff_on_shared_nodes"]))
+    if not args.no_batch:
+        res["banded"] = band_leg(pipe, torch)
+        for k, v in res["banded"].items():
+            if not isinstance(v, dict):
+                continue
+            for nm, e in v.items():
+                if nm.startswith("N"):
+                    log("[bench] banded %s %s (N=%d): %.2fx (FP32) / %.2fx (FP64) the full solve's speed, "
+                        "max rel deviation %.1e" % (k, nm, e["N"], e["fp32"]["speedup_over_full"],
+                                                    e["fp64"]["speedup_over_full"], e["fp64"]["rel_max_vs_full_fp64"]))
     if not args.no_cpu_baseline:
         cb, ophi = cpu_baseline(wl)
         res["cpu_baseline"] = cb

@@ -243,8 +243,14 @@ pipe_status_t pipe_plan_green_table(pipe_plan_t plan, void* out_device, void* hi
  *   planes 3,4 = T_rc(kx,ky,kz); planes 5,6 = T_rr(kx,ky,kz);
  *   planes 7,8 = T_rr(lx-kx,ky,kz)   (re, im pairs).
  * For a banded plan (pipe_green_plan_banded) the copy is the plan's own
- * table: 9 values (same order, T_ab now the 2-D DFT of the slice at plane
- * distance d) per (ky, d, kx) at ((ky (N+1) + d)(lx/2+1) + kx) 9.
+ * coefficient table: with T_ab now the 2-D DFT of the four terms' slices at
+ * plane distance d, ten values K0..K9 of (ky, d, kx) at
+ * ((ky (N+1) + d) 10 + k)(lx/2+1) + kx:
+ *   K0 = Re(T_cc + T_rr)   K1 = Im T_rr           K2 = Re(T_cc - T_rr)
+ *   K3 = -Re(T_cr + T_rc)  K4 = Im(T_rc - T_cr)   K5 = -Im(T_cr + T_rc)
+ *   K6 = Re(T_cr - T_rc)   K7 = Re(T_cc + T_rr')  K8 = Im T_rr'   K9 = Re(T_cc - T_rr'),
+ * T_rr' = T_rr(lx-kx, ky): the symmetric 4 x 4 real matrix the solve applies
+ * to the real and imaginary parts of a plane's spectrum at (kx,ky), (-kx,ky).
  */
 pipe_status_t pipe_plan_spectra(pipe_plan_t plan, void* out_device, void* hip_stream);
 

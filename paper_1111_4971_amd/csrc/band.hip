@@ -1,21 +1,388 @@
 // band.hip -- neighbouring-plane z sums (Eq. 17-18).  When the z dependence of
-// the Green function is negligible beyond nb planes, the potential on plane k is
-//   phi[., ., k] = hx hy hz sum_{d=-nb..nb} (2-D mixed conv/corr of rho[., ., k-d]
-//                                            with the slice of G at z distance |d| hz)
+// the Green function is negligible beyond N planes, the potential on plane k is
+//   phi[., ., k] = hx hy hz sum_{d=-N..N} (2-D mixed conv/corr of rho[., ., k-d]
+//                                          with the slice of G at z distance |d| hz)
 // so the z transform drops out: the planes are transformed in y and x only, the
-// product sums 2 nb + 1 plane products per output plane, and the Green spectra
-// are nb + 1 two-dimensional slices.
+// product sums 2N + 1 plane products per output plane, and the Green spectra
+// are N + 1 two-dimensional slices.
 //
-//   B1 y forward, real planes -> A (nx, ly, nz) complex      [strided_real_kernel<fwd>]
-//   B2 x forward of planes z0-nb .. z0+T+nb-1, banded product,
-//      x inverse of planes z0 .. z0+T-1, A -> B               [xband_kernel]
-//   B3 y inverse B -> real planes, scaled                     [strided_real_kernel<inv>]
+// The planes are real, so two of them travel as one complex plane: packed
+// column p holds rho[., ., 2p] + i rho[., ., 2p+1].  Its 2-D spectrum F splits
+// into the two planes' Hermitian spectra, R_even(k) = (F(k) + conj F(-k)) / 2
+// and R_odd(k) = (F(k) - conj F(-k)) / 2i; the products are needed at only two
+// points of each orbit (the other two are their conjugates), and the outputs
+// are packed the same way before the inverse transforms.
+//
+//   B1 y forward of packed pairs, rho -> A (nx, ly, ceil(nz/2)) complex  [strided_pair_kernel<fwd>]
+//   B2 x forward, split, banded product, pack, x inverse, A -> B         [xband_kernel]
+//   B3 y inverse, unpack to the real planes, scaled                      [strided_pair_kernel<inv>]
 #include "pass_common.h"
 
 namespace pipe {
 
+// y pass between real planes (pairs of z columns) and packed complex columns.
+// Real side: element (slab, e, z) at slab * r_ss + e * r_es + z, z < nz.
+// Complex side: (slab, e, p) at slab * c_ss + e * c_es + p, p < ncols = ceil(nz/2).
+// Forward: real in, complex out (all ly rows, zero-padded beyond n_in).
+// Inverse: complex in, real out (rows e < n_out), times scale.
+template <typename real, int N, int T, bool INV>
+__global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N>::E) * T)) * (N / Plan<N>::E) * T)
+void strided_pair_kernel(const void* in, void* out, int n_in, int n_out, long r_es, long c_es, long ncols,
+                         long r_ss, long c_ss, long nslabs, int nz, real scale, const cplx<real>* __restrict__ tw) {
+    using C = cplx<real>;
+    constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
+    __shared__ C lds[SPW * N * T];
+    __shared__ C s_tw[N];
+    tw = stage_twiddles(s_tw, tw, N);
+    const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
+    const long slab = (long)blockIdx.y * SPW + s;
+    const long col = (long)blockIdx.x * T + c;
+    const bool active = slab < nslabs && col < ncols;
+    const bool pair = 2 * col + 1 < nz;            // the odd plane exists
+    // pairs start on a 2-real boundary: one vector access per pair
+    const void* rp = INV ? (const void*)out : in;
+    const bool vec = (nz % 2) == 0 && (reinterpret_cast<uintptr_t>(rp) % (2 * sizeof(real))) == 0;
+    const long roff = active ? slab * r_ss + 2 * col : 0;
+    const long coff = active ? slab * c_ss + col : 0;
+    LdsCol<C, T> view{lds + s * N * T + c};
+    fft_line<N, INV, false>(
+        t, tw,
+        [&](int e) -> C {
+            if (!(active && e < n_in)) return cmake<C>(0, 0);
+            if constexpr (INV) {
+                return reinterpret_cast<const C*>(in)[coff + e * c_es];
+            } else {
+                const real* r = reinterpret_cast<const real*>(in) + roff + e * r_es;
+                if (vec) return *reinterpret_cast<const C*>(r);
+                return cmake<C>(r[0], pair ? r[1] : (real)0);
+            }
+        },
+        [&](int e, C v) {
+            if (!(active && e < n_out)) return;
+            if constexpr (INV) {
+                real* r = reinterpret_cast<real*>(out) + roff + e * r_es;
+                if (vec) {
+                    *reinterpret_cast<C*>(r) = cmake<C>(v.x * scale, v.y * scale);
+                } else {
+                    r[0] = v.x * scale;
+                    if (pair) r[1] = v.y * scale;
+                }
+            } else {
+                reinterpret_cast<C*>(out)[coff + e * c_es] = v;
+            }
+        },
+        view);
+}
+
+#ifndef PIPE_BAND_TMAX
+#define PIPE_BAND_TMAX 16     // widest packed-column tile of the banded x pass
+#endif
+
+// Packed columns per block of the banded x pass: a power of two <= PIPE_BAND_TMAX
+// with at most 512 threads (two ky lines x P threads x T columns), the padded
+// LDS lines (2 N (T + 1) complex) within PIPE_LDS_CAP + 8 KB, and the whole
+// block's LDS (lines, twiddles, one distance's coefficients) within 156 KB.
+template <typename real, int N> constexpr int band_T() {
+    constexpr int P = N / Plan<N>::E, cs = 2 * (int)sizeof(real);
+    constexpr int fixed = N * cs + 10 * (N / 2 + 1) * (int)sizeof(real);
+    int t = PIPE_BAND_TMAX;
+    while (t > 1 && (2 * P * t > 512 || 2 * N * (t + 1) * cs > PIPE_LDS_CAP + 8192 ||
+                     2 * N * (t + 1) * cs + fixed > 156 * 1024))
+        t /= 2;
+    return t;
+}
+
+__device__ __forceinline__ int floor_half(int x) { return x >= 0 ? x / 2 : -((1 - x) / 2); }
+
+// Block (tile, ky): lines ky and -ky of the 2 to output planes z0 = 2 to tile ...
+// z0 + 2 to - 1 (packed columns to tile ..., to <= T).  The packed input
+// columns holding planes z0 - nb .. z0 + 2 to - 1 + nb (to + nb + (nb odd)
+// of them) are transformed along x, T at a time, into
+// LDS (element e of column j at e (T+1) + j: the padding keeps both the
+// transforms' column-wise and the products' orbit-wise accesses free of bank
+// conflicts).  Each chunk is split into the planes' spectra in place; then
+// every (kx orbit, output column) item adds the products of its two output
+// planes with the chunk's planes within nb of them to register accumulators.
+// Lanes of a wave run over kx orbits, so the plane bookkeeping is uniform per
+// wave and the table reads are coalesced.  The accumulators are finally packed
+// into the LDS lines and transformed back.
+//
+// The product.  With R real-plane spectra (Hermitian), the four-term product
+// at the orbit points (kx, ky) and (-kx, ky) of an output plane needs only
+// x0 = R(kx, ky) = a + ib and x1 = R(-kx, ky) = c + id of the input plane:
+//   Phi(kx, ky)  = T_cc x0 - T_cr conj x1 - T_rc x1 + T_rr conj x0,
+//   Phi(-kx, ky) = T_cc x1 - T_cr conj x0 - conj(T_rc) x0 + T_rr(-kx, ky) conj x1,
+// (the other two points are the conjugates), a real-linear map of (a, b, c, d)
+// whose 4 x 4 matrix is symmetric with ten distinct entries K0..K9
+// (band_coefficients).  The adjoint therefore applies the same matrices.
+//
+// Banded table: K_k of (ky orbit kyo, plane distance d, kx orbit kxo) at
+// ((kyo (nb + 1) + d) 10 + k) (N/2 + 1) + kxo.  The split leaves a factor 2
+// on the spectra, which the inverse y pass removes with its scale.
+template <typename real, int N>
+__global__ __launch_bounds__((2 * (N / Plan<N>::E) * band_T<real, N>()))
+void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz, int nb,
+                  int to, const real* __restrict__ table, const cplx<real>* __restrict__ tw) {
+    using C = cplx<real>;
+    constexpr int T = band_T<real, N>(), TS = T + 1;
+    constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NH = N / 2, NKX = NH + 1;
+    // items (orbit o < N/2, output column c2): exactly IM per thread; the
+    // orbit o = N/2 of output column c2 goes to thread c2 as one more item
+    constexpr int IM = NH * T / NT;
+    static_assert(IM * NT == NH * T, "the E/4 items per thread must tile the orbits");
+    constexpr int KPT = (10 * NKX + NT - 1) / NT;   // coefficients each thread stages per distance
+    __shared__ C lds[2 * N * TS];
+    __shared__ C s_tw[N];
+    __shared__ real sK[10 * NKX];   // K0..K9 of one plane distance, this block's ky
+    tw = stage_twiddles(s_tw, tw, N);
+    const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
+    const unsigned ntile = gridDim.x;
+    const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
+    const int tile = (int)(lid % ntile);
+    const int ky = (int)(lid / ntile);
+    const int kyl = l == 0 ? ky : (ly - ky) % ly;
+    const bool self = (ky == 0) || (2 * ky == ly);
+    const int nzp = (nz + 1) / 2;
+    const int z0 = 2 * to * tile;   // to <= T output columns per block
+    const long xs = (long)ly * nzp;
+    const real* trow = table + (long)ky * (nb + 1) * 10 * NKX;
+    for (int idx = threadIdx.x; idx < 10 * NKX; idx += NT) sK[idx] = trow[idx];   // distance 0 (barriers follow)
+    LdsCol<C, TS> view{lds + l * N * TS + c};
+    const bool extra = threadIdx.x < T;   // owns item (N/2, c2 = threadIdx.x)
+    auto item = [&](int i, int& o, int& c2) {
+        if (i < IM) {
+            const int w = threadIdx.x + i * NT;
+            o = w % NH;
+            c2 = w / NH;
+        } else {
+            o = NH;
+            c2 = threadIdx.x;
+        }
+    };
+
+    C acc[IM + 1][4];   // per item: Phi_even at (kx,ky), (-kx,ky); Phi_odd at the same
+#pragma unroll
+    for (int i = 0; i <= IM; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[i][q] = cmake<C>(0, 0);
+
+    // packed input columns pbase .. pbase + ncolp - 1 hold planes z0 - nb .. z0 + 2 to - 1 + nb
+    const int pbase = floor_half(z0 - nb);
+    const int ncolp = floor_half(z0 + 2 * to - 1 + nb) - pbase + 1;
+    const int nchunk = (ncolp + T - 1) / T;
+    for (int ch = 0; ch < nchunk; ++ch) {
+        if (ch > 0) __syncthreads();   // previous chunk's products have read the LDS
+        const int pc = pbase + ch * T + c;
+        const bool act = ch * T + c < ncolp && pc >= 0 && pc < nzp;
+        const C* line = in + (act ? (long)kyl * nzp + pc : 0);
+        fft_line<N, false, false>(
+            t, tw, [&](int e) -> C { return (act && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
+            [&](int e, C v) { view.set(e, v); }, view);
+        __syncthreads();
+        // split every packed column into 2 R_even (line 0) and 2 R_odd (line 1)
+        // at slots o, -o: F(k) +- conj F(-k), times -i for the odd plane; the
+        // item of orbit o owns all four slots
+#pragma unroll
+        for (int i = 0; i <= IM; ++i) {
+            if (i == IM && !extra) break;
+            int o, j;
+            item(i, o, j);
+            const int on = (N - o) % N;
+            const C f0 = lds[o * TS + j], f1 = lds[on * TS + j];
+            const C g0 = lds[(N + o) * TS + j], g1 = lds[(N + on) * TS + j];
+            const C u0 = csub(f0, cconj(g1)), u1 = csub(f1, cconj(g0));
+            lds[o * TS + j] = cadd(f0, cconj(g1));
+            lds[(N + o) * TS + j] = cmake<C>(u0.y, -u0.x);
+            if (on != o) {
+                lds[on * TS + j] = cadd(f1, cconj(g0));
+                lds[(N + on) * TS + j] = cmake<C>(u1.y, -u1.x);
+            }
+        }
+        __syncthreads();
+        // products: output plane ze + h (ze = z0 + 2 c2) with input plane
+        // z = ze + h - d, |d| <= nb, when z lies in this chunk and in the mesh.
+        // The coefficients of distance ad sit in sK; those of ad + 1 are
+        // fetched into registers meanwhile and stored after the products.
+        const int p0 = pbase + ch * T;
+        const int jlim = min(T, ncolp - ch * T);
+        for (int ad = 0; ad <= nb; ++ad) {
+            real pre[KPT];
+            if (ad < nb) {
+                const real* src = trow + (long)(ad + 1) * 10 * NKX;
+#pragma unroll
+                for (int u = 0; u < KPT; ++u) {
+                    const int idx = threadIdx.x + u * NT;
+                    if (idx < 10 * NKX) pre[u] = src[idx];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i <= IM; ++i) {
+                if (i == IM && !extra) break;
+                int o, c2;
+                item(i, o, c2);
+                if (c2 >= to) continue;
+                const int on = (N - o) % N;
+                const int ze = z0 + 2 * c2;
+                // the (up to) four pairs at this distance: d = +-ad, h = 0, 1
+                int zk[4];
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int z = ze + (k & 1) - ((k & 2) ? -ad : ad);
+                    const int j = (z >> 1) - p0;
+                    const bool ok = !((k & 2) && ad == 0) && z >= 0 && z < nz && j >= 0 && j < jlim;
+                    zk[k] = ok ? z : -1;
+                    any |= ok;
+                }
+                if (!any) continue;
+                real q[10];
+#pragma unroll
+                for (int m = 0; m < 10; ++m) q[m] = sK[m * NKX + o];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int z = zk[k];
+                    if (z < 0) continue;
+                    const int j = (z >> 1) - p0, sN = (z & 1) * N;
+                    const C x0 = lds[(sN + o) * TS + j], x1 = lds[(sN + on) * TS + j];
+                    C& y0 = acc[i][2 * (k & 1)];
+                    C& y1 = acc[i][2 * (k & 1) + 1];
+                    y0.x += q[0] * x0.x + q[1] * x0.y + q[3] * x1.x + q[4] * x1.y;
+                    y0.y += q[1] * x0.x + q[2] * x0.y + q[5] * x1.x + q[6] * x1.y;
+                    y1.x += q[3] * x0.x + q[5] * x0.y + q[7] * x1.x + q[8] * x1.y;
+                    y1.y += q[4] * x0.x + q[6] * x0.y + q[8] * x1.x + q[9] * x1.y;
+                }
+            }
+            __syncthreads();   // every product of distance ad has read sK
+            if (ad < nb) {
+#pragma unroll
+                for (int u = 0; u < KPT; ++u) {
+                    const int idx = threadIdx.x + u * NT;
+                    if (idx < 10 * NKX) sK[idx] = pre[u];
+                }
+            } else if (ch + 1 < nchunk && nb > 0) {
+                // next chunk starts again at distance 0
+                const real* src = trow;
+                for (int idx = threadIdx.x; idx < 10 * NKX; idx += NT) sK[idx] = src[idx];
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    // G = Phi_even + i Phi_odd; Phi Hermitian: Phi(kx,-ky) = conj Phi(-kx,ky), Phi(-kx,-ky) = conj Phi(kx,ky)
+    auto pack = [](C e, C d) { return cmake<C>(e.x - d.y, e.y + d.x); };   // e + i d
+#pragma unroll
+    for (int i = 0; i <= IM; ++i) {
+        if (i == IM && !extra) break;
+        int o, c2;
+        item(i, o, c2);
+        const int on = (N - o) % N;
+        const C e0 = acc[i][0], e1 = acc[i][1], d0 = acc[i][2], d1 = acc[i][3];
+        lds[o * TS + c2] = pack(e0, d0);
+        lds[(N + o) * TS + c2] = pack(cconj(e1), cconj(d1));
+        if (on != o) {   // o = 0 and o = N/2 are their own mirror
+            lds[on * TS + c2] = pack(e1, d1);
+            lds[(N + on) * TS + c2] = pack(cconj(e0), cconj(d0));
+        }
+    }
+    __syncthreads();
+
+    // inverse x transforms of the output columns c < to, rows i < nx
+    const int pco = to * tile + c;
+    const bool oact = c < to && pco < nzp && !(l == 1 && self);
+    C* oline = out + (oact ? (long)kyl * nzp + pco : 0);
+    fft_line<N, true, true>(
+        t, tw, [&](int e) -> C { return view.get(e); },
+        [&](int e, C v) {
+            if (oact && e < nx) oline[e * xs] = v;
+        },
+        view);
+}
+
+// N = 0 (Eq. 17: independent planes).  Each output column depends on its
+// own input column only, so the split, the product and the packing happen in
+// place, one orbit at a time, between the two transforms, with no halo, no
+// accumulators and the 3-D fused pass's block shape: T packed columns of the
+// two lines ky, -ky.  Coefficients as xband_kernel (distance 0).
+template <typename real, int N> constexpr int band0_T() {
+    constexpr int P = N / Plan<N>::E;
+    int t = PIPE_XPROD_TMAX;
+    while (t > 1 && (2 * N * t * 2 * (int)sizeof(real) > PIPE_LDS_CAP || 2 * P * t > 1024)) t /= 2;
+    return t;
+}
+
+template <typename real, int N>
+__global__ __launch_bounds__((2 * (N / Plan<N>::E) * band0_T<real, N>()))
+void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz,
+                   const real* __restrict__ table, const cplx<real>* __restrict__ tw) {
+    using C = cplx<real>;
+    constexpr int T = band0_T<real, N>();
+    constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NKX = N / 2 + 1;
+    __shared__ C lds[2 * N * T];
+    __shared__ C s_tw[N];
+    tw = stage_twiddles(s_tw, tw, N);
+    const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
+    const unsigned ntile = gridDim.x;
+    const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
+    const int tile = (int)(lid % ntile);
+    const int ky = (int)(lid / ntile);
+    const int kyl = l == 0 ? ky : (ly - ky) % ly;
+    const bool self = (ky == 0) || (2 * ky == ly);
+    const int nzp = (nz + 1) / 2;
+    const int pc = tile * T + c;
+    const bool active = pc < nzp;
+    const long xs = (long)ly * nzp;
+    const C* iline = in + (active ? (long)kyl * nzp + pc : 0);
+    C* oline = out + (active ? (long)kyl * nzp + pc : 0);
+    LdsCol<C, T> view{lds + l * N * T + c};
+
+    fft_line<N, false, false>(
+        t, tw, [&](int e) -> C { return (active && e < nx) ? iline[e * xs] : cmake<C>(0, 0); },
+        [&](int e, C v) { view.set(e, v); }, view);
+    __syncthreads();
+
+    const real* trow = table + (long)ky * 10 * NKX;
+    for (int w = threadIdx.x; w < NKX * T; w += NT) {
+        const int j = w % T, o = w / T;
+        const int on = (N - o) % N;
+        const C f0 = lds[o * T + j], f1 = lds[on * T + j];
+        const C g0 = lds[(N + o) * T + j], g1 = lds[(N + on) * T + j];
+        real q[10];
+#pragma unroll
+        for (int m = 0; m < 10; ++m) q[m] = trow[m * NKX + o];
+        // 2 R of the even and the odd plane at (kx,ky), (-kx,ky)
+        const C u0 = csub(f0, cconj(g1)), u1 = csub(f1, cconj(g0));
+        const C xe0 = cadd(f0, cconj(g1)), xe1 = cadd(f1, cconj(g0));
+        const C xo0 = cmake<C>(u0.y, -u0.x), xo1 = cmake<C>(u1.y, -u1.x);
+        auto apply = [&](C x0, C x1, C& y0, C& y1) {
+            y0 = cmake<C>(q[0] * x0.x + q[1] * x0.y + q[3] * x1.x + q[4] * x1.y,
+                          q[1] * x0.x + q[2] * x0.y + q[5] * x1.x + q[6] * x1.y);
+            y1 = cmake<C>(q[3] * x0.x + q[5] * x0.y + q[7] * x1.x + q[8] * x1.y,
+                          q[4] * x0.x + q[6] * x0.y + q[8] * x1.x + q[9] * x1.y);
+        };
+        C e0, e1, d0, d1;
+        apply(xe0, xe1, e0, e1);
+        apply(xo0, xo1, d0, d1);
+        // G = Phi_even + i Phi_odd at the four points (Phi Hermitian)
+        auto pack = [](C e, C d) { return cmake<C>(e.x - d.y, e.y + d.x); };
+        lds[o * T + j] = pack(e0, d0);
+        lds[(N + o) * T + j] = pack(cconj(e1), cconj(d1));
+        if (on != o) {
+            lds[on * T + j] = pack(e1, d1);
+            lds[(N + on) * T + j] = pack(cconj(e0), cconj(d0));
+        }
+    }
+    __syncthreads();
+
+    fft_line<N, true, true>(
+        t, tw, [&](int e) -> C { return view.get(e); },
+        [&](int e, C v) {
+            if (active && e < nx && !(l == 1 && self)) oline[e * xs] = v;
+        },
+        view);
+}
+
 // y pass with real input (forward: rho -> complex) or real output (inverse:
-// complex -> scaled real part).  Same block shape as the complex y pass.
+// complex -> scaled real part), one plane per column (the Green arrangements).
 template <typename real, int N, int T, bool INV>
 __global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N>::E) * T)) * (N / Plan<N>::E) * T)
 void strided_real_kernel(const void* in, void* out, int n_in, int n_out, long in_es, long out_es, long ncols,
@@ -47,124 +414,12 @@ void strided_real_kernel(const void* in, void* out, int n_in, int n_out, long in
         view);
 }
 
-// Planes per block of the banded x pass: a power of two <= 16 with at most
-// 512 threads (two ky lines x P threads x T planes) and 2 N T complex of LDS
-// within PIPE_LDS_CAP.
-template <typename real, int N> constexpr int band_T() {
-    constexpr int P = N / Plan<N>::E;
-    int t = 16;
-    while (t > 1 && (2 * P * t > 512 || 2 * N * t * 2 * (int)sizeof(real) > PIPE_LDS_CAP)) t /= 2;
-    return t;
-}
-
-// Block (tile, ky): the two lines ky and -ky of T consecutive output planes
-// z0 = tile T ...  The input planes z0 - nb .. z0 + T + nb - 1 are transformed
-// along x T at a time into LDS; after each chunk every (kx orbit, output plane)
-// item of this thread adds the products of the chunk's planes within nb of it
-// to register accumulators.  The accumulators then replace the LDS lines and
-// are transformed back.  Banded table: 9 values per (ky orbit, |d|, kx orbit)
-// at ((kyo (nb + 1) + |d|) (N/2 + 1) + kxo) 9, same plane order as the 3-D
-// orbit table.
-template <typename real, int N, bool ADJ>
-__global__ __launch_bounds__((2 * (N / Plan<N>::E) * band_T<real, N>()))
-void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz, int nb,
-                  const real* __restrict__ table, const cplx<real>* __restrict__ tw) {
-    using C = cplx<real>;
-    constexpr int T = band_T<real, N>();
-    constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NKX = N / 2 + 1;
-    constexpr int IMAX = (NKX * T + NT - 1) / NT;   // (orbit, plane) items per thread
-    __shared__ C lds[2 * N * T];
-    __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, N);
-    const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
-    const unsigned ntile = gridDim.x;
-    const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
-    const int tile = (int)(lid % ntile);
-    const int ky = (int)(lid / ntile);
-    const int kyl = l == 0 ? ky : (ly - ky) % ly;
-    const bool self = (ky == 0) || (2 * ky == ly);
-    const int z0 = tile * T;
-    const long xs = (long)ly * nz;
-    const real* trow = table + (long)ky * (nb + 1) * NKX * 9;
-    LdsCol<C, T> view{lds + l * N * T + c};
-
-    C acc[IMAX][4];
-#pragma unroll
-    for (int i = 0; i < IMAX; ++i)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[i][q] = cmake<C>(0, 0);
-
-    // input column cc (0 <= cc < T + 2 nb) is plane z0 - nb + cc; output plane
-    // z0 + c2 takes column cc = c2 + nb - d for d in [-nb, nb]
-    const int ncol = T + 2 * nb;
-    const int nchunk = (ncol + T - 1) / T;
-    for (int ch = 0; ch < nchunk; ++ch) {
-        if (ch > 0) __syncthreads();   // previous chunk's products have read the LDS
-        const int z = z0 - nb + ch * T + c;
-        const bool act = ch * T + c < ncol && z >= 0 && z < nz;
-        const C* line = in + (act ? (long)kyl * nz + z : 0);
-        fft_line<N, false, false>(
-            t, tw, [&](int e) -> C { return (act && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
-            [&](int e, C v) { view.set(e, v); }, view);
-        __syncthreads();
-        // planes of this chunk that lie inside the mesh
-        const int zc0 = z0 - nb + ch * T;
-        const int jmin = ce_max(0, -zc0);
-        const int jmax = min(T, min(ncol - ch * T, nz - zc0));   // exclusive
-#pragma unroll
-        for (int i = 0; i < IMAX; ++i) {
-            const int w = threadIdx.x + i * NT;
-            if (w >= NKX * T) break;
-            const int c2 = w % T, o = w / T;
-            const int on = (N - o) % N;
-            // column j of the chunk is cc = ch T + j, d = c2 + nb - cc
-            const int lo = ce_max(jmin, c2 - ch * T);
-            const int hi = min(jmax, c2 - ch * T + 2 * nb + 1);
-            for (int j = lo; j < hi; ++j) {
-                const int d = c2 + nb - ch * T - j;
-                const int ad = d < 0 ? -d : d;
-                const C r[4] = {lds[o * T + j], lds[on * T + j], lds[(N + o) * T + j], lds[(N + on) * T + j]};
-                const Orbit<real> ob = load_orbit(trow + ((long)ad * NKX + o) * 9, 1);
-                C p[4];
-                orbit_product<ADJ>(ob, r, p);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[i][q] = cadd(acc[i][q], p[q]);
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < IMAX; ++i) {
-        const int w = threadIdx.x + i * NT;
-        if (w >= NKX * T) break;
-        const int c2 = w % T, o = w / T;
-        const int on = (N - o) % N;
-        // o = 0 and o = N/2 are their own mirror: acc[i][0] and acc[i][1] agree there
-        lds[o * T + c2] = acc[i][0];
-        lds[(N + o) * T + c2] = acc[i][2];
-        if (on != o) {
-            lds[on * T + c2] = acc[i][1];
-            lds[(N + on) * T + c2] = acc[i][3];
-        }
-    }
-    __syncthreads();
-
-    // inverse x transforms of the T output planes, rows i < nx
-    const int zo = z0 + c;
-    const bool oact = zo < nz && !(l == 1 && self);
-    C* oline = out + (oact ? (long)kyl * nz + zo : 0);
-    fft_line<N, true, true>(
-        t, tw, [&](int e) -> C { return view.get(e); },
-        [&](int e, C v) {
-            if (oact && e < nx) oline[e * xs] = v;
-        },
-        view);
-}
-
-// Banded orbit table from the 2-D forward spectra S[lx][ly][D] (FP64 complex)
-// of one term's arrangement; term: 0 cc, 1 cr, 2 rc, 3 rr.
-template <typename out_t>
-__global__ void compress_band_kernel(const double2* __restrict__ S, out_t* table, int term, int lx, int ly, int D) {
+// The four terms' 2-D spectra of one plane distance, 9 values per orbit in
+// the 3-D orbit table's order (0 T_cc, 1-2 T_cr, 3-4 T_rc, 5-6 T_rr(kx,ky),
+// 7-8 T_rr(-kx,ky)), FP64, planar: value p of (kyo, d, kxo) at
+// ((kyo D + d) 9 + p) (lx/2 + 1) + kxo.  S[lx][ly][D] is one term's spectrum;
+// term: 0 cc, 1 cr, 2 rc, 3 rr.
+__global__ void compress_band_kernel(const double2* __restrict__ S, double* tmp, int term, int lx, int ly, int D) {
     const int kxo_n = lx / 2 + 1, kyo_n = ly / 2 + 1;
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long total = (long)kxo_n * kyo_n * D;
@@ -172,24 +427,71 @@ __global__ void compress_band_kernel(const double2* __restrict__ S, out_t* table
     const int d = (int)(i % D);
     const int kyo = (int)((i / D) % kyo_n);
     const int kxo = (int)(i / ((long)D * kyo_n));
-    out_t* e = table + (((long)kyo * D + d) * kxo_n + kxo) * 9;
+    double* e = tmp + ((long)kyo * D + d) * 9 * kxo_n + kxo;   // value p at e[p kxo_n]
     const double2 v = S[((long)kxo * ly + kyo) * D + d];
     switch (term) {
-        case 0: e[0] = (out_t)v.x; break;
-        case 1: e[1] = (out_t)v.x; e[2] = (out_t)v.y; break;
-        case 2: e[3] = (out_t)v.x; e[4] = (out_t)v.y; break;
+        case 0: e[0] = v.x; break;
+        case 1: e[1 * kxo_n] = v.x; e[2 * kxo_n] = v.y; break;
+        case 2: e[3 * kxo_n] = v.x; e[4 * kxo_n] = v.y; break;
         default: {
             const double2 m = S[((long)((lx - kxo) % lx) * ly + kyo) * D + d];
-            e[5] = (out_t)v.x;
-            e[6] = (out_t)v.y;
-            e[7] = (out_t)m.x;
-            e[8] = (out_t)m.y;
+            e[5 * kxo_n] = v.x;
+            e[6 * kxo_n] = v.y;
+            e[7 * kxo_n] = m.x;
+            e[8 * kxo_n] = m.y;
             break;
         }
     }
 }
 
+// K0..K9 of xband_kernel from the nine values (cc; cr = p + iq; rc = u + iv;
+// rr = m + in; rr(-kx) = m2 + i n2), computed in FP64 and rounded once:
+//   K0 = cc + m   K1 = n        K2 = cc - m   K3 = -p - u   K4 = -q + v
+//   K5 = -q - v   K6 = p - u    K7 = cc + m2  K8 = n2       K9 = cc - m2
+template <typename out_t>
+__global__ void band_coefficients_kernel(const double* __restrict__ tmp, out_t* table, long n_entries, int kxo_n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_entries * kxo_n) return;
+    const long row = i / kxo_n, kxo = i % kxo_n;
+    const double* e = tmp + row * 9 * kxo_n + kxo;
+    const double cc = e[0], p = e[kxo_n], q = e[2 * kxo_n], u = e[3 * kxo_n], v = e[4 * kxo_n];
+    const double m = e[5 * kxo_n], n = e[6 * kxo_n], m2 = e[7 * kxo_n], n2 = e[8 * kxo_n];
+    const double K[10] = {cc + m, n, cc - m, -p - u, -q + v, -q - v, p - u, cc + m2, n2, cc - m2};
+    out_t* o = table + row * 10 * kxo_n + kxo;
+    for (int k = 0; k < 10; ++k) o[k * kxo_n] = (out_t)K[k];
+}
+
 // ---------------------------------------------------------------- launchers
+
+template <typename real>
+hipError_t launch_strided_pair(int n, bool inverse, const void* in, void* out, int n_in, int n_out, long r_es,
+                               long c_es, long r_ss, long c_ss, long nslabs, int nz, real scale,
+                               const TwiddleBank& twb, hipStream_t s) {
+    using C = cplx<real>;
+    const C* tw = twb.get<C>(n);
+    const long ncols = (nz + 1) / 2;
+    if (!tw || nz < 1 || nslabs <= 0) return hipErrorInvalidValue;
+    switch (n) {
+#define X(N_)                                                                                        \
+    case N_: {                                                                                       \
+        constexpr int T = strided_T<real, N_>();                                                     \
+        constexpr int P = N_ / Plan<N_>::E, SPW = ce_max(1, 256 / (P * T));                          \
+        dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW));            \
+        if (inverse)                                                                                 \
+            hipLaunchKernelGGL((strided_pair_kernel<real, N_, T, true>), grid, dim3(SPW * P * T), 0, \
+                               s, in, out, n_in, n_out, r_es, c_es, ncols, r_ss, c_ss, nslabs, nz,    \
+                               scale, tw);                                                           \
+        else                                                                                         \
+            hipLaunchKernelGGL((strided_pair_kernel<real, N_, T, false>), grid, dim3(SPW * P * T),   \
+                               0, s, in, out, n_in, n_out, r_es, c_es, ncols, r_ss, c_ss, nslabs, nz, \
+                               scale, tw);                                                           \
+        return hipGetLastError();                                                                    \
+    }
+        PIPE_FOR_EACH_N(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
 
 template <typename real>
 hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, int n_in, int n_out, long in_es,
@@ -230,24 +532,37 @@ int band_tile(int lx, int real_bytes) {
     return 0;
 }
 
+// Output columns per block of xband_kernel: as many as leave the input window
+// (to + nb + (nb odd) packed columns) inside one chunk of T, while that keeps
+// at least half the tile; otherwise T, with the window taken in several chunks.
+static int band_out_columns(int T, int nb) {
+    const int to = T - nb - (nb & 1);
+    return 2 * to >= T ? to : T;
+}
+
 template <typename real>
-hipError_t launch_xband(int lx, bool adjoint, const void* in, void* out, int nx, int ly, int nz, int nb,
-                        const real* table, const TwiddleBank& twb, hipStream_t s) {
+hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
+                        const TwiddleBank& twb, hipStream_t s) {
     using C = cplx<real>;
     const C* tw = twb.get<C>(lx);
     if (!tw || nb < 0 || nx > lx || nz < 1) return hipErrorInvalidValue;
+    const int nzp = (nz + 1) / 2;
     switch (lx) {
 #define X(N_)                                                                                        \
     case N_: {                                                                                       \
-        constexpr int T = band_T<real, N_>();                                                        \
         constexpr int P = N_ / Plan<N_>::E;                                                          \
-        dim3 grid((unsigned)((nz + T - 1) / T), (unsigned)(ly / 2 + 1));                             \
-        if (adjoint)                                                                                 \
-            hipLaunchKernelGGL((xband_kernel<real, N_, true>), grid, dim3(2 * P * T), 0, s,          \
-                               (const C*)in, (C*)out, nx, ly, nz, nb, table, tw);                    \
-        else                                                                                         \
-            hipLaunchKernelGGL((xband_kernel<real, N_, false>), grid, dim3(2 * P * T), 0, s,         \
-                               (const C*)in, (C*)out, nx, ly, nz, nb, table, tw);                    \
+        if (nb == 0) {                                                                               \
+            constexpr int T = band0_T<real, N_>();                                                   \
+            dim3 grid((unsigned)((nzp + T - 1) / T), (unsigned)(ly / 2 + 1));                        \
+            hipLaunchKernelGGL((xband0_kernel<real, N_>), grid, dim3(2 * P * T), 0, s,               \
+                               (const C*)in, (C*)out, nx, ly, nz, table, tw);                        \
+        } else {                                                                                     \
+            constexpr int T = band_T<real, N_>();                                                    \
+            const int to = band_out_columns(T, nb);                                                  \
+            dim3 grid((unsigned)((nzp + to - 1) / to), (unsigned)(ly / 2 + 1));                      \
+            hipLaunchKernelGGL((xband_kernel<real, N_>), grid, dim3(2 * P * T), 0, s,                \
+                               (const C*)in, (C*)out, nx, ly, nz, nb, to, table, tw);                \
+        }                                                                                            \
         return hipGetLastError();                                                                    \
     }
         PIPE_FOR_EACH_N(X)
@@ -258,23 +573,35 @@ hipError_t launch_xband(int lx, bool adjoint, const void* in, void* out, int nx,
 
 static unsigned blocks_for(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t launch_compress_band(const void* spec, void* table, int real_bytes, int term, int lx, int ly, int D,
-                                hipStream_t st) {
+hipError_t launch_compress_band(const void* spec, double* tmp, int term, int lx, int ly, int D, hipStream_t st) {
     const long n = (long)(lx / 2 + 1) * (ly / 2 + 1) * D;
     if (D < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(compress_band_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const double2*)spec, tmp,
+                       term, lx, ly, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_coefficients(const double* tmp, void* table, int real_bytes, int lx, int ly, int D,
+                                    hipStream_t st) {
+    const int kxo_n = lx / 2 + 1;
+    const long rows = (long)(ly / 2 + 1) * D;
+    const long n = rows * kxo_n;
+    if (D < 1) return hipErrorInvalidValue;
     if (real_bytes == 8)
-        hipLaunchKernelGGL(compress_band_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                           (const double2*)spec, (double*)table, term, lx, ly, D);
+        hipLaunchKernelGGL(band_coefficients_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st, tmp,
+                           (double*)table, rows, kxo_n);
     else
-        hipLaunchKernelGGL(compress_band_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                           (const double2*)spec, (float*)table, term, lx, ly, D);
+        hipLaunchKernelGGL(band_coefficients_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, tmp,
+                           (float*)table, rows, kxo_n);
     return hipGetLastError();
 }
 
 #define PIPE_INST(real)                                                                                      \
+    template hipError_t launch_strided_pair<real>(int, bool, const void*, void*, int, int, long, long, long, \
+                                                  long, long, int, real, const TwiddleBank&, hipStream_t);   \
     template hipError_t launch_strided_real<real>(int, bool, const void*, void*, int, int, long, long, long, \
                                                   long, long, long, real, const TwiddleBank&, hipStream_t);  \
-    template hipError_t launch_xband<real>(int, bool, const void*, void*, int, int, int, int, const real*,   \
+    template hipError_t launch_xband<real>(int, const void*, void*, int, int, int, int, const real*,         \
                                            const TwiddleBank&, hipStream_t);
 PIPE_INST(float)
 PIPE_INST(double)

@@ -123,14 +123,15 @@ template <typename real> struct OrbitView {
 // r[q] = rho at point q of the orbit: q = 0 (kx,ky), 1 (-kx,ky), 2 (kx,-ky), 3 (-kx,-ky).
 // Forward: Phi(p) = sum_ab sigma_ab T_ab(p) rho(S_ab p).
 // Adjoint: Phi(p) = sum_ab sigma_ab conj(T_ab(S_ab p)) g(S_ab p)  (transposed gather).
-template <bool ADJ, typename real>
+// Outputs q < NQ only (NQ = 2 where Phi is Hermitian and q = 2, 3 follow by conjugation).
+template <bool ADJ, int NQ = 4, typename real>
 __device__ __forceinline__ void orbit_product(const Orbit<real>& o, const cplx<real>* r, cplx<real>* out) {
     using C = cplx<real>;
     OrbitView<real> T{o};
     const int SX[4] = {1, -1, 1, -1}, SY[4] = {1, 1, -1, -1};
     auto idx = [](int sx, int sy) { return (sx > 0 ? 0 : 1) + (sy > 0 ? 0 : 2); };
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const int sx = SX[q], sy = SY[q];
         const int qcr = idx(sx, -sy), qrc = idx(-sx, sy), qrr = idx(-sx, -sy);
         C tcc, tcr, trc, trr;
@@ -153,13 +154,5 @@ __device__ __forceinline__ void orbit_product(const Orbit<real>& o, const cplx<r
     }
 }
 
-
-// Column-interleaved LDS view with a runtime column stride.
-template <typename C> struct LdsColR {
-    C* base;
-    int stride;
-    __device__ __forceinline__ C get(int e) const { return base[e * stride]; }
-    __device__ __forceinline__ void set(int e, C v) const { base[e * stride] = v; }
-};
 
 }  // namespace pipe

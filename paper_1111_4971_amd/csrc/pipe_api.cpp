@@ -165,7 +165,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t plan_ws_bytes(const pipe_plan_s* p) {
     const size_t cb = 2 * (size_t)p->rb;
-    if (p->band >= 0) return 2 * align256((size_t)p->nx * p->ly * p->nz * cb);   // A and B of the banded passes
+    if (p->band >= 0) return 2 * align256((size_t)p->nx * p->ly * ((p->nz + 1) / 2) * cb);   // A, B: packed pairs
     const size_t a1 = (size_t)p->nx * p->ny * p->nh * cb;
     const size_t a2 = (size_t)p->nx * p->ly * p->nh * cb;
     return align256(a1) + align256(a2);
@@ -180,7 +180,7 @@ void plan_pass_bytes(const pipe_plan_s* p, double out[5]) {
     const double tab = 9.0 * orbits * (p->nh + 1) * rb;   // values read once per solve
     if (p->band >= 0) {
         // banded: y forward (real in), x + banded product, y inverse (real out)
-        const double A = (double)p->nx * p->ly * p->nz * cb;
+        const double A = (double)p->nx * p->ly * ((p->nz + 1) / 2) * cb;
         out[0] = phys + A;
         out[1] = 2.0 * A + 9.0 * orbits * (p->band + 1) * rb;
         out[2] = A + phys;
@@ -316,7 +316,7 @@ pipe_status_t build_band_spectra(pipe_plan_s* p, hipStream_t st, int nband, doub
     p->band = nb;
     const int D = nb + 1;
     const size_t orbits = (size_t)(lx / 2 + 1) * (ly / 2 + 1);
-    p->table_elems = 9 * orbits * D;
+    p->table_elems = 10 * orbits * D;
     p->nyq_elems = 0;
     HIP_TRY(dev_alloc(&p->table, p->table_elems * p->rb), "allocation (Green spectra)");
     p->nyq = nullptr;
@@ -325,6 +325,8 @@ pipe_status_t build_band_spectra(pipe_plan_s* p, hipStream_t st, int nband, doub
     HIP_TRY(s.get((void**)&rbar, sizeof(double) * (size_t)px * qy * D), "allocation (Green table)");
     HIP_TRY(s.get((void**)&buf, sizeof(double) * (size_t)lx * ly * D), "allocation (spectrum buffer)");
     HIP_TRY(s.get((void**)&cbuf, 2 * sizeof(double) * (size_t)lx * ly * D), "allocation (spectrum buffer)");
+    double* tmp;
+    HIP_TRY(s.get((void**)&tmp, sizeof(double) * 9 * orbits * D), "allocation (spectra staging)");
     // U[m] (qy x D) = Cy (qy x my) * D[m] (my x D, rows rfull apart)
     HIP_TRY(launch_gemm_f64(cy, d, u, qy, D, my, my, rfull, D, 0, (long)my * rfull, (long)qy * D, mx, st),
             "mode contraction (y)");
@@ -340,8 +342,9 @@ pipe_status_t build_band_spectra(pipe_plan_s* p, hipStream_t st, int nband, doub
         HIP_TRY(launch_strided<double>(lx, false, cbuf, cbuf, lx, lx, (long)ly * D, (long)ly * D, (long)ly * D, 0, 0, 1,
                                        p->ctx->tw, st),
                 "spectra x transform");
-        HIP_TRY(launch_compress_band(cbuf, p->table, p->rb, term, lx, ly, D, st), "spectra compression");
+        HIP_TRY(launch_compress_band(cbuf, tmp, term, lx, ly, D, st), "spectra compression");
     }
+    HIP_TRY(launch_band_coefficients(tmp, p->table, p->rb, lx, ly, D, st), "banded coefficients");
     if (keep_green) {
         HIP_TRY(dev_alloc((void**)&p->green, sizeof(double) * (size_t)px * qy * D), "allocation (kept Green table)");
         HIP_TRY(hipMemcpyAsync(p->green, rbar, sizeof(double) * (size_t)px * qy * D, hipMemcpyDeviceToDevice, st),
@@ -415,19 +418,21 @@ pipe_status_t run_band_passes(pipe_plan_s* p, const void* rho, void* phi, void* 
                               hipEvent_t* ev) {
     const size_t cb = 2 * sizeof(real);
     char* A = (char*)ws;
-    char* B = A + align256((size_t)p->nx * p->ly * p->nz * cb);
-    const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly;
+    const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly, nzp = (nz + 1) / 2;
+    char* B = A + align256((size_t)nx * ly * nzp * cb);
     const TwiddleBank& tw = p->ctx->tw;
     if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event");
-    HIP_TRY(launch_strided_real<real>(ly, false, rho, A, ny, ly, nz, nz, nz, (long)ny * nz, (long)ly * nz, nx, (real)1,
-                                      tw, st),
+    HIP_TRY(launch_strided_pair<real>(ly, false, rho, A, ny, ly, nz, nzp, (long)ny * nz, (long)ly * nzp, nx, nz,
+                                      (real)1, tw, st),
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
-    HIP_TRY(launch_xband<real>(p->lx, adjoint, A, B, nx, ly, nz, p->band, (const real*)p->table, tw, st),
+    (void)adjoint;   // the banded coefficient matrices are symmetric: same kernel both ways
+    HIP_TRY(launch_xband<real>(p->lx, A, B, nx, ly, nz, p->band, (const real*)p->table, tw, st),
             "x pass with banded product");
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
-    const real scale = (real)(p->hx * p->hy * p->hz / ((double)p->lx * p->ly));
-    HIP_TRY(launch_strided_real<real>(ly, true, B, phi, ly, ny, nz, nz, nz, (long)ly * nz, (long)ny * nz, nx, scale,
+    // 1/2 undoes the factor 2 of the split in the x pass
+    const real scale = (real)(0.5 * p->hx * p->hy * p->hz / ((double)p->lx * p->ly));
+    HIP_TRY(launch_strided_pair<real>(ly, true, B, phi, ly, ny, nz, nzp, (long)ny * nz, (long)ly * nzp, nx, nz, scale,
                                       tw, st),
             "y inverse pass");
     if (ev)

@@ -82,22 +82,36 @@ hipError_t launch_untile(const void* table, const void* nyq, void* out, int real
                          int tile, hipStream_t st);
 
 // Neighbouring-plane (banded z) path (band.hip).
-// y pass with real input (forward) or real output (inverse, times scale);
-// arguments as launch_strided.
+// y pass between real planes (rho, phi: (slab, e, z) at slab r_ss + e r_es + z,
+// z < nz) and packed complex columns p < ceil(nz/2) holding planes 2p + i (2p+1)
+// ((slab, e, p) at slab c_ss + e c_es + p).  Forward reads rows e < n_in and
+// writes all n rows; inverse reads n rows, writes rows e < n_out times scale.
+template <typename real>
+hipError_t launch_strided_pair(int n, bool inverse, const void* in, void* out, int n_in, int n_out, long r_es,
+                               long c_es, long r_ss, long c_ss, long nslabs, int nz, real scale,
+                               const TwiddleBank& tw, hipStream_t s);
+// y pass with real input (forward) or real output (inverse, times scale), one
+// plane per column; arguments as launch_strided.
 template <typename real>
 hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, int n_in, int n_out, long in_es,
                                long out_es, long ncols, long in_ss, long out_ss, long nslabs, real scale,
                                const TwiddleBank& tw, hipStream_t s);
-// x forward, sum over plane distances |d| <= nb of the orbit products, x
-// inverse: in, out (nx, ly, nz) complex (distinct buffers); table banded
-// ((ly/2+1) (nb+1) (lx/2+1) 9 values).
+// x forward, split of the packed plane pairs, sum over plane distances
+// |d| <= nb of the orbit products, packing, x inverse: in, out (nx, ly,
+// ceil(nz/2)) packed complex (distinct buffers); table: the banded
+// coefficients (launch_band_coefficients).  The output carries a factor 2.
+// The coefficient matrices are symmetric, so the adjoint is the same launch.
 template <typename real>
-hipError_t launch_xband(int lx, bool adjoint, const void* in, void* out, int nx, int ly, int nz, int nb,
-                        const real* table, const TwiddleBank& tw, hipStream_t s);
-// Output planes per block of the banded x pass (0 if lx unsupported).
+hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
+                        const TwiddleBank& tw, hipStream_t s);
+// Packed columns per block of the banded x pass (0 if lx unsupported).
 int band_tile(int lx, int real_bytes);
-// Banded orbit table from the 2-D spectra S[lx][ly][D] (FP64 complex) of one term.
-hipError_t launch_compress_band(const void* spec, void* table, int real_bytes, int term, int lx, int ly, int D,
-                                hipStream_t st);
+// One term's 2-D spectra S[lx][ly][D] (FP64 complex) into the nine-value
+// FP64 staging table tmp ((ly/2+1) D 9 (lx/2+1) values).
+hipError_t launch_compress_band(const void* spec, double* tmp, int term, int lx, int ly, int D, hipStream_t st);
+// The banded coefficient table (10 values per orbit and distance, plan
+// precision) from the staging table once all four terms are in.
+hipError_t launch_band_coefficients(const double* tmp, void* table, int real_bytes, int lx, int ly, int D,
+                                    hipStream_t st);
 
 }  // namespace pipe

@@ -247,12 +247,12 @@ class GreenPlan:
 
     def spectra(self):
         """(table, nyquist) as tensors of shape (9, lx/2+1, ly/2+1, lz/2) and (9, lx/2+1, ly/2+1);
-        for a banded plan the one table of shape (ly/2+1, N+1, lx/2+1, 9)."""
+        for a banded plan its coefficient table K0..K9, shape (ly/2+1, N+1, 10, lx/2+1)."""
         torch = _torch()
         i = self.info
         kx, ky, nh = i.lx // 2 + 1, i.ly // 2 + 1, i.lz // 2
         if self.band is not None:
-            out = torch.empty((ky, self.band + 1, kx, 9), dtype=self.dtype, device="cuda")
+            out = torch.empty((ky, self.band + 1, 10, kx), dtype=self.dtype, device="cuda")
             check(lib().pipe_plan_spectra(self.handle, _P(out.data_ptr()), _stream_ptr()))
             return out
         flat = torch.empty(9 * kx * ky * (nh + 1), dtype=self.dtype, device="cuda")

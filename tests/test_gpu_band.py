@@ -104,9 +104,12 @@ def test_band_adjoint(torch_cuda, prec):
 
 
 def test_band_spectra_and_table(torch_cuda):
-    """The plan's N + 1 two-dimensional spectra are the 2-D DFTs of the four terms'
-    arrangements of the Green slices at plane distances 0..N (Appendix A.3, A.9),
-    and its kept Green table is R at those distances."""
+    """The plan's coefficients come from the 2-D DFTs of the four terms'
+    arrangements of the Green slices at plane distances 0..N (Appendix A.3,
+    A.9), combined into the symmetric 4 x 4 real matrix that maps the real and
+    imaginary parts of a real plane's spectrum at (kx, ky), (-kx, ky) to the
+    potential's (the four-term product with the Hermitian symmetry of real
+    planes written out); its kept Green table is R at those distances."""
     from oracle import fourterm, green
     shape = (7, 6, 10)
     nx, ny, nz = shape
@@ -115,8 +118,8 @@ def test_band_spectra_and_table(torch_cuda):
     log("band spectra")
     plan = _plan(shape, "fp64", 1, nb, offset=offset, keep_green=True)
     lx, ly = plan.info.lx, plan.info.ly
-    got = plan.spectra().cpu().numpy()            # (ly/2+1, N+1, lx/2+1, 9)
-    assert got.shape == (ly // 2 + 1, nb + 1, lx // 2 + 1, 9)
+    got = plan.spectra().cpu().numpy()            # (ly/2+1, N+1, 10, lx/2+1)
+    assert got.shape == (ly // 2 + 1, nb + 1, 10, lx // 2 + 1)
     L3 = (lx, ly, 2 * nz)
     S = {}
     for name, xc, yc in (("cc", False, False), ("cr", False, True), ("rc", True, False), ("rr", True, True)):
@@ -125,14 +128,29 @@ def test_band_spectra_and_table(torch_cuda):
     kx = np.arange(lx // 2 + 1)
     ky = np.arange(ly // 2 + 1)
     sel = lambda a, kxs: a[np.ix_(kxs, ky)].transpose(1, 2, 0)    # -> (ky, d, kx)
-    ref = np.stack([sel(S["cc"], kx).real,
-                    sel(S["cr"], kx).real, sel(S["cr"], kx).imag,
-                    sel(S["rc"], kx).real, sel(S["rc"], kx).imag,
-                    sel(S["rr"], kx).real, sel(S["rr"], kx).imag,
-                    sel(S["rr"], (lx - kx) % lx).real, sel(S["rr"], (lx - kx) % lx).imag], axis=-1)
-    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    cc, cr, rc = sel(S["cc"], kx), sel(S["cr"], kx), sel(S["rc"], kx)
+    rr, rr2 = sel(S["rr"], kx), sel(S["rr"], (lx - kx) % lx)
     # T_cc of a real, even arrangement is real
-    assert np.max(np.abs(sel(S["cc"], kx).imag)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(cc.imag)) <= 1e-12 * np.max(np.abs(cc))
+    # Phi(kx,ky)  = T_cc x0 - T_cr conj(x1) - T_rc x1 + T_rr conj(x0)
+    # Phi(-kx,ky) = T_cc x1 - T_cr conj(x0) - conj(T_rc) x0 + T_rr(-kx,ky) conj(x1)
+    # as a real map of (Re x0, Im x0, Re x1, Im x1): check it on the unit vectors
+    c0 = cc.real
+    K = np.empty(got.shape)
+    for col, (x0, x1) in enumerate(((1, 0), (1j, 0), (0, 1), (0, 1j))):
+        p0 = c0 * x0 - cr * np.conj(x1) - rc * x1 + rr * np.conj(x0)
+        p1 = c0 * x1 - cr * np.conj(x0) - np.conj(rc) * x0 + rr2 * np.conj(x1)
+        M = np.stack([p0.real, p0.imag, p1.real, p1.imag], axis=2)   # rows of column col
+        if col == 0:
+            K[:, :, 0], K[:, :, 1], K[:, :, 3], K[:, :, 4] = M[:, :, 0], M[:, :, 1], M[:, :, 2], M[:, :, 3]
+        elif col == 1:
+            assert np.allclose(M[:, :, 0], K[:, :, 1], rtol=0, atol=1e-12 * np.abs(c0).max())   # symmetric
+            K[:, :, 2], K[:, :, 5], K[:, :, 6] = M[:, :, 1], M[:, :, 2], M[:, :, 3]
+        elif col == 2:
+            K[:, :, 7], K[:, :, 8] = M[:, :, 2], M[:, :, 3]
+        else:
+            K[:, :, 9] = M[:, :, 3]
+    assert np.max(np.abs(got - K)) <= 1e-12 * np.max(np.abs(K))
     # kept table: R at the difference and sum distances, planes 0..N
     x0, y0 = offset
     u = np.concatenate([np.arange(nx) * H[0], 2 * x0 + (np.arange(2 * nx - 1) + 2) * H[0]])
@@ -197,3 +215,26 @@ def test_long_bunch_banded_matches_full(torch_cuda):
     ref = gpu_solve(full, wl.rho)
     got = gpu_solve(band, wl.rho)
     assert rel_max(got, ref) <= 1e-9
+
+
+def test_band_unaligned_fp32_buffers(torch_cuda):
+    """Plane pairs are read and written as one vector access only when the
+    buffer start allows it: rho and phi at an odd float offset give the same
+    result as aligned buffers."""
+    torch = torch_cuda
+    shape = (9, 7, 20)
+    n = int(np.prod(shape))
+    rho = np.random.default_rng(71).standard_normal(shape)
+    log("band fp32 unaligned buffers")
+    plan = _plan(shape, "fp32", 1, 2)
+    x = torch.tensor(rho, device="cuda", dtype=torch.float32)
+    ref = plan.solve(x).cpu().numpy()
+    big_in = torch.zeros(n + 1, device="cuda", dtype=torch.float32)
+    big_out = torch.zeros(n + 1, device="cuda", dtype=torch.float32)
+    xin = big_in[1:].view(shape)
+    xin.copy_(x)
+    out = big_out[1:].view(shape)
+    assert xin.data_ptr() % 8 == 4 and out.data_ptr() % 8 == 4
+    plan.solve(xin, out=out)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
