@@ -422,3 +422,95 @@ def test_band_limits_of_the_z_sum(kind):
         d = direct.solve(rho, hx, hy, hz, a, b, 9, 8, kind, band=band)
         f = fourterm.solve(rho, hx, hy, hz, a, b, 9, 8, kind, band=band)
         assert rel_l2(f, d) <= 1e-13
+
+
+# ---------------------------------------------------------------- free space (Eq. 3-5)
+
+def test_free_direct_equals_python_loops():
+    from oracle import free
+    rng = np.random.default_rng(81)
+    rho = rng.standard_normal((3, 2, 4))
+    h = (0.3, 0.5, 0.2)
+    assert rel_l2(free.solve_direct(rho, h, 2.5), free.solve_python_loops(rho, h, 2.5)) <= 1e-14
+
+
+@pytest.mark.parametrize("shape,L", [((4, 3, 5), None), ((5, 4, 3), (9, 7, 5)), ((6, 2, 7), (16, 6, 20))])
+def test_free_eq5_fft_equals_direct_sum(shape, L):
+    """Eq. 5 with any padding L >= 2n - 1 reproduces the direct sum of Eq. 4 (Appendix A.8)."""
+    from oracle import free
+    rng = np.random.default_rng(sum(shape))
+    rho = rng.standard_normal(shape)
+    h = (0.11, 0.07, 0.13)
+    assert rel_l2(free.solve_fft(rho, h, 3.0, L), free.solve_direct(rho, h, 3.0)) <= 1e-13
+
+
+def test_free_point_charge_gives_the_green_function():
+    """A unit point charge (rho = delta / (hx hy hz)) at node c: phi = G(i - c) exactly,
+    with the supplied self value at c."""
+    from oracle import free
+    h = (0.2, 0.3, 0.25)
+    rho = np.zeros((5, 4, 6))
+    c = (2, 1, 4)
+    rho[c] = 1.0 / (h[0] * h[1] * h[2])
+    phi = free.solve_fft(rho, h, 7.0)
+    i, j, k = np.meshgrid(np.arange(5) - c[0], np.arange(4) - c[1], np.arange(6) - c[2], indexing="ij")
+    r = np.sqrt((i * h[0]) ** 2 + (j * h[1]) ** 2 + (k * h[2]) ** 2)
+    ref = np.where(r > 0, 1.0 / np.where(r > 0, r, 1.0), 7.0)
+    assert np.max(np.abs(phi - ref)) <= 1e-12 * np.max(ref)
+
+
+def test_free_green_of_a_far_charge_is_coulomb():
+    """Far from a compact charge the potential is Q / r to leading order (the
+    dipole vanishes for a charge symmetric about its centre)."""
+    from oracle import free
+    h = (0.1, 0.1, 0.1)
+    rho = np.zeros((3, 3, 40))
+    rho[:, :, :3] = 1.0                       # a 3x3x3 block at the near end, centre (1, 1, 1)
+    Q = rho.sum() * h[0] * h[1] * h[2]
+    phi = free.solve_fft(rho, h, 0.0)
+    r = (np.arange(40) - 1) * h[2]
+    far = slice(30, 40)
+    assert np.max(np.abs(phi[1, 1, far] * r[far] / Q - 1.0)) <= 2e-3
+
+
+@pytest.mark.parametrize("dirs", ["fff", "bbb", "fbf", "bfb", "ffb", "bbf", "fbb", "bff"])
+def test_mixed_fft_directions(dirs):
+    """Each dimension's transform is the DFT matrix W^{jk} ('f') or W^{-jk} ('b'),
+    W = e^{-2 pi i/N}, applied along that axis (Eq. A.4), unscaled."""
+    from oracle import free
+    rng = np.random.default_rng(3)
+    shape = (4, 6, 8)
+    a = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    ref = a.copy()
+    for axis, (n, d) in enumerate(zip(shape, dirs)):
+        m = np.exp((-2j if d == "f" else 2j) * np.pi * np.outer(np.arange(n), np.arange(n)) / n)
+        ref = np.moveaxis(np.tensordot(m, np.moveaxis(ref, axis, 0), axes=(1, 0)), 0, axis)
+    assert np.max(np.abs(free.mixed_fft(a, dirs) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_eq6_correlation_in_y_by_mixed_directions():
+    """Eq. 6: sum rho[i',j',k'] G[i-i', j+j', k-k'] = F^bfb{(F^fff rho)(F^fbf G)} / (Lx Ly Lz),
+    with the y slots of G holding the sums j + j' (Appendix A.9)."""
+    from oracle import free
+    rng = np.random.default_rng(12)
+    nx, ny, nz = 4, 3, 5
+    rho = rng.standard_normal((nx, ny, nz))
+    Gf = rng.standard_normal((2 * nx - 1, 2 * ny - 1, 2 * nz - 1))   # G[d_x + nx-1, s_y, d_z + nz-1]
+    L = (2 * nx, 2 * ny, 2 * nz)
+    direct_sum = np.zeros((nx, ny, nz))
+    for i in range(nx):
+        for j in range(ny):
+            for k in range(nz):
+                for a in range(nx):
+                    for b in range(ny):
+                        for c in range(nz):
+                            direct_sum[i, j, k] += rho[a, b, c] * Gf[i - a + nx - 1, j + b, k - c + nz - 1]
+    garr = np.zeros(L)
+    for p in range(-(nx - 1), nx):
+        for s in range(2 * ny - 1):
+            for q in range(-(nz - 1), nz):
+                garr[p % L[0], s, q % L[2]] = Gf[p + nx - 1, s, q + nz - 1]
+    pad = np.zeros(L)
+    pad[:nx, :ny, :nz] = rho
+    out = free.mixed_fft(free.mixed_fft(pad, 'fff') * free.mixed_fft(garr, 'fbf'), 'bfb') / np.prod(L)
+    assert np.max(np.abs(out[:nx, :ny, :nz].real - direct_sum)) <= 1e-12 * np.max(np.abs(direct_sum))
