@@ -65,6 +65,7 @@ typedef enum pipe_status {
 enum {
     PIPE_GREEN_POINT = 0,   /* R of Eq. 9: z-factor e^{-kappa|w|}                         */
     PIPE_GREEN_IGF_Z = 1,   /* R_int of Eq. 16: z-factor g_z(w) of Eq. 15 (hat basis)     */
+    PIPE_GREEN_FREE = 2,    /* free space, G = 1/r of Eq. 3 (plans from pipe_free_plan)   */
     PIPE_PREC_FP64 = 0x00,  /* transforms, products, rho and phi in double                */
     PIPE_PREC_FP32 = 0x10,  /* transforms, products, rho and phi in float                 */
     PIPE_KEEP_GREEN = 0x100,/* keep the on-mesh Green table for pipe_plan_green_table     */
@@ -166,6 +167,22 @@ pipe_status_t pipe_green_plan_banded(int nx, int ny, int nz, double hx, double h
                                      double a, double b, double x0, double y0, int kind, int mx, int my,
                                      int lx, int ly, int nband, double tol, void* hip_stream,
                                      pipe_plan_t* out);
+
+/*
+ * pipe_free_plan -- the isolated (free-space) problem by Hockney's method,
+ * Sec. 1, Eq. 3-5: phi[i,j,k] = hx hy hz sum rho[i',j',k'] G((i-i') hx,
+ * (j-j') hy, (k-k') hz) with G = 1/sqrt(u^2 + v^2 + w^2) (the 4 pi dropped, as
+ * in Eq. 3), computed as one zero-padded convolution (Eq. 5).  G is singular
+ * at zero separation and the paper leaves that grid value open: g0 (finite)
+ * is used there.  kind = PIPE_PREC_* optionally | PIPE_AUTOTUNE* (a Green
+ * kind in its low nibble is INVALID_ARG; PIPE_KEEP_GREEN is INVALID_ARG).
+ * Padded lengths as pipe_green_plan_ex.  The plan reports kind
+ * PIPE_GREEN_FREE, a = b = 0, norm = 1, and solves, adjoints (the operator
+ * is symmetric), batches and timing hooks work on it unchanged.
+ * Errors: INVALID_ARG, UNSUPPORTED_SIZE, NO_DEVICE, OUT_OF_MEMORY, HIP.
+ */
+pipe_status_t pipe_free_plan(int nx, int ny, int nz, double hx, double hy, double hz, double g0, int kind,
+                             int lx, int ly, int lz, void* hip_stream, pipe_plan_t* out);
 
 /* pipe_plan_info -- sizes and constants of a plan.  Errors: INVALID_ARG. */
 pipe_status_t pipe_plan_info(pipe_plan_t plan, pipe_plan_info_t* out);
@@ -283,6 +300,22 @@ pipe_status_t pipe_plan_timing(pipe_plan_t plan, int max_solves, float* pass_ms_
  */
 pipe_status_t pipe_fft_lines(int real_bytes, int len, int n_in, int howmany, int dir,
                              const void* in_device, void* out_device, void* hip_stream);
+
+/*
+ * pipe_fft3d -- unscaled 3-D complex DFT with the direction chosen per
+ * dimension (Sec. 5: the method needs, and other uses such as split-operator
+ * Vlasov solvers want, per-dimension direction control that multidimensional
+ * FFT packages rarely offer; Eq. 6 is an example).  in, out: device arrays of
+ * n0 x n1 x n2 complex values (interleaved re, im; real_bytes 4 or 8), C order,
+ * last index fastest; out may equal in (in place) but must not otherwise
+ * overlap it (ALIASING).  dirs: three characters, one per dimension in order,
+ * 'f' = sum_n a_n W^{nk}, 'b' = sum_n a_n W^{-nk}, W = e^{-2 pi i/N}
+ * (Eq. A.4's conventions; e.g. "fbf" is F^{fbf} of Eq. 6).  Each n must be a
+ * supported length (2^p 3^q in [8, 1024]).  Asynchronous on hip_stream.
+ * Errors: INVALID_ARG, UNSUPPORTED_SIZE, ALIASING, NO_DEVICE, HIP.
+ */
+pipe_status_t pipe_fft3d(int real_bytes, int n0, int n1, int n2, const char* dirs, const void* in_device,
+                         void* out_device, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpipe.so")
-SOURCES = ["passes.hip", "band.hip", "green.hip", "pipe_api.cpp"]
+SOURCES = ["passes.hip", "band.hip", "fft3d.hip", "green.hip", "pipe_api.cpp"]
 ARCH = os.environ.get("PIPE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -169,6 +169,30 @@ __global__ void arrange_kernel(double* xi, const double* __restrict__ rbar, int 
     xi[i] = v;
 }
 
+// Free-space Green array of Eq. 5: slot (p, q, s) holds G = 1/r at the grid
+// distance (|m| hx, |n| hy, |l| hz) of its convolution slot (Appendix A.3),
+// g0 at zero distance (Eq. 3 is singular there), zero in unused slots.
+__global__ void free_arrange_kernel(double* xi, int nx, int ny, int nz, int lx, int ly, int lz, double hx,
+                                    double hy, double hz, double g0) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long total = (long)lx * ly * lz;
+    if (i >= total) return;
+    const int s = (int)(i % lz);
+    const int q = (int)((i / lz) % ly);
+    const int p = (int)(i / ((long)lz * ly));
+    const int ip = conv_slot(p, lx, nx), iq = conv_slot(q, ly, ny), is = conv_slot(s, lz, nz);
+    double v = 0.0;
+    if (ip >= 0 && iq >= 0 && is >= 0) {
+        if (ip == 0 && iq == 0 && is == 0) {
+            v = g0;
+        } else {
+            const double u = ip * hx, w = iq * hy, z = is * hz;
+            v = 1.0 / sqrt(u * u + w * w + z * z);
+        }
+    }
+    xi[i] = v;
+}
+
 // Orbit table from the full forward spectrum S[lx][ly][nh] (FP64 complex, kz = lz/2
 // packed into slot 0 as A + iB).  term: 0 cc, 1 cr, 2 rc, 3 rr.
 template <typename out_t>
@@ -271,6 +295,14 @@ hipError_t launch_arrange(double* xi, const double* rbar, int nx, int ny, int nz
     if (z_identity && lz != nz) return hipErrorInvalidValue;
     hipLaunchKernelGGL(arrange_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, xi, rbar, nx, ny, nz, lx, ly,
                        lz, xcorr, ycorr, (int)z_identity);
+    return hipGetLastError();
+}
+
+hipError_t launch_free_arrange(double* xi, int nx, int ny, int nz, int lx, int ly, int lz, double hx, double hy,
+                              double hz, double g0, hipStream_t st) {
+    const long n = (long)lx * ly * lz;
+    hipLaunchKernelGGL(free_arrange_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, xi, nx, ny, nz, lx, ly, lz,
+                       hx, hy, hz, g0);
     return hipGetLastError();
 }
 

@@ -150,6 +150,7 @@ struct pipe_plan_s {
     size_t table_elems = 0, nyq_elems = 0;
     int tile = 0;            // kz tile of the table layout
     int band = -1;           // banded plan: planes kept each side of the z sum (Eq. 18); -1 = 3-D plan
+    double g0 = 0;           // free-space plans: G at zero separation
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
     double tune_ms = -1;     // autotuner: best candidate's time per solve, 0 if cached, -1 if not tuned
@@ -194,12 +195,19 @@ void plan_pass_bytes(const pipe_plan_s* p, double out[5]) {
     out[4] = a1 + phys;
 }
 
+// free_space: the Eq. 5 plan (no pipe: a, b, offsets and modes are not used).
 pipe_status_t validate(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b, double x0,
-                       double y0, int kind, int mx, int my, int* lx, int* ly, int* lz) {
+                       double y0, int kind, int mx, int my, int* lx, int* ly, int* lz, bool free_space = false) {
     if (nx < 1 || ny < 1 || nz < 1) return fail(PIPE_ERR_INVALID_ARG, "mesh sizes must be >= 1 (got %d,%d,%d)", nx, ny, nz);
-    const double v[5] = {hx, hy, hz, a, b};
+    const double v[5] = {hx, hy, hz, free_space ? 1.0 : a, free_space ? 1.0 : b};
     for (double t : v)
         if (!(t > 0.0) || !std::isfinite(t)) return fail(PIPE_ERR_INVALID_ARG, "spacings and pipe sizes must be finite and > 0");
+    if (free_space) {
+        x0 = y0 = 0.0;
+        a = nx * hx;
+        b = ny * hy;
+        mx = my = 1;
+    }
     if (!(x0 >= 0.0) || !(y0 >= 0.0) || !std::isfinite(x0) || !std::isfinite(y0))
         return fail(PIPE_ERR_INVALID_ARG, "mesh offsets must be finite and >= 0");
     if (x0 + nx * hx > a * (1.0 + 1e-12))
@@ -207,7 +215,9 @@ pipe_status_t validate(int nx, int ny, int nz, double hx, double hy, double hz, 
     if (y0 + ny * hy > b * (1.0 + 1e-12))
         return fail(PIPE_ERR_INVALID_ARG, "y0 + ny*hy = %g exceeds the pipe height b = %g", y0 + ny * hy, b);
     const int g = kind & 0x0f, pr = kind & ~0x0f;
-    if (g != PIPE_GREEN_POINT && g != PIPE_GREEN_IGF_Z) return fail(PIPE_ERR_INVALID_ARG, "unknown Green kind %d", g);
+    if (free_space ? g != PIPE_GREEN_FREE : (g != PIPE_GREEN_POINT && g != PIPE_GREEN_IGF_Z))
+        return fail(PIPE_ERR_INVALID_ARG, g == PIPE_GREEN_FREE ? "free-space plans are made by pipe_free_plan"
+                                                               : "unknown Green kind %d", g);
     if (pr != PIPE_PREC_FP64 && pr != PIPE_PREC_FP32) return fail(PIPE_ERR_INVALID_ARG, "unknown precision flag 0x%x", pr);
     if (mx < 1 || my < 1 || mx > 8192 || my > 8192) return fail(PIPE_ERR_INVALID_ARG, "mode counts must be in [1, 8192]");
     // padded lengths
@@ -242,7 +252,29 @@ struct Scratch {
     }
 };
 
+// Eq. 5: one term, G = 1/r arranged straight into the padded array.
+pipe_status_t build_free_spectra(pipe_plan_s* p, hipStream_t st) {
+    const int lx = p->lx, ly = p->ly, lz = p->lz, nh = p->nh;
+    Scratch s;
+    double* buf;
+    HIP_TRY(s.get((void**)&buf, sizeof(double) * (size_t)lx * ly * lz), "allocation (spectrum buffer)");
+    HIP_TRY(launch_free_arrange(buf, p->nx, p->ny, p->nz, lx, ly, lz, p->hx, p->hy, p->hz, p->g0, st),
+            "Green arrangement");
+    HIP_TRY(launch_z_r2c<double>(nh, buf, lz, lz, buf, nh, (long)lx * ly, p->ctx->tw, st), "spectra z transform");
+    HIP_TRY(launch_strided<double>(ly, false, buf, buf, ly, ly, nh, nh, nh, (long)ly * nh, (long)ly * nh, lx,
+                                   p->ctx->tw, st),
+            "spectra y transform");
+    HIP_TRY(launch_strided<double>(lx, false, buf, buf, lx, lx, (long)ly * nh, (long)ly * nh, (long)ly * nh, 0, 0, 1,
+                                   p->ctx->tw, st),
+            "spectra x transform");
+    // only T_cc: the other terms' planes of the (zeroed) table stay zero
+    HIP_TRY(launch_compress(buf, p->table, p->nyq, p->rb, 0, lx, ly, nh, p->tile, st), "spectra compression");
+    HIP_TRY(hipStreamSynchronize(st), "plan build");
+    return PIPE_OK;
+}
+
 pipe_status_t build_spectra(pipe_plan_s* p, hipStream_t st, bool keep_green) {
+    if ((p->kind & 0x0f) == PIPE_GREEN_FREE) return build_free_spectra(p, st);
     // Rbar rows: nx differences then 2nx - 1 sums along x, likewise along y
     const int px = 3 * p->nx - 1, qy = 3 * p->ny - 1, rz = p->nz;
     const int lx = p->lx, ly = p->ly, lz = p->lz, nh = p->nh;
@@ -667,17 +699,21 @@ const char* pipe_status_string(pipe_status_t s) {
 
 const char* pipe_last_error(void) { return g_err.c_str(); }
 
-pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b,
-                                     double x0, double y0, int kind, int mx, int my, int lx, int ly, int lz,
-                                     void* hip_stream, pipe_plan_t* out) {
+namespace {
+
+pipe_status_t create_plan(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b, double x0,
+                          double y0, int kind, int mx, int my, int lx, int ly, int lz, bool free_space, double g0,
+                          void* hip_stream, pipe_plan_t* out) {
     if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
     *out = nullptr;
     const bool keep = (kind & PIPE_KEEP_GREEN) != 0;
     const bool tune = (kind & (PIPE_AUTOTUNE | PIPE_AUTOTUNE_BATCH)) != 0 && lx == 0 && ly == 0 && lz == 0;
     const int tune_members = (kind & PIPE_AUTOTUNE_BATCH) ? 16 : 1;
     kind &= 0xff;
-    pipe_status_t s = validate(nx, ny, nz, hx, hy, hz, a, b, x0, y0, kind, mx, my, &lx, &ly, &lz);
+    pipe_status_t s = validate(nx, ny, nz, hx, hy, hz, a, b, x0, y0, kind, mx, my, &lx, &ly, &lz, free_space);
     if (s != PIPE_OK) return s;
+    if (free_space && !std::isfinite(g0)) return fail(PIPE_ERR_INVALID_ARG, "g0 must be finite");
+    if (free_space && keep) return fail(PIPE_ERR_INVALID_ARG, "free-space plans keep no Green table");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev < 1) return fail(PIPE_ERR_NO_DEVICE, "no HIP device available");
@@ -700,7 +736,7 @@ pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double h
     p->nx = nx; p->ny = ny; p->nz = nz; p->lx = lx; p->ly = ly; p->lz = lz; p->nh = lz / 2;
     p->mx = mx; p->my = my; p->kind = kind; p->rb = (kind & PIPE_PREC_FP32) ? 4 : 8;
     p->hx = hx; p->hy = hy; p->hz = hz; p->a = a; p->b = b;
-    p->x0 = x0; p->y0 = y0;
+    p->x0 = x0; p->y0 = y0; p->g0 = g0;
     p->device = dev; p->ctx = ctx;
     const size_t orbits = (size_t)(lx / 2 + 1) * (ly / 2 + 1);
     p->tile = xprod_tile(lx, p->rb);
@@ -725,6 +761,21 @@ pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double h
     reg_add(p);
     *out = p;
     return PIPE_OK;
+}
+
+}  // namespace
+
+pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b,
+                                     double x0, double y0, int kind, int mx, int my, int lx, int ly, int lz,
+                                     void* hip_stream, pipe_plan_t* out) {
+    return create_plan(nx, ny, nz, hx, hy, hz, a, b, x0, y0, kind, mx, my, lx, ly, lz, false, 0.0, hip_stream, out);
+}
+
+pipe_status_t pipe_free_plan(int nx, int ny, int nz, double hx, double hy, double hz, double g0, int kind, int lx,
+                             int ly, int lz, void* hip_stream, pipe_plan_t* out) {
+    if ((kind & 0x0f) != 0) return fail(PIPE_ERR_INVALID_ARG, "pipe_free_plan takes precision and autotune flags only");
+    return create_plan(nx, ny, nz, hx, hy, hz, 0.0, 0.0, 0.0, 0.0, kind | PIPE_GREEN_FREE, 0, 0, lx, ly, lz, true, g0,
+                       hip_stream, out);
 }
 
 pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b,
@@ -786,7 +837,7 @@ pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     out->mx = p->mx; out->my = p->my; out->kind = p->kind; out->real_bytes = p->rb;
     out->hx = p->hx; out->hy = p->hy; out->hz = p->hz; out->a = p->a; out->b = p->b;
     out->x0 = p->x0; out->y0 = p->y0;
-    out->norm = 1.0 / (2.0 * M_PI * p->a * p->b);
+    out->norm = (p->kind & 0x0f) == PIPE_GREEN_FREE ? 1.0 : 1.0 / (2.0 * M_PI * p->a * p->b);
     out->workspace_bytes = p->ws_bytes;
     out->spectra_bytes = (p->table_elems + p->nyq_elems) * p->rb;
     plan_pass_bytes(p, out->pass_bytes);
@@ -888,6 +939,40 @@ pipe_status_t pipe_plan_spectra(pipe_plan_t p, void* out, void* stream) {
         HIP_TRY(launch_untile(p->table, p->nyq, out, p->rb, p->lx, p->ly, p->nh, p->tile, st), "spectra copy");
     HIP_TRY(hipStreamSynchronize(st), "spectra copy");
     return PIPE_OK;
+}
+
+pipe_status_t pipe_fft3d(int real_bytes, int n0, int n1, int n2, const char* dirs, const void* in, void* out,
+                         void* stream) {
+    if (real_bytes != 4 && real_bytes != 8) return fail(PIPE_ERR_INVALID_ARG, "real_bytes must be 4 or 8");
+    if (!dirs || strlen(dirs) != 3) return fail(PIPE_ERR_INVALID_ARG, "dirs must be three characters");
+    for (int i = 0; i < 3; ++i)
+        if (dirs[i] != 'f' && dirs[i] != 'b') return fail(PIPE_ERR_INVALID_ARG, "dirs[%d] must be 'f' or 'b'", i);
+    if (n0 < 1 || n1 < 1 || n2 < 1) return fail(PIPE_ERR_INVALID_ARG, "sizes must be >= 1");
+    const int n[3] = {n0, n1, n2};
+    for (int i = 0; i < 3; ++i)
+        if (!fft_length_ok(n[i])) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "length %d not supported", n[i]);
+    if (!in || !out) return fail(PIPE_ERR_INVALID_ARG, "null pointer");
+    const size_t bytes = (size_t)n0 * n1 * n2 * 2 * real_bytes;
+    if (in != out && overlaps(in, bytes, out, bytes)) return fail(PIPE_ERR_ALIASING, "in and out overlap");
+    int ndev = 0, dev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PIPE_ERR_NO_DEVICE, "no HIP device available");
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    DeviceCtx* ctx = nullptr;
+    pipe_status_t s = device_ctx(dev, &ctx);
+    if (s != PIPE_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const long plane = (long)n1 * n2;
+    // last dimension: contiguous lines (in -> out); then the other two in place on out
+    auto run = [&](auto zero) -> pipe_status_t {
+        using real = decltype(zero);
+        HIP_TRY(launch_lines<real>(n2, dirs[2] == 'b', in, out, (long)n0 * n1, ctx->tw, st), "fft3d dimension 2");
+        HIP_TRY(launch_strided<real>(n1, dirs[1] == 'b', out, out, n1, n1, n2, n2, n2, plane, plane, n0, ctx->tw, st),
+                "fft3d dimension 1");
+        HIP_TRY(launch_strided<real>(n0, dirs[0] == 'b', out, out, n0, n0, plane, plane, plane, 0, 0, 1, ctx->tw, st),
+                "fft3d dimension 0");
+        return PIPE_OK;
+    };
+    return real_bytes == 8 ? run(0.0) : run(0.0f);
 }
 
 pipe_status_t pipe_fft_lines(int real_bytes, int len, int n_in, int howmany, int dir, const void* in, void* out,

@@ -76,6 +76,10 @@ hipError_t launch_gemm_f64(const double* A, const double* B, double* C, int M, i
 // z_identity (lz == nz): slot s holds plane distance s (banded spectra).
 hipError_t launch_arrange(double* xi, const double* rbar, int nx, int ny, int nz, int lx, int ly,
                           int lz, int xcorr, int ycorr, hipStream_t st, bool z_identity = false);
+// Free-space (Eq. 5) Green array into xi[lx][ly][lz]: 1/r at the convolution
+// slots, g0 at zero distance.
+hipError_t launch_free_arrange(double* xi, int nx, int ny, int nz, int lx, int ly, int lz, double hx, double hy,
+                              double hz, double g0, hipStream_t st);
 hipError_t launch_compress(const void* spec, void* table, void* nyq, int real_bytes, int term,
                            int lx, int ly, int nh, int tile, hipStream_t st);
 hipError_t launch_untile(const void* table, const void* nyq, void* out, int real_bytes, int lx, int ly, int nh,
@@ -113,5 +117,12 @@ hipError_t launch_compress_band(const void* spec, double* tmp, int term, int lx,
 // precision) from the staging table once all four terms are in.
 hipError_t launch_band_coefficients(const double* tmp, void* table, int real_bytes, int lx, int ly, int D,
                                     hipStream_t st);
+
+// Batched contiguous complex lines (fft3d.hip): nlines lines of length n at
+// in + l n, out + l n (in == out allowed), forward (W^{jk}) or inverse (W^{-jk}),
+// unscaled.
+template <typename real>
+hipError_t launch_lines(int n, bool inverse, const void* in, void* out, long nlines, const TwiddleBank& tw,
+                        hipStream_t s);
 
 }  // namespace pipe

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpipe.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pipe_poisson.h")
 
-POINT, IGF_Z = 0, 1
+POINT, IGF_Z, FREE = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0x00, 0x10
 KEEP_GREEN = 0x100
 AUTOTUNE = 0x200
@@ -76,6 +76,8 @@ def lib():
                                     ctypes.POINTER(_P)], _I),
         "pipe_green_plan_banded": ([_I, _I, _I, _D, _D, _D, _D, _D, _D, _D, _I, _I, _I, _I, _I, _I, _D, _P,
                                     ctypes.POINTER(_P)], _I),
+        "pipe_free_plan": ([_I, _I, _I, _D, _D, _D, _D, _I, _I, _I, _I, _P, ctypes.POINTER(_P)], _I),
+        "pipe_fft3d": ([_I, _I, _I, _I, ctypes.c_char_p, _P, _P, _P], _I),
         "pipe_plan_info": ([_P, ctypes.POINTER(PlanInfo)], _I),
         "pipe_poisson_solve": ([_P, _P, _P, _P, _P], _I),
         "pipe_poisson_adjoint": ([_P, _P, _P, _P, _P], _I),
@@ -272,6 +274,45 @@ class GreenPlan:
                 self._h = None
         except Exception:
             pass
+
+
+class FreePlan(GreenPlan):
+    """Free-space (isolated) plan: Hockney's zero-padded convolution with G = 1/r
+    (pipe_free_plan, Sec. 1 Eq. 3-5); g0 is the value used at zero separation.
+    Solves, adjoints, batches and timing work as for GreenPlan."""
+
+    def __init__(self, nx, ny, nz, hx, hy, hz, g0, precision="fp64", L=None, autotune=False, stream=None):
+        flags = (PREC_FP32 if precision == "fp32" else PREC_FP64)
+        flags |= {False: 0, True: AUTOTUNE, "batch": AUTOTUNE_BATCH}[autotune]
+        lx, ly, lz = L if L is not None else (0, 0, 0)
+        h = _P()
+        st = _stream_ptr(stream) if stream is not None else None
+        check(lib().pipe_free_plan(nx, ny, nz, hx, hy, hz, float(g0), flags, lx, ly, lz, st, ctypes.byref(h)))
+        self._h = h
+        info = PlanInfo()
+        check(lib().pipe_plan_info(h, ctypes.byref(info)))
+        self.info = info
+        self.shape = (nx, ny, nz)
+        self.dtype = _dtype(info.real_bytes)
+        self._ws = None
+
+
+def fft3d(x, dirs, out=None, stream=None):
+    """Unscaled 3-D DFT of a complex CUDA tensor with a direction per dimension
+    (pipe_fft3d): dirs[d] = 'f' sums a_n W^{nk}, 'b' sums a_n W^{-nk},
+    W = e^{-2 pi i/N}.  out may be x itself (in place)."""
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dim() != 3:
+        raise TypeError("expected a 3-D CUDA tensor")
+    if x.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("expected complex64 or complex128")
+    x = x.contiguous()
+    if out is None:
+        out = torch.empty_like(x)
+    rb = 8 if x.dtype == torch.complex128 else 4
+    check(lib().pipe_fft3d(rb, x.shape[0], x.shape[1], x.shape[2], dirs.encode(), _P(x.data_ptr()),
+                           _P(out.data_ptr()), _stream_ptr(stream)))
+    return out
 
 
 class Batch:

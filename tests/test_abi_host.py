@@ -156,3 +156,52 @@ def test_banded_plan_rejects_bad_geometry():
     st = L.pipe_green_plan_banded(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0.0, 0.0, 0, 8, 8, 10, 0, 1, 0.0, None,
                                   ctypes.byref(h))
     assert st == 2 and not h.value
+
+
+@needs_lib
+@pytest.mark.parametrize("args,expect", [
+    ((0, 4, 4, 0.1, 0.1, 0.1, 1.0, 0x00), 1),                 # n < 1
+    ((4, 4, 4, 0.0, 0.1, 0.1, 1.0, 0x00), 1),                 # h <= 0
+    ((4, 4, 4, 0.1, 0.1, 0.1, float("nan"), 0x00), 1),        # g0 not finite
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 0x01), 1),                 # a Green kind in the low nibble
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 0x100), 1),                # keep-green
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 0x20), 1),                 # unknown precision
+])
+def test_free_plan_validation(args, expect):
+    L = pipe.lib()
+    h = ctypes.c_void_p()
+    st = L.pipe_free_plan(*args, 0, 0, 0, None, ctypes.byref(h))
+    assert st == expect and not h.value, L.pipe_last_error().decode()
+
+
+@needs_lib
+def test_free_plan_reaches_the_device_check():
+    if _has_device():
+        pytest.skip("would build a plan on the device")
+    L = pipe.lib()
+    h = ctypes.c_void_p()
+    assert L.pipe_free_plan(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 0x10, 0, 0, 0, None, ctypes.byref(h)) == 4
+    # a free-space kind through the pipe entry point is refused
+    assert L.pipe_green_plan_ex(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 2, 8, 8, 0, 0, 0, None, ctypes.byref(h)) == 1
+
+
+@needs_lib
+@pytest.mark.parametrize("rb,n,dirs,same,expect", [
+    (2, (8, 8, 8), b"fff", False, 1),          # real_bytes
+    (8, (8, 8, 8), b"ff", False, 1),           # two directions
+    (8, (8, 8, 8), b"fxf", False, 1),          # bad character
+    (8, (8, 10, 8), b"fff", False, 2),         # unsupported length
+    (8, (0, 8, 8), b"fff", False, 1),          # empty
+])
+def test_fft3d_validation(rb, n, dirs, same, expect):
+    L = pipe.lib()
+    buf = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p(0x1000 if same else 0x10000000)
+    assert L.pipe_fft3d(rb, *n, dirs, buf, out, None) == expect
+
+
+@needs_lib
+def test_fft3d_rejects_partial_overlap():
+    L = pipe.lib()
+    a, b = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x100000 + 16)
+    assert L.pipe_fft3d(8, 8, 8, 8, b"fff", a, b, None) == 6
