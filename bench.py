@@ -287,6 +287,31 @@ def band_leg(pipe, torch, steps=50, tol=1e-6):
     return res
 
 
+def free_leg(pipe, torch, wl, steps=100):
+    """Sec. 1, Eq. 5: the free-space (Hockney) solve on the benchmark's mesh and
+    charge (G = 1/r, zero at zero separation), beside the pipe solve: the same
+    five passes with a one-term spectrum."""
+    res = {}
+    for prec in ("fp32", "fp64"):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        x = torch.from_numpy(wl.rho).to("cuda", dt)
+        log("[bench] free space %s: plan" % prec)
+        plan = pipe.FreePlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, 0.0, precision=prec)
+        y = torch.empty_like(x)
+        ws = plan.workspace()
+        for _ in range(10):
+            plan.solve(x, out=y, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            plan.solve(x, out=y, workspace=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / steps * 1e3
+        res[prec] = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms, "build_ms": plan.info.build_ms}
+        plan.close()
+    return res
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -391,6 +416,9 @@ def main():
         log("[bench] subregion: %.1fx faster than the full cross-section, max rel diff %.1e" % (
             res["subregion"]["speedup_subregion_over_full"], res["subregion"]["rel_max_diff_on_shared_nodes"]))
     if not args.no_batch:
+        res["free_space"] = free_leg(pipe, torch, wl)
+        log("[bench] free space: %.4f ms (FP32), %.4f ms (FP64) per solve" % (
+            res["free_space"]["fp32"]["ms_per_solve"], res["free_space"]["fp64"]["ms_per_solve"]))
         res["banded"] = band_leg(pipe, torch)
         for k, v in res["banded"].items():
             if not isinstance(v, dict):
