@@ -34,7 +34,10 @@ def _plan(shape, prec, kind, band, **kw):
 # (shape, N, offset): nz spans several 16-plane tiles with a ragged tail; N = 20
 # needs four chunks of input planes per tile; N = nz - 1 is the full z sum.
 CASES = [((6, 5, 12), 0, (0.0, 0.0)), ((9, 7, 20), 1, (0.0, 0.0)), ((13, 10, 33), 3, (0.2, 0.1)),
-         ((6, 5, 40), 20, (0.0, 0.0)), ((5, 6, 9), 8, (0.0, 0.0))]
+         ((6, 5, 40), 20, (0.0, 0.0)), ((5, 6, 9), 8, (0.0, 0.0)),
+         # degenerate: one node, one plane, two planes, one node across x
+         ((1, 1, 1), 0, (0.0, 0.0)), ((4, 3, 1), 0, (0.0, 0.0)), ((3, 4, 2), 1, (0.0, 0.0)),
+         ((1, 5, 7), 2, (0.0, 0.0))]
 
 
 @pytest.mark.parametrize("kind", [0, 1])

@@ -28,7 +28,9 @@ def torch_cuda():
 @pytest.mark.parametrize("shape,h,g0,L", [((9, 7, 12), (0.1, 0.12, 0.08), 0.0, None),
                                           ((16, 10, 24), (0.05, 0.07, 0.04), 25.0, None),
                                           ((20, 13, 40), (0.03, 0.03, 0.06), 40.0, (48, 32, 96)),
-                                          ((5, 6, 7), (0.2, 0.2, 0.2), 3.0, (12, 12, 16))])
+                                          ((5, 6, 7), (0.2, 0.2, 0.2), 3.0, (12, 12, 16)),
+                                          ((1, 1, 1), (0.1, 0.1, 0.1), 4.0, None),
+                                          ((3, 1, 2), (0.1, 0.2, 0.3), 4.0, None)])
 def test_free_matches_eq5_oracle(torch_cuda, prec, shape, h, g0, L):
     from oracle import free
     from paper_1111_4971_amd import pipe

@@ -20,6 +20,10 @@ SHAPES = [
     (9, 20, 33, 2.0, 1.0, False),      # odd nz, ragged kz tail
     (16, 16, 16, 1.0, 1.0, True),
     (24, 12, 70, 1.5, 1.0, True),      # radix-3 lengths (48, 24, 96)
+    (1, 1, 1, 1.0, 1.0, True),         # degenerate: one node
+    (1, 7, 9, 1.0, 1.2, False),        # one node across x
+    (6, 1, 12, 1.3, 1.0, True),        # one node across y
+    (4, 5, 1, 1.0, 1.0, False),        # a single plane
 ]
 
 
