@@ -1,6 +1,6 @@
 """Free-space (isolated) Poisson solve by Hockney's zero-padded FFT convolution (oracle; test infrastructure only).
 
-Sec. 2, Eq. 3-5: with the 4 pi (and epsilon_0) dropped, the isolated Green
+Sec. 1, Eq. 3-5: with the 4 pi (and epsilon_0) dropped, the isolated Green
 function is G(u, v, w) = 1 / sqrt(u^2 + v^2 + w^2) and the discretised
 potential (Eq. 4 with G depending on differences only) is
 
