@@ -168,3 +168,24 @@ def test_eq6_on_the_gpu(torch_cuda):
     g = pipe.fft3d(torch.tensor(garr, device="cuda", dtype=torch.complex128), "fbf")
     out = pipe.fft3d(r * g, "bfb").cpu().numpy() / np.prod(L)
     assert np.max(np.abs(out[:nx, :ny, :nz].real - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.fixture(scope="module")
+def three_bunch():
+    from paper_1111_4971_amd import workloads
+    return workloads.three_bunch_cic()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_free_benchmark_mesh_full_field(torch_cuda, three_bunch, prec):
+    """The bench's free-space leg: 128 x 128 x 512 three-bunch charge, G(0) = 0,
+    against the oracle's Eq. 5 on the whole field."""
+    from oracle import free
+    from paper_1111_4971_amd import pipe
+    wl = three_bunch
+    h = (wl.hx, wl.hy, wl.hz)
+    log("free 128x128x512 %s" % prec)
+    got = gpu_solve(pipe.FreePlan(wl.nx, wl.ny, wl.nz, *h, 0.0, precision=prec), wl.rho)
+    log("free 128x128x512 %s: oracle" % prec)
+    ref = free.solve_fft(oracle_input(wl.rho, prec), h, 0.0)
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec]
