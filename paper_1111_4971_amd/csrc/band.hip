@@ -381,6 +381,137 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
         view);
 }
 
+// Small N: the whole input window of a block -- `to` output columns plus the
+// halo, to + N + (N odd) <= T packed columns -- is one transform chunk, so all
+// transforms finish before the products start and the accumulators are never
+// live together with a transform's registers.  Same block shape as the N = 0
+// pass (T packed columns of the lines ky, -ky, padded LDS columns so the
+// orbit-wise product reads are conflict-free); the coefficients of each plane
+// distance are read from global memory, coalesced over orbits.
+template <typename real, int N>
+__global__ __launch_bounds__((2 * (N / Plan<N>::E) * band0_T<real, N>()))
+void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz,
+                   int nb, int to, const real* __restrict__ table, const cplx<real>* __restrict__ tw) {
+    using C = cplx<real>;
+    constexpr int T = band0_T<real, N>(), TS = T + 1;
+    constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NH = N / 2, NKX = NH + 1;
+    constexpr int IM = (NH * T + NT - 1) / NT;   // (orbit < N/2, output column) items per thread, at most
+    __shared__ C lds[2 * N * TS];
+    __shared__ C s_tw[N];
+    tw = stage_twiddles(s_tw, tw, N);
+    const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
+    const unsigned ntile = gridDim.x;
+    const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
+    const int tile = (int)(lid % ntile);
+    const int ky = (int)(lid / ntile);
+    const int kyl = l == 0 ? ky : (ly - ky) % ly;
+    const bool self = (ky == 0) || (2 * ky == ly);
+    const int nzp = (nz + 1) / 2;
+    const int z0 = 2 * to * tile;
+    const long xs = (long)ly * nzp;
+    const real* trow = table + (long)ky * (nb + 1) * 10 * NKX;
+    LdsCol<C, TS> view{lds + l * N * TS + c};
+
+    // the window: packed columns pbase .. pbase + ncolp - 1 (ncolp <= T)
+    const int pbase = floor_half(z0 - nb);
+    const int ncolp = floor_half(z0 + 2 * to - 1 + nb) - pbase + 1;
+    {
+        const int pc = pbase + c;
+        const bool act = c < ncolp && pc >= 0 && pc < nzp;
+        const C* line = in + (act ? (long)kyl * nzp + pc : 0);
+        fft_line<N, false, false>(
+            t, tw, [&](int e) -> C { return (act && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
+            [&](int e, C v) { view.set(e, v); }, view);
+    }
+    __syncthreads();
+    // split every column into 2 R_even (line 0) and 2 R_odd (line 1) at slots o, -o
+    for (int w = threadIdx.x; w < NKX * T; w += NT) {
+        const int o = w % NKX, j = w / NKX, on = (N - o) % N;
+        const C f0 = lds[o * TS + j], f1 = lds[on * TS + j];
+        const C g0 = lds[(N + o) * TS + j], g1 = lds[(N + on) * TS + j];
+        const C u0 = csub(f0, cconj(g1)), u1 = csub(f1, cconj(g0));
+        lds[o * TS + j] = cadd(f0, cconj(g1));
+        lds[(N + o) * TS + j] = cmake<C>(u0.y, -u0.x);
+        if (on != o) {
+            lds[on * TS + j] = cadd(f1, cconj(g0));
+            lds[(N + on) * TS + j] = cmake<C>(u1.y, -u1.x);
+        }
+    }
+    __syncthreads();
+
+    // products: item (o, c2 < to), lanes over o; the orbit o = N/2 of column c2 is thread c2's extra item
+    auto item = [&](int i, int& o, int& c2) {
+        if (i < IM) {
+            const int w = threadIdx.x + i * NT;
+            o = w % NH;
+            c2 = w / NH;
+        } else {
+            o = NH;
+            c2 = threadIdx.x;
+        }
+    };
+    C acc[IM + 1][4];
+#pragma unroll
+    for (int i = 0; i <= IM; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[i][q] = cmake<C>(0, 0);
+    for (int ad = 0; ad <= nb; ++ad) {
+        const real* kp = trow + (long)ad * 10 * NKX;
+#pragma unroll
+        for (int i = 0; i <= IM; ++i) {
+            int o, c2;
+            item(i, o, c2);
+            if (c2 >= to) continue;
+            const int on = (N - o) % N;
+            const int ze = z0 + 2 * c2;
+            real q[10];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) q[m] = kp[m * NKX + o];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((k & 2) && ad == 0) continue;
+                const int z = ze + (k & 1) - ((k & 2) ? -ad : ad);
+                if (z < 0 || z >= nz) continue;
+                const int j = (z >> 1) - pbase, sN = (z & 1) * N;
+                const C x0 = lds[(sN + o) * TS + j], x1 = lds[(sN + on) * TS + j];
+                C& y0 = acc[i][2 * (k & 1)];
+                C& y1 = acc[i][2 * (k & 1) + 1];
+                y0.x += q[0] * x0.x + q[1] * x0.y + q[3] * x1.x + q[4] * x1.y;
+                y0.y += q[1] * x0.x + q[2] * x0.y + q[5] * x1.x + q[6] * x1.y;
+                y1.x += q[3] * x0.x + q[5] * x0.y + q[7] * x1.x + q[8] * x1.y;
+                y1.y += q[4] * x0.x + q[6] * x0.y + q[8] * x1.x + q[9] * x1.y;
+            }
+        }
+    }
+    __syncthreads();   // every product has read the window
+    auto pack = [](C e, C d) { return cmake<C>(e.x - d.y, e.y + d.x); };   // e + i d
+#pragma unroll
+    for (int i = 0; i <= IM; ++i) {
+        int o, c2;
+        item(i, o, c2);
+        if (c2 >= to) continue;
+        const int on = (N - o) % N;
+        const C e0 = acc[i][0], e1 = acc[i][1], d0 = acc[i][2], d1 = acc[i][3];
+        lds[o * TS + c2] = pack(e0, d0);
+        lds[(N + o) * TS + c2] = pack(cconj(e1), cconj(d1));
+        if (on != o) {
+            lds[on * TS + c2] = pack(e1, d1);
+            lds[(N + on) * TS + c2] = pack(cconj(e0), cconj(d0));
+        }
+    }
+    __syncthreads();
+
+    const int pco = to * tile + c;
+    const bool oact = c < to && pco < nzp && !(l == 1 && self);
+    C* oline = out + (oact ? (long)kyl * nzp + pco : 0);
+    fft_line<N, true, true>(
+        t, tw, [&](int e) -> C { return view.get(e); },
+        [&](int e, C v) {
+            if (oact && e < nx) oline[e * xs] = v;
+        },
+        view);
+}
+
 // y pass with real input (forward: rho -> complex) or real output (inverse:
 // complex -> scaled real part), one plane per column (the Green arrangements).
 template <typename real, int N, int T, bool INV>
@@ -540,9 +671,26 @@ static int band_out_columns(int T, int nb) {
     return 2 * to >= T ? to : T;
 }
 
+// Output columns of xband1_kernel (window of to + nb + (nb odd) <= T columns)
+// when that leaves at least a quarter of the tile, else 0 (xband_kernel only).
+static int band_small_columns(int T, int nb) {
+    const int to = T - nb - (nb & 1);
+    return 4 * to >= T && to >= 1 ? to : 0;
+}
+
+int band_small_columns_for(int lx, int real_bytes, int nb) {
+    switch (lx) {
+#define X(N_) \
+    case N_: return band_small_columns(real_bytes == 8 ? band0_T<double, N_>() : band0_T<float, N_>(), nb);
+        PIPE_FOR_EACH_N(X)
+#undef X
+    }
+    return 0;
+}
+
 template <typename real>
 hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
-                        const TwiddleBank& twb, hipStream_t s) {
+                        const TwiddleBank& twb, hipStream_t s, bool single_window) {
     using C = cplx<real>;
     const C* tw = twb.get<C>(lx);
     if (!tw || nb < 0 || nx > lx || nz < 1) return hipErrorInvalidValue;
@@ -556,6 +704,12 @@ hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int n
             dim3 grid((unsigned)((nzp + T - 1) / T), (unsigned)(ly / 2 + 1));                        \
             hipLaunchKernelGGL((xband0_kernel<real, N_>), grid, dim3(2 * P * T), 0, s,               \
                                (const C*)in, (C*)out, nx, ly, nz, table, tw);                        \
+        } else if (single_window && band_small_columns(band0_T<real, N_>(), nb) > 0) {               \
+            constexpr int T = band0_T<real, N_>();                                                   \
+            const int to = band_small_columns(T, nb);                                                \
+            dim3 grid((unsigned)((nzp + to - 1) / to), (unsigned)(ly / 2 + 1));                      \
+            hipLaunchKernelGGL((xband1_kernel<real, N_>), grid, dim3(2 * P * T), 0, s,               \
+                               (const C*)in, (C*)out, nx, ly, nz, nb, to, table, tw);                \
         } else {                                                                                     \
             constexpr int T = band_T<real, N_>();                                                    \
             const int to = band_out_columns(T, nb);                                                  \
@@ -602,7 +756,7 @@ hipError_t launch_band_coefficients(const double* tmp, void* table, int real_byt
     template hipError_t launch_strided_real<real>(int, bool, const void*, void*, int, int, long, long, long, \
                                                   long, long, long, real, const TwiddleBank&, hipStream_t);  \
     template hipError_t launch_xband<real>(int, const void*, void*, int, int, int, int, const real*,         \
-                                           const TwiddleBank&, hipStream_t);
+                                           const TwiddleBank&, hipStream_t, bool);
 PIPE_INST(float)
 PIPE_INST(double)
 #undef PIPE_INST

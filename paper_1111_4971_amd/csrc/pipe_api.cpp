@@ -151,6 +151,7 @@ struct pipe_plan_s {
     int tile = 0;            // kz tile of the table layout
     int band = -1;           // banded plan: planes kept each side of the z sum (Eq. 18); -1 = 3-D plan
     double g0 = 0;           // free-space plans: G at zero separation
+    bool band_single = false; // banded x pass: single-window kernel (else chunked), chosen by timing
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
     double tune_ms = -1;     // autotuner: best candidate's time per solve, 0 if cached, -1 if not tuned
@@ -443,6 +444,50 @@ pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, h
     return PIPE_OK;
 }
 
+// Times the two banded x-pass kernels (on zeroed scratch of the workspace's
+// size: timing does not depend on the values) and keeps the faster.
+// PIPE_BAND_KERNEL=single or =chunked forces one (tests exercise both).
+pipe_status_t choose_band_kernel(pipe_plan_s* p, hipStream_t st) {
+    if (const char* f = std::getenv("PIPE_BAND_KERNEL")) {
+        if (!strcmp(f, "single") || !strcmp(f, "chunked")) {
+            p->band_single = !strcmp(f, "single");
+            return PIPE_OK;
+        }
+    }
+    void* ws = nullptr;
+    HIP_TRY(dev_alloc(&ws, p->ws_bytes), "allocation (band kernel timing)");
+    struct Free {
+        void* q;
+        ~Free() { (void)hipFree(q); }
+    } guard{ws};
+    HIP_TRY(hipMemsetAsync(ws, 0, p->ws_bytes, st), "band kernel timing");
+    const size_t half = p->ws_bytes / 2;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    float best[2] = {0, 0};
+    pipe_status_t s = PIPE_OK;
+    for (int v = 0; v < 2 && s == PIPE_OK; ++v) {
+        auto launch = [&]() -> hipError_t {
+            return p->rb == 8 ? launch_xband<double>(p->lx, ws, (char*)ws + half, p->nx, p->ly, p->nz, p->band,
+                                                     (const double*)p->table, p->ctx->tw, st, v == 1)
+                              : launch_xband<float>(p->lx, ws, (char*)ws + half, p->nx, p->ly, p->nz, p->band,
+                                                    (const float*)p->table, p->ctx->tw, st, v == 1);
+        };
+        hipError_t e = launch();   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&best[v], e0, e1);
+        if (e != hipSuccess) s = hip_fail(e, "band kernel timing");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s == PIPE_OK) p->band_single = best[1] < best[0];
+    return s;
+}
+
 // Banded solve (Eq. 18): three kernels; the timing events of the two absent
 // passes are recorded back to back.
 template <typename real>
@@ -459,7 +504,7 @@ pipe_status_t run_band_passes(pipe_plan_s* p, const void* rho, void* phi, void* 
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
     (void)adjoint;   // the banded coefficient matrices are symmetric: same kernel both ways
-    HIP_TRY(launch_xband<real>(p->lx, A, B, nx, ly, nz, p->band, (const real*)p->table, tw, st),
+    HIP_TRY(launch_xband<real>(p->lx, A, B, nx, ly, nz, p->band, (const real*)p->table, tw, st, p->band_single),
             "x pass with banded product");
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
     // 1/2 undoes the factor 2 of the split in the x pass
@@ -816,6 +861,13 @@ pipe_status_t pipe_green_plan_banded(int nx, int ny, int nz, double hx, double h
         return s;
     }
     p->ws_bytes = plan_ws_bytes(p);
+    if (p->band >= 1 && band_small_columns_for(p->lx, p->rb, p->band) > 0) {
+        s = choose_band_kernel(p, (hipStream_t)hip_stream);
+        if (s != PIPE_OK) {
+            plan_free(p);
+            return s;
+        }
+    }
     p->tune_ms = -1.0;
     p->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     reg_add(p);

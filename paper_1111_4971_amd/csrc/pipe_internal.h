@@ -105,9 +105,14 @@ hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, i
 // ceil(nz/2)) packed complex (distinct buffers); table: the banded
 // coefficients (launch_band_coefficients).  The output carries a factor 2.
 // The coefficient matrices are symmetric, so the adjoint is the same launch.
+// For nb >= 1 two x-pass kernels exist: single_window (the whole input window of
+// a block is one transform chunk, available when band_small_columns_for > 0) and
+// the chunked one; the plan times both and keeps the faster.
 template <typename real>
 hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
-                        const TwiddleBank& tw, hipStream_t s);
+                        const TwiddleBank& tw, hipStream_t s, bool single_window);
+// Output columns per block of the single-window banded x pass, 0 if not available.
+int band_small_columns_for(int lx, int real_bytes, int nb);
 // Packed columns per block of the banded x pass (0 if lx unsupported).
 int band_tile(int lx, int real_bytes);
 // One term's 2-D spectra S[lx][ly][D] (FP64 complex) into the nine-value

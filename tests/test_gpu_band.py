@@ -56,6 +56,24 @@ def test_band_matches_eq18_oracle(torch_cuda, kind, prec, shape, nb, offset):
     assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("variant", ["single", "chunked"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape,nb", [((13, 10, 33), 1), ((9, 7, 20), 2), ((11, 8, 37), 3), ((6, 5, 40), 4),
+                                      ((17, 12, 50), 6)])
+def test_both_x_pass_kernels(torch_cuda, monkeypatch, variant, prec, shape, nb):
+    """The single-window and the chunked x pass (the plan normally keeps the
+    faster) both reproduce the oracle."""
+    from oracle import fourterm
+    monkeypatch.setenv("PIPE_BAND_KERNEL", variant)
+    nx, ny, nz = shape
+    rho = np.random.default_rng(nx + 3 * nz).standard_normal(shape)
+    log("band %s kernel %s shape=%s N=%d" % (prec, variant, shape, nb))
+    plan = _plan(shape, prec, 1, nb)
+    got = gpu_solve(plan, rho)
+    ref = fourterm.solve(oracle_input(rho, prec), *H, A, B, 2 * nx + 3, 2 * ny + 1, 1, band=nb)
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec]
+
+
 def test_band_cut_changes_the_result(torch_cuda):
     """The cut is real: N = 1 differs from N = 2 by far more than rounding."""
     shape = (7, 6, 16)
