@@ -114,9 +114,11 @@ def time_leg(pipe, torch, wl, precision, steps, warmup):
         "plan_build_ms": info.build_ms,
         "model_bytes_per_solve": info.model_bytes,
         "model_GBps_whole_solve": info.model_bytes / (ms_step * 1e-3) / 1e9,
+        "hbm_frac_whole_solve": info.model_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "passes": {PASS_NAMES[i]: {"kernel": KERNEL_NAMES[i], "ms": pass_ms[i],
                                    "model_bytes": info.pass_bytes[i],
-                                   "GBps": info.pass_bytes[i] / (pass_ms[i] * 1e-3) / 1e9}
+                                   "GBps": info.pass_bytes[i] / (pass_ms[i] * 1e-3) / 1e9,
+                                   "hbm_frac": info.pass_bytes[i] / (pass_ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS}
                    for i in range(5)},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
