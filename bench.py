@@ -289,6 +289,41 @@ def band_leg(pipe, torch, steps=50, tol=1e-6):
     return res
 
 
+def same_plan_leg(pipe, torch, wl, members=8, replays=20):
+    """Many charges, one cached Green function (Sec. 2 after Eq. 10: the spectra
+    are computed once and reused): the benchmark plan repeated `members` times
+    in one batch, each member with its own charge (the benchmark charge shifted
+    along z by k planes).  The fused x pass runs the members of one (kz tile, ky)
+    back to back, so the spectra tile comes from L2 for all but the first."""
+    import numpy as np
+    res = {"members": members}
+    for prec in ("fp32", "fp64"):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        log("[bench] same-plan batch %s: plan" % prec)
+        plan = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind,
+                              precision=prec, mx=wl.mx, my=wl.my)
+        rhos = [torch.from_numpy(np.roll(wl.rho, k, axis=2)).to("cuda", dt) for k in range(members)]
+        b = pipe.Batch([plan] * members)
+        outs = [torch.empty_like(r) for r in rhos]
+        ws = b.workspace()
+        for _ in range(3):
+            b.solve(rhos, outs=outs, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(replays):
+            b.solve(rhos, outs=outs, workspace=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / replays * 1e3
+        single = plan.solve(rhos[-1])
+        torch.cuda.synchronize()
+        res[prec] = {"ms_per_batch": ms, "solves_per_s": members * 1e3 / ms,
+                     "last_member_equals_single_solve": bool(torch.equal(outs[-1], single))}
+        del b, outs, ws
+        plan.close()
+        torch.cuda.empty_cache()
+    return res
+
+
 def free_leg(pipe, torch, wl, steps=100):
     """Sec. 1, Eq. 5: the free-space (Hockney) solve on the benchmark's mesh and
     charge (G = 1/r, zero at zero separation), beside the pipe solve: the same
@@ -425,6 +460,10 @@ def main():
         log("[bench] subregion: %.1fx faster than the full cross-section, max rel diff %.1e" % (
             res["subregion"]["speedup_subregion_over_full"], res["subregion"]["rel_max_diff_on_shared_nodes"]))
     if not args.no_batch:
+        res["same_plan_batch"] = same_plan_leg(pipe, torch, wl)
+        log("[bench] same-plan batch of %d: %.0f (FP32) / %.0f (FP64) solves/s" % (
+            res["same_plan_batch"]["members"], res["same_plan_batch"]["fp32"]["solves_per_s"],
+            res["same_plan_batch"]["fp64"]["solves_per_s"]))
         res["free_space"] = free_leg(pipe, torch, wl)
         log("[bench] free space: %.4f ms (FP32), %.4f ms (FP64) per solve" % (
             res["free_space"]["fp32"]["ms_per_solve"], res["free_space"]["fp64"]["ms_per_solve"]))

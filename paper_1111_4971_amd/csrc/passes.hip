@@ -217,24 +217,36 @@ template <typename real, int N, int T, bool ADJ>
 __global__ __launch_bounds__(2 * (N / Plan<N>::E) * T)
 void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restrict__ table,
                   const real* __restrict__ nyq, const cplx<real>* __restrict__ tw,
-                  const GroupArgs* __restrict__ group) {
+                  const GroupArgs* __restrict__ group, int shared_table) {
     using C = cplx<real>;
+    // Logical order of the (kz tile, ky) items: neighbouring kz tiles share
+    // 128-byte lines when T complex values are narrower, so consecutive items
+    // run back to back on one XCD.  When the members of a grouped launch share
+    // one spectra table (one plan, many charges), the member index goes
+    // fastest, so all members of an item read its spectra tile from L2 after
+    // the first; otherwise each member's items stay together.
+    const unsigned ntile = gridDim.x, nmem = gridDim.z, nitem = ntile * gridDim.y;
+    unsigned member, item;
+    if (shared_table) {
+        const unsigned lid = xcd_remap(blockIdx.x + ntile * (blockIdx.y + gridDim.y * blockIdx.z), nitem * nmem);
+        member = lid % nmem;
+        item = lid / nmem;
+    } else {
+        member = blockIdx.z;
+        item = xcd_remap(blockIdx.x + ntile * blockIdx.y, nitem);
+    }
     if (group) {
-        data = (C*)group[blockIdx.z].out;
-        table = (const real*)group[blockIdx.z].table;
-        nyq = (const real*)group[blockIdx.z].nyq;
+        data = (C*)group[member].out;
+        table = (const real*)group[member].table;
+        nyq = (const real*)group[member].nyq;
     }
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T;
     __shared__ C lds[2 * N * T];
     __shared__ C s_tw[N];
     tw = stage_twiddles(s_tw, tw, N);
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
-    // logical (kz tile, ky): neighbouring kz tiles share 128-byte lines when
-    // T * sizeof(complex) < 128, so they are kept on one XCD, back to back
-    const unsigned ntile = gridDim.x;
-    const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
-    const int tile = (int)(lid % ntile);
-    const int ky = (int)(lid / ntile);
+    const int tile = (int)(item % ntile);
+    const int ky = (int)(item / ntile);
     const int kyl = l == 0 ? ky : (ly - ky) % ly;
     const bool self = (ky == 0) || (2 * ky == ly);
     const long kz = (long)tile * T + c;
@@ -412,7 +424,7 @@ int xprod_tile(int lx, int real_bytes) {
 template <typename real>
 hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh, const real* table,
                         const real* nyq, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
-                        int ngroup) {
+                        int ngroup, bool shared_table) {
     using C = cplx<real>;
     const C* tw = twb.get<C>(lx);
     if (!tw) return hipErrorInvalidValue;
@@ -424,10 +436,10 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
         dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1), (unsigned)ngroup);        \
         if (adjoint)                                                                              \
             hipLaunchKernelGGL((xprod_kernel<real, N_, T, true>), grid, dim3(2 * P * T), 0, s,    \
-                               (C*)data, nx, ly, nh, table, nyq, tw, group);                      \
+                               (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);   \
         else                                                                                      \
             hipLaunchKernelGGL((xprod_kernel<real, N_, T, false>), grid, dim3(2 * P * T), 0, s,   \
-                               (C*)data, nx, ly, nh, table, nyq, tw, group);                      \
+                               (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);   \
         return hipGetLastError();                                                                 \
     }
         PIPE_FOR_EACH_N(X)
@@ -445,7 +457,7 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
                                              long, long, long, const TwiddleBank&, hipStream_t,         \
                                              const GroupArgs*, int);                                    \
     template hipError_t launch_xprod<real>(int, bool, void*, int, int, int, const real*, const real*,  \
-                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int);
+                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool);
 PIPE_INST(float)
 PIPE_INST(double)
 #undef PIPE_INST

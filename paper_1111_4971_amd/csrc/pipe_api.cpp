@@ -599,7 +599,8 @@ template <typename real>
 pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, hipStream_t st, bool adjoint,
                          hipEvent_t* ev);
 template <typename real>
-pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al_in, bool al_out, hipStream_t st);
+pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al_in, bool al_out, hipStream_t st,
+                           bool shared_table = false);
 
 // members = 1: time one solve at a time (latency); members > 1: time one grouped
 // launch of that many concurrent solves (throughput, as in a batch).
@@ -1104,7 +1105,9 @@ void batch_free(pipe_batch_s* b) {
 }
 
 template <typename real>
-pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al_in, bool al_out, hipStream_t st) {
+// shared_table: every member solves on the same plan (many charges, one spectra table).
+pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al_in, bool al_out, hipStream_t st,
+                           bool shared_table) {
     const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly, nh = p->nh;
     const TwiddleBank& tw = p->ctx->tw;
     const real scale = (real)0;  // taken from each member's GroupArgs
@@ -1113,7 +1116,8 @@ pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al
     HIP_TRY(launch_strided<real>(ly, false, nullptr, nullptr, ny, ly, nh, nh, nh, (long)ny * nh, (long)ly * nh, nx,
                                  tw, st, args + n, n),
             "grouped y forward pass");
-    HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, nullptr, nullptr, tw, st, args + 2 * n, n),
+    HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, nullptr, nullptr, tw, st, args + 2 * n, n,
+                               shared_table),
             "grouped x pass with spectral product");
     HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, nh, nh, nh, (long)ly * nh, (long)ny * nh, nx,
                                  tw, st, args + 3 * n, n),
@@ -1255,15 +1259,16 @@ pipe_status_t pipe_batch_solve(pipe_batch_t b, const void* const* rho, void* con
                 hipStream_t st = b->streams[k];
                 ce = hipStreamWaitEvent(st, b->events[0], 0);
                 if (ce != hipSuccess) break;
-                bool al_in = true, al_out = true;
+                bool al_in = true, al_out = true, shared = true;
                 for (int i : g.members) {
                     al_in = al_in && ((uintptr_t)rho[i] % (2 * b->rb) == 0);
                     al_out = al_out && ((uintptr_t)phi[i] % (2 * b->rb) == 0);
+                    shared = shared && b->plans[i] == b->plans[g.members[0]];
                 }
                 const GroupArgs* args = b->dargs + b->args_off[k];
                 const int m = (int)g.members.size();
-                s = b->rb == 8 ? launch_group<double>(g.rep, args, m, al_in, al_out, st)
-                               : launch_group<float>(g.rep, args, m, al_in, al_out, st);
+                s = b->rb == 8 ? launch_group<double>(g.rep, args, m, al_in, al_out, st, shared && m > 1)
+                               : launch_group<float>(g.rep, args, m, al_in, al_out, st, shared && m > 1);
                 if (s != PIPE_OK) break;
                 ce = hipEventRecord(b->events[k + 1], st);
                 if (ce == hipSuccess) ce = hipStreamWaitEvent(b->cap, b->events[k + 1], 0);

@@ -53,9 +53,11 @@ hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_
                           const TwiddleBank& tw, hipStream_t s, const GroupArgs* group = nullptr,
                           int ngroup = 1);
 template <typename real>
+// shared_table (grouped launches whose members all use one plan's spectra):
+// members of one (kz tile, ky) item run back to back, so the tile is read once.
 hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh,
                         const real* table, const real* nyq, const TwiddleBank& tw, hipStream_t s,
-                        const GroupArgs* group = nullptr, int ngroup = 1);
+                        const GroupArgs* group = nullptr, int ngroup = 1, bool shared_table = false);
 
 // kz tile width of the fused x pass for padded length lx (0 if unsupported).
 // The Green spectra are stored tile-blocked to match: for orbit row kyo, kz tile

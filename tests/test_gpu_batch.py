@@ -103,3 +103,20 @@ def test_batch_rejects_bad_arguments(torch_cuda, batch_setup):
     assert L.pipe_batch_solve(b._h, ra, pa, ctypes.c_void_p(ws.data_ptr()), None) == 6
     b.close()
     assert L.pipe_batch_destroy(h) == 1
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_same_plan_many_charges(torch_cuda, prec):
+    """A batch holding one plan several times (many charges, one cached Green
+    function): every member equals that plan's single solve."""
+    torch = torch_cuda
+    from paper_1111_4971_amd import pipe
+    plan = pipe.GreenPlan(24, 20, 48, 1.0 / 25, 1.0 / 21, 0.05, 1.0, 1.0, kind=pipe.IGF_Z, precision=prec)
+    rng = np.random.default_rng(77)
+    rhos = [torch.tensor(rng.standard_normal(plan.shape), device="cuda", dtype=plan.dtype) for _ in range(5)]
+    log("same plan x5 %s" % prec)
+    outs = pipe.Batch([plan] * 5).solve(rhos)
+    torch.cuda.synchronize()
+    for r, o in zip(rhos, outs):
+        ref = plan.solve(r)
+        assert torch.equal(o, ref)
