@@ -264,7 +264,19 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     constexpr int NKX = N / 2 + 1;
     const int ntiles = (nh + T - 1) / T;
     const real* tblock = table + ((long)kyo * ntiles + tile) * NKX * 9 * T;
-    for (int w = threadIdx.x; w < NKX * T; w += NT) {
+    // this thread's items w = threadIdx.x + it NT: their spectra are loaded
+    // together, before the first product, so the loads overlap
+    constexpr int IT = (NKX * T + NT - 1) / NT;
+    Orbit<real> obs[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int w = threadIdx.x + it * NT;
+        if (w < NKX * T) obs[it] = load_orbit(tblock + (long)(w / T) * 9 * T + w % T, T);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int w = threadIdx.x + it * NT;
+        if (w >= NKX * T) break;
         const int cc = w % T, o = w / T;
         const long kzz = (long)tile * T + cc;
         if (kzz >= nh) continue;
@@ -273,7 +285,7 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
         C* L1 = lds + N * T + cc;
         C r[4] = {L0[o * T], L0[on * T], L1[o * T], L1[on * T]};
         C p[4];
-        const Orbit<real> ob = load_orbit(tblock + (long)o * 9 * T + cc, T);
+        const Orbit<real>& ob = obs[it];
         if (kzz != 0) {
             orbit_product<ADJ>(ob, r, p);
         } else {
