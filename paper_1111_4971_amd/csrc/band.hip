@@ -14,7 +14,8 @@
 // are packed the same way before the inverse transforms.
 //
 //   B1 y forward of packed pairs, rho -> A (nx, ly, ceil(nz/2)) complex  [strided_pair_kernel<fwd>]
-//   B2 x forward, split, banded product, pack, x inverse, A -> B         [xband_kernel]
+//   B2 x forward, split, banded product, pack, x inverse, A -> B         [xband0_kernel (N = 0),
+//                                                                         xband1_kernel / xband_kernel]
 //   B3 y inverse, unpack to the real planes, scaled                      [strided_pair_kernel<inv>]
 #include "pass_common.h"
 
