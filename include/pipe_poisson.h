@@ -160,8 +160,9 @@ pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double h
  * B(d) = sum over the kept modes (m, n) of |the mode's z factor at d hz|
  * times the Eq. 9 prefactor, an upper bound on |R| over the cross-section at
  * that distance.  tol must then be in (0, 1).  Other arguments, ownership and
- * errors as pipe_green_plan_region; PIPE_AUTOTUNE flags are ignored.  Banded
- * plans cannot join a batch (pipe_batch_create returns INVALID_ARG).
+ * errors as pipe_green_plan_region; PIPE_AUTOTUNE flags are ignored.  In a
+ * batch (pipe_batch_create) a banded plan runs its own three passes inside the
+ * captured graph rather than in grouped launches.
  */
 pipe_status_t pipe_green_plan_banded(int nx, int ny, int nz, double hx, double hy, double hz,
                                      double a, double b, double x0, double y0, int kind, int mx, int my,

@@ -1067,6 +1067,7 @@ struct pipe_batch_s {
     struct Group {
         std::vector<int> members;
         pipe_plan_t rep;   // representative plan (sizes, lengths, precision)
+        bool banded = false;   // one banded plan: its own three passes, not grouped launches
     };
     std::vector<pipe_plan_t> plans;
     std::vector<Group> groups;
@@ -1137,8 +1138,6 @@ pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_
     if (!plans || count < 1) return fail(PIPE_ERR_INVALID_ARG, "need at least one plan");
     for (int i = 0; i < count; ++i)
         if (!reg_has(plans[i])) return fail(PIPE_ERR_INVALID_ARG, "plan %d is not a live plan", i);
-    for (int i = 0; i < count; ++i)
-        if (plans[i]->band >= 0) return fail(PIPE_ERR_INVALID_ARG, "plan %d is banded; batches take 3-D plans", i);
     for (int i = 1; i < count; ++i)
         if (plans[i]->rb != plans[0]->rb || plans[i]->device != plans[0]->device)
             return fail(PIPE_ERR_INVALID_ARG, "batch members must share precision and device");
@@ -1149,14 +1148,14 @@ pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_
     for (int i = 0; i < count; ++i) {
         pipe_plan_s* p = plans[i];
         int g = -1;
-        for (size_t k = 0; k < b->groups.size(); ++k) {
+        for (size_t k = 0; p->band < 0 && k < b->groups.size(); ++k) {
             pipe_plan_s* r = b->groups[k].rep;
-            if (r->nx == p->nx && r->ny == p->ny && r->nz == p->nz && r->lx == p->lx && r->ly == p->ly &&
-                r->lz == p->lz)
+            if (!b->groups[k].banded && r->nx == p->nx && r->ny == p->ny && r->nz == p->nz && r->lx == p->lx &&
+                r->ly == p->ly && r->lz == p->lz)
                 g = (int)k;
         }
         if (g < 0) {
-            b->groups.push_back({{}, p});
+            b->groups.push_back({{}, p, p->band >= 0});
             g = (int)b->groups.size() - 1;
         }
         b->groups[g].members.push_back(i);
@@ -1228,6 +1227,10 @@ pipe_status_t pipe_batch_solve(pipe_batch_t b, const void* const* rho, void* con
         std::vector<GroupArgs> host;
         for (auto& g : b->groups) {
             const size_t m = g.members.size();
+            if (g.banded) {   // launched directly with its own pointers
+                host.insert(host.end(), 5 * m, GroupArgs{nullptr, nullptr, nullptr, nullptr, 0.0});
+                continue;
+            }
             std::vector<GroupArgs> a(5 * m);
             for (size_t k = 0; k < m; ++k) {
                 const int i = g.members[k];
@@ -1267,8 +1270,15 @@ pipe_status_t pipe_batch_solve(pipe_batch_t b, const void* const* rho, void* con
                 }
                 const GroupArgs* args = b->dargs + b->args_off[k];
                 const int m = (int)g.members.size();
-                s = b->rb == 8 ? launch_group<double>(g.rep, args, m, al_in, al_out, st, shared && m > 1)
-                               : launch_group<float>(g.rep, args, m, al_in, al_out, st, shared && m > 1);
+                if (g.banded) {
+                    const int i = g.members[0];
+                    void* mws = (char*)ws + b->ws_off[i];
+                    s = b->rb == 8 ? run_band_passes<double>(g.rep, rho[i], phi[i], mws, st, false, nullptr)
+                                   : run_band_passes<float>(g.rep, rho[i], phi[i], mws, st, false, nullptr);
+                } else {
+                    s = b->rb == 8 ? launch_group<double>(g.rep, args, m, al_in, al_out, st, shared && m > 1)
+                                   : launch_group<float>(g.rep, args, m, al_in, al_out, st, shared && m > 1);
+                }
                 if (s != PIPE_OK) break;
                 ce = hipEventRecord(b->events[k + 1], st);
                 if (ce == hipSuccess) ce = hipStreamWaitEvent(b->cap, b->events[k + 1], 0);

@@ -277,3 +277,23 @@ def test_long_bunch_128x128x256_full_field(torch_cuda, prec, nb):
     ref = fourterm.solve(oracle_input(wl.rho, prec), wl.hx, wl.hy, wl.hz, wl.a, wl.b, wl.mx, wl.my, wl.kind,
                          band=nb)
     assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec]
+
+
+def test_banded_plans_in_a_batch(torch_cuda):
+    """Banded plans join a batch (their own passes inside the captured graph)
+    beside 3-D plans; every member equals its single solve."""
+    torch = torch_cuda
+    from paper_1111_4971_amd import pipe
+    plans = [_plan((9, 7, 20), "fp64", 1, 2), _plan((9, 7, 20), "fp64", 1, 0),
+             pipe.GreenPlan(9, 7, 20, *H, A, B, kind=1, precision="fp64", mx=21, my=15),
+             _plan((6, 5, 40), "fp64", 0, 20)]
+    rng = np.random.default_rng(5)
+    rhos = [torch.tensor(rng.standard_normal(p.shape), device="cuda") for p in plans]
+    log("banded plans in a batch")
+    b = pipe.Batch(plans)
+    outs = [torch.empty_like(r) for r in rhos]
+    for _ in range(2):   # the second call replays the captured graph
+        b.solve(rhos, outs=outs)
+        torch.cuda.synchronize()
+        for p, r, o in zip(plans, rhos, outs):
+            assert torch.equal(o, p.solve(r))
