@@ -344,7 +344,17 @@ def free_leg(pipe, torch, wl, steps=100):
             plan.solve(x, out=y, workspace=ws)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) / steps * 1e3
-        res[prec] = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms, "build_ms": plan.info.build_ms}
+        plan.timing_start(steps)
+        for _ in range(steps):
+            plan.solve(x, out=y, workspace=ws)
+        torch.cuda.synchronize()
+        pass_ms, _ = plan.timing_stop()
+        info = plan.info
+        res[prec] = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms, "build_ms": plan.info.build_ms,
+                     "spectra_bytes": info.spectra_bytes,
+                     "passes": {PASS_NAMES[i]: {"ms": pass_ms[i], "model_bytes": info.pass_bytes[i],
+                                                "hbm_frac": info.pass_bytes[i] / (pass_ms[i] * 1e-3) / 1e9
+                                                / HBM_PEAK_GBS} for i in range(5)}}
         plan.close()
     return res
 

@@ -195,9 +195,10 @@ __global__ void free_arrange_kernel(double* xi, int nx, int ny, int nz, int lx, 
 
 // Orbit table from the full forward spectrum S[lx][ly][nh] (FP64 complex, kz = lz/2
 // packed into slot 0 as A + iB).  term: 0 cc, 1 cr, 2 rc, 3 rr.
+// nval = 9 (the four terms) or 1 (T_cc only: free space).
 template <typename out_t>
 __global__ void compress_kernel(const double2* __restrict__ S, out_t* table, out_t* nyq, int term, int lx, int ly,
-                                int nh, int tile) {
+                                int nh, int tile, int nval) {
     const int kxo_n = lx / 2 + 1, kyo_n = ly / 2 + 1;
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long total = (long)kxo_n * kyo_n * nh;
@@ -207,8 +208,8 @@ __global__ void compress_kernel(const double2* __restrict__ S, out_t* table, out
     const int kxo = (int)(i / ((long)nh * kyo_n));
     const int ntiles = (nh + tile - 1) / tile;
     // tile-blocked position of (kxo, kyo, kz), plane p at ti + p * tile; kz = lz/2 at ni + p
-    const long ti = ((((long)kyo * ntiles + kz / tile) * kxo_n + kxo) * 9) * tile + kz % tile;
-    const long ni = ((long)kyo * kxo_n + kxo) * 9;
+    const long ti = ((((long)kyo * ntiles + kz / tile) * kxo_n + kxo) * nval) * tile + kz % tile;
+    const long ni = ((long)kyo * kxo_n + kxo) * nval;
     auto at = [&](int kx, int ky) { return S[((long)kx * ly + ky) * nh + kz]; };
     // value at (kx, ky): main (kz) and, for kz = 0, the kz = lz/2 part
     auto split = [&](int kx, int ky, double2& A, double2& B) {
@@ -227,6 +228,7 @@ __global__ void compress_kernel(const double2* __restrict__ S, out_t* table, out
     double2 A, B, A2, B2;
     split(kxo, kyo, A, B);
     auto put = [&](int pl, double va, double vb) {
+        if (pl >= nval) return;
         table[ti + (long)pl * tile] = (out_t)va;
         if (kz == 0) nyq[ni + pl] = (out_t)vb;
     };
@@ -244,10 +246,11 @@ __global__ void compress_kernel(const double2* __restrict__ S, out_t* table, out
     }
 }
 
-// Tile-blocked table -> 9 planes [p][kx][ky][kz] followed by 9 planes [p][kx][ky] (kz = lz/2).
+// Tile-blocked table -> 9 planes [p][kx][ky][kz] followed by 9 planes [p][kx][ky] (kz = lz/2);
+// planes p >= nval (absent terms) are zero.
 template <typename T_>
 __global__ void untile_kernel(const T_* __restrict__ table, const T_* __restrict__ nyq, T_* out, int lx, int ly,
-                              int nh, int tile) {
+                              int nh, int tile, int nval) {
     const int kxo_n = lx / 2 + 1, kyo_n = ly / 2 + 1;
     const long plane = (long)kxo_n * kyo_n * nh;
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,11 +259,12 @@ __global__ void untile_kernel(const T_* __restrict__ table, const T_* __restrict
     const int kyo = (int)((i / nh) % kyo_n);
     const int kxo = (int)(i / ((long)nh * kyo_n));
     const int ntiles = (nh + tile - 1) / tile;
-    const long ti = ((((long)kyo * ntiles + kz / tile) * kxo_n + kxo) * 9) * tile + kz % tile;
-    for (int p = 0; p < 9; ++p) out[p * plane + i] = table[ti + (long)p * tile];
+    const long ti = ((((long)kyo * ntiles + kz / tile) * kxo_n + kxo) * nval) * tile + kz % tile;
+    for (int p = 0; p < 9; ++p) out[p * plane + i] = p < nval ? table[ti + (long)p * tile] : (T_)0;
     if (kz == 0) {
         const long np_ = (long)kxo_n * kyo_n, ni = (long)kxo * kyo_n + kyo;
-        for (int p = 0; p < 9; ++p) out[9 * plane + p * np_ + ni] = nyq[((long)kyo * kxo_n + kxo) * 9 + p];
+        for (int p = 0; p < 9; ++p)
+            out[9 * plane + p * np_ + ni] = p < nval ? nyq[((long)kyo * kxo_n + kxo) * nval + p] : (T_)0;
     }
 }
 
@@ -307,28 +311,28 @@ hipError_t launch_free_arrange(double* xi, int nx, int ny, int nz, int lx, int l
 }
 
 hipError_t launch_compress(const void* spec, void* table, void* nyq, int real_bytes, int term, int lx, int ly,
-                           int nh, int tile, hipStream_t st) {
+                           int nh, int tile, hipStream_t st, int nval) {
     const long n = (long)(lx / 2 + 1) * (ly / 2 + 1) * nh;
     if (tile < 1) return hipErrorInvalidValue;
     if (real_bytes == 8)
         hipLaunchKernelGGL(compress_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                           (const double2*)spec, (double*)table, (double*)nyq, term, lx, ly, nh, tile);
+                           (const double2*)spec, (double*)table, (double*)nyq, term, lx, ly, nh, tile, nval);
     else
         hipLaunchKernelGGL(compress_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                           (const double2*)spec, (float*)table, (float*)nyq, term, lx, ly, nh, tile);
+                           (const double2*)spec, (float*)table, (float*)nyq, term, lx, ly, nh, tile, nval);
     return hipGetLastError();
 }
 
 hipError_t launch_untile(const void* table, const void* nyq, void* out, int real_bytes, int lx, int ly, int nh,
-                         int tile, hipStream_t st) {
+                         int tile, hipStream_t st, int nval) {
     const long n = (long)(lx / 2 + 1) * (ly / 2 + 1) * nh;
     if (tile < 1) return hipErrorInvalidValue;
     if (real_bytes == 8)
         hipLaunchKernelGGL(untile_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const double*)table,
-                           (const double*)nyq, (double*)out, lx, ly, nh, tile);
+                           (const double*)nyq, (double*)out, lx, ly, nh, tile, nval);
     else
         hipLaunchKernelGGL(untile_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const float*)table,
-                           (const float*)nyq, (float*)out, lx, ly, nh, tile);
+                           (const float*)nyq, (float*)out, lx, ly, nh, tile, nval);
     return hipGetLastError();
 }
 

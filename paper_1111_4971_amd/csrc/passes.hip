@@ -212,8 +212,9 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
 // the nx nonzero rows, the mixed product on each orbit {+-kx} x {+-ky} (see
 // orbit_product), inverse x transform, rows i < nx written back in place.  The
 // spectra are stored tile-blocked (see xprod_tile); the kz = lz/2 values sit in
-// `nyq`.
-template <typename real, int N, int T, bool ADJ>
+// `nyq`.  NV = 9: the four terms; NV = 1: T_cc alone (free space), where the
+// product is a real scaling and its own adjoint.
+template <typename real, int N, int T, bool ADJ, int NV>
 __global__ __launch_bounds__(2 * (N / Plan<N>::E) * T)
 void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restrict__ table,
                   const real* __restrict__ nyq, const cplx<real>* __restrict__ tw,
@@ -263,7 +264,21 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     const int kyo = ky;
     constexpr int NKX = N / 2 + 1;
     const int ntiles = (nh + T - 1) / T;
-    const real* tblock = table + ((long)kyo * ntiles + tile) * NKX * 9 * T;
+    const real* tblock = table + ((long)kyo * ntiles + tile) * NKX * NV * T;
+    auto load = [](const real* e, int stride) -> Orbit<real> {
+        if constexpr (NV == 9) return load_orbit(e, stride);
+        Orbit<real> o{};
+        o.cc = e[0];
+        return o;
+    };
+    auto product = [](const Orbit<real>& ob, const C* rin, C* pout) {
+        if constexpr (NV == 9) {
+            orbit_product<ADJ>(ob, rin, pout);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pout[q] = cscale(rin[q], ob.cc);
+        }
+    };
     // this thread's items w = threadIdx.x + it NT: their spectra are loaded
     // together, before the first product, so the loads overlap
     constexpr int IT = (NKX * T + NT - 1) / NT;
@@ -271,7 +286,7 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int w = threadIdx.x + it * NT;
-        if (w < NKX * T) obs[it] = load_orbit(tblock + (long)(w / T) * 9 * T + w % T, T);
+        if (w < NKX * T) obs[it] = load(tblock + (long)(w / T) * NV * T + w % T, T);
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -287,7 +302,7 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
         C p[4];
         const Orbit<real>& ob = obs[it];
         if (kzz != 0) {
-            orbit_product<ADJ>(ob, r, p);
+            product(ob, r, p);
         } else {
             // slot 0 carries A + iB, A at kz = 0, B at kz = lz/2 (both Hermitian in (kx,ky)):
             // A(k) = (P(k) + conj P(-k))/2, B(k) = (P(k) - conj P(-k))/(2i); -point of q is 3-q.
@@ -299,9 +314,9 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
                 ra[q] = cscale(s, (real)0.5);
                 rb[q] = cscale(cmake<C>(d.y, -d.x), (real)0.5);
             }
-            const Orbit<real> obn = load_orbit(nyq + ((long)kyo * NKX + o) * 9, 1);
-            orbit_product<ADJ>(ob, ra, pa);
-            orbit_product<ADJ>(obn, rb, pb);
+            const Orbit<real> obn = load(nyq + ((long)kyo * NKX + o) * NV, 1);
+            product(ob, ra, pa);
+            product(obn, rb, pb);
 #pragma unroll
             for (int q = 0; q < 4; ++q) p[q] = cmake<C>(pa[q].x - pb[q].y, pa[q].y + pb[q].x);
         }
@@ -436,22 +451,25 @@ int xprod_tile(int lx, int real_bytes) {
 template <typename real>
 hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh, const real* table,
                         const real* nyq, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
-                        int ngroup, bool shared_table) {
+                        int ngroup, bool shared_table, int nval) {
     using C = cplx<real>;
     const C* tw = twb.get<C>(lx);
-    if (!tw) return hipErrorInvalidValue;
+    if (!tw || (nval != 9 && nval != 1)) return hipErrorInvalidValue;
     switch (lx) {
 #define X(N_)                                                                                     \
     case N_: {                                                                                    \
         constexpr int T = xprod_T<real, N_>();                                                    \
         constexpr int P = N_ / Plan<N_>::E;                                                       \
         dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1), (unsigned)ngroup);        \
-        if (adjoint)                                                                              \
-            hipLaunchKernelGGL((xprod_kernel<real, N_, T, true>), grid, dim3(2 * P * T), 0, s,    \
+        if (nval == 1)                                                                            \
+            hipLaunchKernelGGL((xprod_kernel<real, N_, T, false, 1>), grid, dim3(2 * P * T), 0,   \
+                               s, (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table); \
+        else if (adjoint)                                                                         \
+            hipLaunchKernelGGL((xprod_kernel<real, N_, T, true, 9>), grid, dim3(2 * P * T), 0, s, \
                                (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);   \
         else                                                                                      \
-            hipLaunchKernelGGL((xprod_kernel<real, N_, T, false>), grid, dim3(2 * P * T), 0, s,   \
-                               (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);   \
+            hipLaunchKernelGGL((xprod_kernel<real, N_, T, false, 9>), grid, dim3(2 * P * T), 0,   \
+                               s, (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table); \
         return hipGetLastError();                                                                 \
     }
         PIPE_FOR_EACH_N(X)
@@ -469,7 +487,7 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
                                              long, long, long, const TwiddleBank&, hipStream_t,         \
                                              const GroupArgs*, int);                                    \
     template hipError_t launch_xprod<real>(int, bool, void*, int, int, int, const real*, const real*,  \
-                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool);
+                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool, int);
 PIPE_INST(float)
 PIPE_INST(double)
 #undef PIPE_INST

@@ -145,10 +145,11 @@ struct pipe_plan_s {
     double x0 = 0, y0 = 0;   // mesh offset: node i at x0 + (i+1) hx, node j at y0 + (j+1) hy
     int device;
     DeviceCtx* ctx;
-    void* table = nullptr;   // tile-blocked spectra, 9 values per orbit (see xprod_tile)
-    void* nyq = nullptr;     // kz = lz/2 values, 9 per orbit (inside the table allocation)
+    void* table = nullptr;   // tile-blocked spectra, nval values per orbit (see xprod_tile)
+    void* nyq = nullptr;     // kz = lz/2 values, nval per orbit (inside the table allocation)
     size_t table_elems = 0, nyq_elems = 0;
     int tile = 0;            // kz tile of the table layout
+    int nval = 9;            // values per orbit: 9 (four terms), 1 (free space: T_cc only)
     int band = -1;           // banded plan: planes kept each side of the z sum (Eq. 18); -1 = 3-D plan
     double g0 = 0;           // free-space plans: G at zero separation
     bool band_single = false; // banded x pass: single-window kernel (else chunked), chosen by timing
@@ -179,12 +180,12 @@ void plan_pass_bytes(const pipe_plan_s* p, double out[5]) {
     const double a1 = (double)p->nx * p->ny * p->nh * cb;
     const double a2 = (double)p->nx * p->ly * p->nh * cb;
     const double orbits = (double)(p->lx / 2 + 1) * (p->ly / 2 + 1);
-    const double tab = 9.0 * orbits * (p->nh + 1) * rb;   // values read once per solve
+    const double tab = p->nval * orbits * (p->nh + 1) * rb;   // values read once per solve
     if (p->band >= 0) {
         // banded: y forward (real in), x + banded product, y inverse (real out)
         const double A = (double)p->nx * p->ly * ((p->nz + 1) / 2) * cb;
         out[0] = phys + A;
-        out[1] = 2.0 * A + 9.0 * orbits * (p->band + 1) * rb;
+        out[1] = 2.0 * A + 10.0 * orbits * (p->band + 1) * rb;   // K0..K9 per orbit and distance
         out[2] = A + phys;
         out[3] = out[4] = 0.0;
         return;
@@ -268,8 +269,9 @@ pipe_status_t build_free_spectra(pipe_plan_s* p, hipStream_t st) {
     HIP_TRY(launch_strided<double>(lx, false, buf, buf, lx, lx, (long)ly * nh, (long)ly * nh, (long)ly * nh, 0, 0, 1,
                                    p->ctx->tw, st),
             "spectra x transform");
-    // only T_cc: the other terms' planes of the (zeroed) table stay zero
-    HIP_TRY(launch_compress(buf, p->table, p->nyq, p->rb, 0, lx, ly, nh, p->tile, st), "spectra compression");
+    // only T_cc, stored alone (one value per orbit)
+    HIP_TRY(launch_compress(buf, p->table, p->nyq, p->rb, 0, lx, ly, nh, p->tile, st, p->nval),
+            "spectra compression");
     HIP_TRY(hipStreamSynchronize(st), "plan build");
     return PIPE_OK;
 }
@@ -432,7 +434,8 @@ pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, h
     HIP_TRY(launch_strided<real>(ly, false, A1, A2, ny, ly, nh, nh, nh, (long)ny * nh, (long)ly * nh, nx, tw, st),
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
-    HIP_TRY(launch_xprod<real>(p->lx, adjoint, A2, nx, ly, nh, (const real*)p->table, (const real*)p->nyq, tw, st),
+    HIP_TRY(launch_xprod<real>(p->lx, adjoint, A2, nx, ly, nh, (const real*)p->table, (const real*)p->nyq, tw, st,
+                               nullptr, 1, false, p->nval),
             "x pass with spectral product");
     if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event");
     HIP_TRY(launch_strided<real>(ly, true, A2, A1, ly, ny, nh, nh, nh, (long)ly * nh, (long)ny * nh, nx, tw, st),
@@ -639,8 +642,8 @@ pipe_status_t autotune_lengths(pipe_plan_s* tmpl, int members, hipStream_t st, i
         q.lx = cands[i].lx; q.ly = cands[i].ly; q.lz = cands[i].lz; q.nh = q.lz / 2;
         q.tile = xprod_tile(q.lx, q.rb);
         const size_t orbits = (size_t)(q.lx / 2 + 1) * (q.ly / 2 + 1);
-        q.table_elems = 9 * orbits * ((q.nh + q.tile - 1) / q.tile) * q.tile;
-        q.nyq_elems = 9 * orbits;
+        q.table_elems = q.nval * orbits * ((q.nh + q.tile - 1) / q.tile) * q.tile;
+        q.nyq_elems = q.nval * orbits;
         q.ws_bytes = plan_ws_bytes(&q);
         ws_max = std::max(ws_max, q.ws_bytes);
         tab_max = std::max(tab_max, (q.table_elems + q.nyq_elems) * q.rb);
@@ -774,7 +777,7 @@ pipe_status_t create_plan(int nx, int ny, int nz, double hx, double hy, double h
         pipe_plan_s tmpl;
         tmpl.nx = nx; tmpl.ny = ny; tmpl.nz = nz; tmpl.kind = kind; tmpl.rb = (kind & PIPE_PREC_FP32) ? 4 : 8;
         tmpl.hx = hx; tmpl.hy = hy; tmpl.hz = hz; tmpl.a = a; tmpl.b = b; tmpl.mx = mx; tmpl.my = my;
-        tmpl.device = dev; tmpl.ctx = ctx;
+        tmpl.device = dev; tmpl.ctx = ctx; tmpl.nval = free_space ? 1 : 9;
         if ((s = autotune_lengths(&tmpl, tune_members, (hipStream_t)hip_stream, &lx, &ly, &lz, &tune_ms)) != PIPE_OK)
             return s;
     }
@@ -784,11 +787,12 @@ pipe_status_t create_plan(int nx, int ny, int nz, double hx, double hy, double h
     p->hx = hx; p->hy = hy; p->hz = hz; p->a = a; p->b = b;
     p->x0 = x0; p->y0 = y0; p->g0 = g0;
     p->device = dev; p->ctx = ctx;
+    p->nval = free_space ? 1 : 9;
     const size_t orbits = (size_t)(lx / 2 + 1) * (ly / 2 + 1);
     p->tile = xprod_tile(lx, p->rb);
     const size_t ntiles = (p->nh + p->tile - 1) / p->tile;
-    p->table_elems = 9 * orbits * ntiles * p->tile;
-    p->nyq_elems = 9 * orbits;
+    p->table_elems = p->nval * orbits * ntiles * p->tile;
+    p->nyq_elems = p->nval * orbits;
     e = dev_alloc(&p->table, (p->table_elems + p->nyq_elems) * p->rb);
     if (e == hipSuccess) e = hipMemset(p->table, 0, (p->table_elems + p->nyq_elems) * p->rb);
     if (e != hipSuccess) {
@@ -989,7 +993,8 @@ pipe_status_t pipe_plan_spectra(pipe_plan_t p, void* out, void* stream) {
     if (p->band >= 0)
         HIP_TRY(hipMemcpyAsync(out, p->table, p->table_elems * p->rb, hipMemcpyDeviceToDevice, st), "spectra copy");
     else
-        HIP_TRY(launch_untile(p->table, p->nyq, out, p->rb, p->lx, p->ly, p->nh, p->tile, st), "spectra copy");
+        HIP_TRY(launch_untile(p->table, p->nyq, out, p->rb, p->lx, p->ly, p->nh, p->tile, st, p->nval),
+                "spectra copy");
     HIP_TRY(hipStreamSynchronize(st), "spectra copy");
     return PIPE_OK;
 }
@@ -1118,7 +1123,7 @@ pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al
                                  tw, st, args + n, n),
             "grouped y forward pass");
     HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, nullptr, nullptr, tw, st, args + 2 * n, n,
-                               shared_table),
+                               shared_table, p->nval),
             "grouped x pass with spectral product");
     HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, nh, nh, nh, (long)ly * nh, (long)ny * nh, nx,
                                  tw, st, args + 3 * n, n),
@@ -1151,7 +1156,7 @@ pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_
         for (size_t k = 0; p->band < 0 && k < b->groups.size(); ++k) {
             pipe_plan_s* r = b->groups[k].rep;
             if (!b->groups[k].banded && r->nx == p->nx && r->ny == p->ny && r->nz == p->nz && r->lx == p->lx &&
-                r->ly == p->ly && r->lz == p->lz)
+                r->ly == p->ly && r->lz == p->lz && r->nval == p->nval)
                 g = (int)k;
         }
         if (g < 0) {

@@ -55,16 +55,19 @@ hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_
 template <typename real>
 // shared_table (grouped launches whose members all use one plan's spectra):
 // members of one (kz tile, ky) item run back to back, so the tile is read once.
+// nval: values per orbit in the table, 9 (four terms) or 1 (T_cc only: free space).
 hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh,
                         const real* table, const real* nyq, const TwiddleBank& tw, hipStream_t s,
-                        const GroupArgs* group = nullptr, int ngroup = 1, bool shared_table = false);
+                        const GroupArgs* group = nullptr, int ngroup = 1, bool shared_table = false,
+                        int nval = 9);
 
 // kz tile width of the fused x pass for padded length lx (0 if unsupported).
 // The Green spectra are stored tile-blocked to match: for orbit row kyo, kz tile
-// t, orbit kx = o, plane p (0..8) and column c < T the value sits at
-//   (((kyo * ntiles + t) * (lx/2 + 1) + o) * 9 + p) * T + c,   kz = t * T + c,
+// t, orbit kx = o, plane p < nval (9, or 1 for free space) and column c < T the
+// value sits at
+//   (((kyo * ntiles + t) * (lx/2 + 1) + o) * nval + p) * T + c,   kz = t * T + c,
 // so one block of the fused pass reads one contiguous run.  The kz = lz/2
-// values sit at (kyo * (lx/2 + 1) + o) * 9 + p.
+// values sit at (kyo * (lx/2 + 1) + o) * nval + p.
 int xprod_tile(int lx, int real_bytes);
 
 // Green evaluation (green.hip).
@@ -83,9 +86,9 @@ hipError_t launch_arrange(double* xi, const double* rbar, int nx, int ny, int nz
 hipError_t launch_free_arrange(double* xi, int nx, int ny, int nz, int lx, int ly, int lz, double hx, double hy,
                               double hz, double g0, hipStream_t st);
 hipError_t launch_compress(const void* spec, void* table, void* nyq, int real_bytes, int term,
-                           int lx, int ly, int nh, int tile, hipStream_t st);
+                           int lx, int ly, int nh, int tile, hipStream_t st, int nval = 9);
 hipError_t launch_untile(const void* table, const void* nyq, void* out, int real_bytes, int lx, int ly, int nh,
-                         int tile, hipStream_t st);
+                         int tile, hipStream_t st, int nval = 9);
 
 // Neighbouring-plane (banded z) path (band.hip).
 // y pass between real planes (rho, phi: (slab, e, z) at slab r_ss + e r_es + z,
