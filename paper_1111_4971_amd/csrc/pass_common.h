@@ -53,6 +53,19 @@ template <typename real, int N> constexpr int strided_T() {
     return t;
 }
 
+// Pointer into device global memory.  Buffers taken from a grouped launch's
+// descriptor array arrive as generic pointers, which compile to flat memory
+// instructions; flat accesses also count on the LDS wait counter, so every LDS
+// wait would drain the global loads in flight.  The kernels address their
+// buffers through global-typed pointers instead.  (The host pass of the
+// compiler only parses device code and has no such address space.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+#else
+template <typename T> using gptr = T*;
+#endif
+template <typename T> __device__ __forceinline__ gptr<T> to_global(T* p) { return (gptr<T>)p; }
+
 // Copy n twiddles into LDS (no barrier: every use follows a later barrier).
 template <typename C>
 __device__ __forceinline__ const C* stage_twiddles(C* s_tw, const C* __restrict__ tw, int n) {
@@ -95,7 +108,7 @@ template <typename real> struct Orbit {
 
 // Nine values of one orbit, `stride` apart (T in the tiled table, 1 for kz = lz/2).
 template <typename real>
-__device__ __forceinline__ Orbit<real> load_orbit(const real* __restrict__ e, int stride) {
+__device__ __forceinline__ Orbit<real> load_orbit(gptr<const real> e, int stride) {
     using C = cplx<real>;
     Orbit<real> o;
     o.cc = e[0];
