@@ -56,6 +56,32 @@ def test_solve_matches_eq10_oracle(torch_cuda, shape, kind, prec):
     assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
 
 
+# one dimension at the largest padded length each (lx = 1024, ly = 1024, lz = 2048)
+LARGEST = [((512, 2, 4), "lx", 1024), ((2, 512, 4), "ly", 1024), ((3, 2, 1024), "lz", 2048)]
+
+
+@pytest.mark.parametrize("shape,dim,L", LARGEST)
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_largest_transform_lengths_match_eq10_oracle(torch_cuda, shape, dim, L, kind, prec):
+    """The biggest kernels of every pass (x: 1024-point lines in the fused pass;
+    y: 1024-point strided lines; z: 2048-point real lines as 1024 packed bins)
+    against the literal Eq. 10 algorithm, element by element."""
+    from oracle import fourterm
+    from paper_1111_4971_amd import pipe
+    nx, ny, nz = shape
+    a, b = 1.0, 1.0
+    hx, hy = a / (nx + 1), b / (ny + 1)
+    mx, my = 2 * nx + 3, 2 * ny + 1
+    rho = np.random.default_rng(sum(shape) + kind).standard_normal(shape)
+    log("largest %s %s kind=%d shape=%s" % (dim, prec, kind, shape))
+    plan = pipe.GreenPlan(nx, ny, nz, hx, hy, 0.05, a, b, kind=kind, precision=prec, mx=mx, my=my)
+    assert getattr(plan.info, dim) == L
+    got = gpu_solve(plan, rho)
+    ref = fourterm.solve(oracle_input(rho, prec), hx, hy, 0.05, a, b, mx, my, kind)
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_padded_length_does_not_change_the_result(torch_cuda, prec):
     from paper_1111_4971_amd import pipe
