@@ -81,7 +81,7 @@ typedef struct pipe_plan_info {
     int real_bytes;          /* 8 (FP64) or 4 (FP32)                                        */
     double hx, hy, hz, a, b;
     double x0, y0;           /* mesh offset (pipe_green_plan_region; 0 otherwise)           */
-    double norm;             /* the R prefactor 1/(2 pi a b)                                */
+    double norm;             /* the R prefactor 1/(2 pi a b); 1 for free-space plans         */
     size_t workspace_bytes;  /* device bytes a solve needs as scratch                       */
     size_t spectra_bytes;    /* device bytes held by the plan's Green spectra               */
     double model_bytes;      /* algorithmic HBM bytes of one solve (all passes)             */
@@ -260,6 +260,8 @@ pipe_status_t pipe_plan_green_table(pipe_plan_t plan, void* out_device, void* hi
  *   plane 0 = Re T_cc(kx,ky,kz); planes 1,2 = T_cr(kx,ky,kz);
  *   planes 3,4 = T_rc(kx,ky,kz); planes 5,6 = T_rr(kx,ky,kz);
  *   planes 7,8 = T_rr(lx-kx,ky,kz)   (re, im pairs).
+ * A free-space plan (pipe_free_plan) has only plane 0 (T_cc of G = 1/r);
+ * planes 1..8 of its copy are zero.
  * For a banded plan (pipe_green_plan_banded) the copy is the plan's own
  * coefficient table: with T_ab now the 2-D DFT of the four terms' slices at
  * plane distance d, ten values K0..K9 of (ky, d, kx) at

@@ -34,7 +34,7 @@ void strided_pair_kernel(const void* in, void* out, int n_in, int n_out, long r_
     constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, N);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -135,7 +135,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
     __shared__ C lds[2 * N * TS];
     __shared__ C s_tw[N];
     __shared__ real sK[10 * NKX];   // K0..K9 of one plane distance, this block's ky
-    tw = stage_twiddles(s_tw, tw, N);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const unsigned ntile = gridDim.x;
     const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
@@ -320,7 +320,7 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NKX = N / 2 + 1;
     __shared__ C lds[2 * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, N);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const unsigned ntile = gridDim.x;
     const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
@@ -399,7 +399,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     constexpr int IM = (NH * T + NT - 1) / NT;   // (orbit < N/2, output column) items per thread, at most
     __shared__ C lds[2 * N * TS];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, N);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const unsigned ntile = gridDim.x;
     const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
@@ -523,7 +523,7 @@ void strided_real_kernel(const void* in, void* out, int n_in, int n_out, long in
     constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, N);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -600,7 +600,7 @@ hipError_t launch_strided_pair(int n, bool inverse, const void* in, void* out, i
                                long c_es, long r_ss, long c_ss, long nslabs, int nz, real scale,
                                const TwiddleBank& twb, hipStream_t s) {
     using C = cplx<real>;
-    const C* tw = twb.get<C>(n);
+    const C* tw = twb.stage<C>(n);
     const long ncols = (nz + 1) / 2;
     if (!tw || nz < 1 || nslabs <= 0) return hipErrorInvalidValue;
     switch (n) {
@@ -630,7 +630,7 @@ hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, i
                                long out_es, long ncols, long in_ss, long out_ss, long nslabs, real scale,
                                const TwiddleBank& twb, hipStream_t s) {
     using C = cplx<real>;
-    const C* tw = twb.get<C>(n);
+    const C* tw = twb.stage<C>(n);
     if (!tw || ncols <= 0 || nslabs <= 0) return hipErrorInvalidValue;
     switch (n) {
 #define X(N_)                                                                                        \
@@ -693,7 +693,7 @@ template <typename real>
 hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
                         const TwiddleBank& twb, hipStream_t s, bool single_window) {
     using C = cplx<real>;
-    const C* tw = twb.get<C>(lx);
+    const C* tw = twb.stage<C>(lx);
     if (!tw || nb < 0 || nx > lx || nz < 1) return hipErrorInvalidValue;
     const int nzp = (nz + 1) / 2;
     switch (lx) {

@@ -19,7 +19,7 @@ void lines_kernel(const cplx<real>* in, cplx<real>* out, long nlines, const cplx
     constexpr int P = N / Plan<N>::E, LPB = lines_per_block<real, N>(), LS = N + N / 16 + 1;
     __shared__ C lds[LPB * LS];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, N);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
     const int t = threadIdx.x % P, li = threadIdx.x / P;
     const long line = (long)blockIdx.x * LPB + li;
     const bool active = line < nlines;
@@ -39,7 +39,7 @@ template <typename real>
 hipError_t launch_lines(int n, bool inverse, const void* in, void* out, long nlines, const TwiddleBank& twb,
                         hipStream_t s) {
     using C = cplx<real>;
-    const C* tw = twb.get<C>(n);
+    const C* tw = twb.stage<C>(n);
     if (!tw || nlines <= 0) return hipErrorInvalidValue;
     switch (n) {
 #define X(N_)                                                                                        \

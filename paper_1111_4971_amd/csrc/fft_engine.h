@@ -10,8 +10,9 @@
 // costs (stages - 1) LDS round trips.
 //
 // Direction: forward uses W = e^{-2 pi i/N}, inverse W^{-1}; both unscaled.
-// Twiddles come from a per-length table tw[m] = W_N^m, m < N, computed in FP64
-// on the host and rounded once to the working precision.
+// Twiddles come from a per-length stage table (stage_tw_offset) whose values
+// W_N^m are computed on the host in extended precision and rounded once to the
+// working precision.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -177,6 +178,21 @@ template <int N> __host__ __device__ constexpr int plan_ns(int s) {
     return ns;
 }
 
+// Stage twiddle table of length N: stage s >= 1 (radix R, span NS) owns R - 1
+// runs of NS values starting at stage_tw_offset<N>(NS); run r - 1 holds
+// W_{NS R}^{r k} = W_N^{r k N / (NS R)} for k < NS.  The lanes of a stage
+// differ in k, so they read consecutive entries (no LDS bank conflicts), where
+// a natural-order table would be read at stride r N / (NS R).
+template <int N> __host__ __device__ constexpr int stage_tw_offset(int ns) {
+    int off = 0;
+    for (int s = 1; s < Plan<N>::S; ++s) {
+        if (plan_ns<N>(s) == ns) return off;
+        off += (Plan<N>::radix(s) - 1) * plan_ns<N>(s);
+    }
+    return off;
+}
+template <int N> __host__ __device__ constexpr int stage_tw_size() { return stage_tw_offset<N>(0); }
+
 // ---------------------------------------------------------------- stage pieces
 // v[b*R + r] holds input r of the thread's b-th butterfly, j = t + b*P.
 
@@ -198,8 +214,9 @@ __device__ __forceinline__ void stage_compute(C* v, int t, const C* __restrict__
     for (int b = 0; b < NB; ++b) {
         if constexpr (NS > 1) {
             const int k = (t + b * P) % NS;
+            constexpr int off = stage_tw_offset<N>(NS);
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[b * R + r] = ctw<INV>(v[b * R + r], tw[r * k * (N / (NS * R))]);
+            for (int r = 1; r < R; ++r) v[b * R + r] = ctw<INV>(v[b * R + r], tw[off + (r - 1) * NS + k]);
         }
         dft<R, INV>(&v[b * R]);
     }

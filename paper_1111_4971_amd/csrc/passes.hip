@@ -31,6 +31,38 @@ template <> const double2* TwiddleBank::get<double2>(int n) const {
         if (kTwLengths[i] == n) return reinterpret_cast<const double2*>(d64) + offset[i];
     return nullptr;
 }
+template <> const float2* TwiddleBank::stage<float2>(int n) const {
+    if (!fft_length_ok(n)) return nullptr;
+    for (int i = 0; i < kNumTw; ++i)
+        if (kTwLengths[i] == n) return reinterpret_cast<const float2*>(d32) + soffset[i];
+    return nullptr;
+}
+template <> const double2* TwiddleBank::stage<double2>(int n) const {
+    if (!fft_length_ok(n)) return nullptr;
+    for (int i = 0; i < kNumTw; ++i)
+        if (kTwLengths[i] == n) return reinterpret_cast<const double2*>(d64) + soffset[i];
+    return nullptr;
+}
+
+template <int N> static int stage_exponents(int* m) {
+    int i = 0;
+    for (int s = 1; s < Plan<N>::S; ++s) {
+        const int R = Plan<N>::radix(s), NS = plan_ns<N>(s);
+        for (int r = 1; r < R; ++r)
+            for (int k = 0; k < NS; ++k) m[i++] = r * k * (N / (NS * R));
+    }
+    return i;
+}
+
+int fft_stage_exponents(int n, int* m_out) {
+    switch (n) {
+#define X(N_) \
+    case N_: return stage_exponents<N_>(m_out);
+        PIPE_FOR_EACH_N(X)
+#undef X
+    }
+    return -1;
+}
 
 // The z passes are persistent: block b handles line groups b, b + gridDim.x, ...
 // (LPW lines per group) and issues the global loads of its next group before
@@ -58,7 +90,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     constexpr int PADN = NH + NH / 16 + 1;
     __shared__ C lds[LPW * PADN];
     __shared__ C s_tw[NH], s_tw2[NH];
-    tw = stage_twiddles(s_tw, tw, NH);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<NH>());
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     const int t = threadIdx.x % P, l = threadIdx.x / P;
     LdsLine<C> view{lds + l * PADN};
@@ -132,7 +164,7 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
     constexpr int PADN = NH + NH / 16 + 1;
     __shared__ C lds[LPW * PADN];
     __shared__ C s_tw[NH], s_tw2[NH];
-    tw = stage_twiddles(s_tw, tw, NH);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<NH>());
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     const int t = threadIdx.x % P, l = threadIdx.x / P;
     LdsLine<C> view{lds + l * PADN};
@@ -202,7 +234,7 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
     constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, N);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -258,7 +290,7 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T;
     __shared__ C lds[2 * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, N);
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const int tile = (int)(item % ntile);
     const int ky = (int)(item / ntile);
@@ -384,7 +416,7 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
                         long nlines, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group, int ngroup,
                         bool aligned) {
     using C = cplx<real>;
-    const C* tw = twb.get<C>(nh);
+    const C* tw = twb.stage<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
     if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
     const int vec2 = (n_in % 2 == 0) && (in_pitch % 2 == 0) && aligned &&
@@ -409,7 +441,7 @@ hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long o
                         long nlines, real scale, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
                         int ngroup, bool aligned) {
     using C = cplx<real>;
-    const C* tw = twb.get<C>(nh);
+    const C* tw = twb.stage<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
     if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
     const int vec2 = (n_out % 2 == 0) && (out_pitch % 2 == 0) && aligned &&
@@ -434,7 +466,7 @@ hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_
                           long out_es, long ncols, long in_ss, long out_ss, long nslabs,
                           const TwiddleBank& twb, hipStream_t s, const GroupArgs* group, int ngroup) {
     using C = cplx<real>;
-    const C* tw = twb.get<C>(n);
+    const C* tw = twb.stage<C>(n);
     if (!tw || ncols <= 0 || nslabs <= 0) return hipErrorInvalidValue;
     switch (n) {
 #define X(N_)                                                                                      \
@@ -483,7 +515,7 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
                         const real* nyq, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
                         int ngroup, bool shared_table, int nval) {
     using C = cplx<real>;
-    const C* tw = twb.get<C>(lx);
+    const C* tw = twb.stage<C>(lx);
     if (!tw || (nval != 9 && nval != 1)) return hipErrorInvalidValue;
     switch (lx) {
 #define X(N_)                                                                                     \

@@ -77,26 +77,41 @@ pipe_status_t device_ctx(int dev, DeviceCtx** out) {
     if (dev < 0 || dev >= 64) return fail(PIPE_ERR_NO_DEVICE, "device index %d out of range", dev);
     DeviceCtx& c = g_ctx[dev];
     if (!c.ready) {
-        size_t off = 0;
+        // natural tables (exponent m at offset + m), then the stage tables of
+        // the FFT lengths (exponents from fft_stage_exponents)
+        std::vector<int> m_of;   // exponent of every entry
+        std::vector<int> n_of;   // its table length
         for (int i = 0; i < kNumTw; ++i) {
-            c.tw.offset[i] = off;
-            off += kTwLengths[i];
+            const int n = kTwLengths[i];
+            c.tw.offset[i] = m_of.size();
+            for (int m = 0; m < n; ++m) {
+                m_of.push_back(m);
+                n_of.push_back(n);
+            }
         }
+        std::vector<int> ms(4096);
+        for (int i = 0; i < kNumTw; ++i) {
+            const int n = kTwLengths[i];
+            c.tw.soffset[i] = m_of.size();
+            const int cnt = fft_length_ok(n) ? fft_stage_exponents(n, ms.data()) : 0;
+            for (int q = 0; q < cnt; ++q) {
+                m_of.push_back(ms[q]);
+                n_of.push_back(n);
+            }
+        }
+        const size_t off = m_of.size();
         c.tw.total = off;
         std::vector<double> h64(2 * off);
         std::vector<float> h32(2 * off);
-        for (int i = 0; i < kNumTw; ++i) {
-            const int n = kTwLengths[i];
-            for (int m = 0; m < n; ++m) {
-                // W_n^m = exp(-2 pi i m / n), evaluated in long double and rounded once
-                const long double ang = -2.0L * 3.141592653589793238462643383279503L * (long double)m / (long double)n;
-                const long double cr = cosl(ang), ci = sinl(ang);
-                const size_t k = c.tw.offset[i] + m;
-                h64[2 * k] = (double)cr;
-                h64[2 * k + 1] = (double)ci;
-                h32[2 * k] = (float)cr;
-                h32[2 * k + 1] = (float)ci;
-            }
+        for (size_t k = 0; k < off; ++k) {
+            // W_n^m = exp(-2 pi i m / n), evaluated in long double and rounded once
+            const long double ang =
+                -2.0L * 3.141592653589793238462643383279503L * (long double)m_of[k] / (long double)n_of[k];
+            const long double cr = cosl(ang), ci = sinl(ang);
+            h64[2 * k] = (double)cr;
+            h64[2 * k + 1] = (double)ci;
+            h32[2 * k] = (float)cr;
+            h32[2 * k + 1] = (float)ci;
         }
         HIP_TRY(dev_alloc(&c.tw.d64, h64.size() * sizeof(double)), "twiddle allocation");
         hipError_t e = dev_alloc(&c.tw.d32, h32.size() * sizeof(float));

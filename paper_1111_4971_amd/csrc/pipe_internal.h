@@ -17,14 +17,24 @@ inline bool fft_length_ok(int n) {
     return false;
 }
 
-// Per-device twiddle bank: tw[m] = exp(-2 pi i m / N) for every N in kTwLengths.
+// Per-device twiddle bank: for every N in kTwLengths the natural table
+// tw[m] = exp(-2 pi i m / N), m < N (get), and for every FFT length the
+// stage table of the transform engine (stage; see stage_tw_offset), both in
+// one allocation per precision.
 struct TwiddleBank {
     void* d64 = nullptr;   // double2
     void* d32 = nullptr;   // float2
     size_t offset[kNumTw] = {};
+    size_t soffset[kNumTw] = {};
     size_t total = 0;
     template <typename C> const C* get(int n) const;
+    template <typename C> const C* stage(int n) const;
 };
+
+// Stage table of FFT length n: writes the exponent m of each entry (the entry
+// is W_n^m) to m_out (at least n slots) and returns the entry count, or -1 if
+// n is not an FFT length.
+int fft_stage_exponents(int n, int* m_out);
 
 // Per-member pointers of a grouped launch: blockIdx.z selects the member and its
 // entry replaces the launch's own data pointers (in/out; table/nyq for the x

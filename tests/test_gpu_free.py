@@ -43,6 +43,27 @@ def test_free_matches_eq5_oracle(torch_cuda, prec, shape, h, g0, L):
     assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_free_spectra_are_the_transform_of_eq5_green_array(torch_cuda, prec):
+    """The plan keeps one value per orbit: the forward 3-D DFT of the zero-padded
+    1/r array (real, as the array is even in every dimension); the spectra copy
+    returns it as plane 0 and zeros in planes 1..8."""
+    from oracle import free
+    from paper_1111_4971_amd import pipe
+    shape, h, g0 = (9, 7, 12), (0.1, 0.12, 0.08), 5.0
+    log("free spectra %s" % prec)
+    plan = pipe.FreePlan(*shape, *h, g0, precision=prec, L=(24, 16, 32))
+    i = plan.info
+    tab, nyq = (t.double().cpu().numpy() for t in plan.spectra())
+    full = np.concatenate([tab, nyq[..., None]], axis=3)        # kz = 0 .. lz/2
+    S = np.fft.fftn(free.green_array(shape, (i.lx, i.ly, i.lz), h, g0))
+    ref = S[:i.lx // 2 + 1, :i.ly // 2 + 1, :i.lz // 2 + 1]
+    assert np.max(np.abs(ref.imag)) <= 1e-12 * np.max(np.abs(ref))
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    assert np.max(np.abs(full[0] - ref.real)) <= tol * np.max(np.abs(ref))
+    assert not np.any(full[1:])
+
+
 def test_free_point_charge(torch_cuda):
     """rho = delta / (hx hy hz) at node c gives phi = 1/r, and g0 at c."""
     from paper_1111_4971_amd import pipe
