@@ -133,6 +133,15 @@ template <typename real> struct OrbitView {
     }
 };
 
+// acc += S t x (S = +1 or -1) as four fused multiply-adds.
+template <int S, typename C> __device__ __forceinline__ void cfma(C& acc, C t, C x) {
+    const auto tx = S > 0 ? t.x : -t.x, ty = S > 0 ? t.y : -t.y;
+    acc.x = fma(tx, x.x, acc.x);
+    acc.x = fma(-ty, x.y, acc.x);
+    acc.y = fma(tx, x.y, acc.y);
+    acc.y = fma(ty, x.x, acc.y);
+}
+
 // r[q] = rho at point q of the orbit: q = 0 (kx,ky), 1 (-kx,ky), 2 (kx,-ky), 3 (-kx,-ky).
 // Forward: Phi(p) = sum_ab sigma_ab T_ab(p) rho(S_ab p).
 // Adjoint: Phi(p) = sum_ab sigma_ab conj(T_ab(S_ab p)) g(S_ab p)  (transposed gather).
@@ -159,10 +168,11 @@ __device__ __forceinline__ void orbit_product(const Orbit<real>& o, const cplx<r
             trc = cconj(T.rc(-sx, sy));
             trr = cconj(T.rr(-sx, -sy));
         }
-        C acc = cmul(tcc, r[q]);
-        acc = csub(acc, cmul(tcr, r[qcr]));
-        acc = csub(acc, cmul(trc, r[qrc]));
-        acc = cadd(acc, cmul(trr, r[qrr]));
+        // T_cc is real: two products; the other three terms as fused multiply-adds
+        C acc = cscale(r[q], tcc.x);
+        cfma<-1>(acc, tcr, r[qcr]);
+        cfma<-1>(acc, trc, r[qrc]);
+        cfma<1>(acc, trr, r[qrr]);
         out[q] = acc;
     }
 }
