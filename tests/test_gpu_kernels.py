@@ -81,6 +81,30 @@ def test_green_table_with_offset_matches_oracle(torch_cuda, kind):
     assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
 
 
+def test_gpu_igf_kernel_matches_golden_quadrature(torch_cuda):
+    """One mode (m = n = 1) on a 1 x 1 x 21 mesh: the table's R(0, 0, r hz) is
+    g_z(kappa_11, r hz) / (2 pi a b kappa_11), so the GPU's FP64 Eq. 15 form is
+    checked directly against the 40-digit quadrature values of
+    tests/golden/igf_gz_quadrature.txt (hz = x / kappa_11 for each tabulated x)."""
+    import math
+    import os
+    from paper_1111_4971_amd import pipe
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "igf_gz_quadrature.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    a = b = 1.0
+    kap = math.pi * math.sqrt(2.0)
+    for xs in sorted({r[0] for r in rows}, key=float):
+        x = float(xs)
+        log("igf golden x=%s" % xs)
+        plan = pipe.GreenPlan(1, 1, 21, 0.5, 0.5, x / kap, a, b, kind=pipe.IGF_Z, precision="fp64",
+                              mx=1, my=1, keep_green=True)
+        got = plan.green_table().cpu().numpy()[0, 0] * (2.0 * math.pi * a * b * kap)
+        plan.close()
+        for rx, n, v in rows:
+            if rx == xs:
+                assert abs(got[int(n)] - float(v)) <= 1e-13 * float(v), (xs, n, got[int(n)], v)
+
+
 @pytest.mark.parametrize("which", ["plain_fp64_32cubed", "igf_long_bunch"])
 def test_green_table_matches_oracle_full_size(torch_cuda, which):
     from oracle import green

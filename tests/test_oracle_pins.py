@@ -5,6 +5,7 @@ textbook routine, brute force, an invariant of the pipe problem, or a second
 algorithm that shares no arithmetic with the first.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -78,6 +79,23 @@ def test_igf_rewrite_matches_quadrature_of_eq14(x, r):
         # argument moves it by that many ulps
         cond = 1.0 + x * (r + 1)
         assert abs(got - ref) <= 4e-15 * cond * abs(ref), (got, ref)
+
+
+def igf_golden():
+    """(x, n, g_z) rows of tests/golden/igf_gz_quadrature.txt (40-digit quadrature, hz = 1)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "igf_gz_quadrature.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    return [(float(x), int(n), float(v)) for x, n, v in rows]
+
+
+def test_igf_rewrite_matches_golden_quadrature():
+    """The cancellation-free Eq. 15 of the oracle against the stored quadrature values,
+    from x = kappa hz = 1e-8 (where the printed Eq. 15 loses all digits) to x = 40."""
+    rows = igf_golden()
+    assert len(rows) >= 50
+    for x, n, v in rows:
+        got = float(green.gz_igf(np.array(x), np.array([n]), 1.0)[0])
+        assert abs(got - v) <= 1e-14 * v, (x, n, got, v)
 
 
 def test_igf_literal_eq15_agrees_where_it_is_accurate():
