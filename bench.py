@@ -368,7 +368,7 @@ def blas_threads():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(wl, min_seconds=10.0, max_solves=5):
+def cpu_baseline(wl, min_seconds=10.0, max_solves=12):
     """The oracle's mode-space solve (FP64 numpy/scipy on the host cores) of the
     same 128x128x512 charge, mode kernel included, repeated until at least
     min_seconds have passed (at most max_solves); the rate is solves per second
