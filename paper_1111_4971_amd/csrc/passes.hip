@@ -1,11 +1,15 @@
 // passes.hip -- the five transform passes of one open-pipe solve, and their launchers.
 //
-// Data layout: C-order [x][y][z], z fastest.  A solve is
+// Data layout: C-order, z fastest.  A solve is
 //   P1 z-forward  real (nx, ny, nz) -> half spectrum (nx, ny, lz/2)       [z_r2c]
-//   P2 y-forward  (nx, ny, lz/2)    -> (nx, ly, lz/2), input rows j < ny  [strided]
-//   P3 x-forward, mixed product, x-inverse, in place on (nx, ly, lz/2)    [xprod]
-//   P4 y-inverse  (nx, ly, lz/2)    -> (nx, ny, lz/2), rows j < ny kept   [strided]
+//   P2 y-forward  (nx, ny, lz/2)    -> (ly, nx, lz/2), input rows j < ny  [strided]
+//   P3 x-forward, mixed product, x-inverse, in place on (ly, nx, lz/2)    [xprod]
+//   P4 y-inverse  (ly, nx, lz/2)    -> (nx, ny, lz/2), rows j < ny kept   [strided]
 //   P5 z-inverse  (nx, ny, lz/2)    -> real (nx, ny, nz), scaled           [z_c2r]
+// The y passes write and read the y-transformed array ky-major, so the rows a
+// block of P3 gathers (all x at one ky, a few kz) lie lz/2 values apart inside
+// one nx lz/2 run rather than ly lz/2 apart across the whole array; HBM serves
+// those short row segments much faster from nearby addresses.
 // The half spectrum stores kz = 0 .. lz/2 - 1 with the real kz = lz/2 value
 // packed into the imaginary part of the kz = 0 slot (both are real for real
 // input), so every z line holds exactly lz/2 complex values.
@@ -298,8 +302,8 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     const bool self = (ky == 0) || (2 * ky == ly);
     const long kz = (long)tile * T + c;
     const bool active = kz < nh;
-    const long xs = (long)ly * nh;
-    const gptr<C> line = to_global(data) + (active ? (long)kyl * nh + kz : 0);
+    const long xs = nh;
+    const gptr<C> line = to_global(data) + (active ? (long)kyl * nx * nh + kz : 0);
     LdsCol<C, T> view{lds + l * N * T + c};
 
     const int kyo = ky;

@@ -446,14 +446,15 @@ pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, h
     if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event");
     HIP_TRY(launch_z_r2c<real>(nh, (const real*)rho, nz, nz, A1, nh, (long)nx * ny, tw, st), "z forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
-    HIP_TRY(launch_strided<real>(ly, false, A1, A2, ny, ly, nh, nh, nh, (long)ny * nh, (long)ly * nh, nx, tw, st),
+    // A2 is (ly, nx, lz/2): ky-major, see passes.hip
+    HIP_TRY(launch_strided<real>(ly, false, A1, A2, ny, ly, nh, (long)nx * nh, nh, (long)ny * nh, nh, nx, tw, st),
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
     HIP_TRY(launch_xprod<real>(p->lx, adjoint, A2, nx, ly, nh, (const real*)p->table, (const real*)p->nyq, tw, st,
                                nullptr, 1, false, p->nval),
             "x pass with spectral product");
     if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event");
-    HIP_TRY(launch_strided<real>(ly, true, A2, A1, ly, ny, nh, nh, nh, (long)ly * nh, (long)ny * nh, nx, tw, st),
+    HIP_TRY(launch_strided<real>(ly, true, A2, A1, ly, ny, (long)nx * nh, nh, nh, nh, (long)ny * nh, nx, tw, st),
             "y inverse pass");
     if (ev) HIP_TRY(hipEventRecord(ev[4], st), "event");
     const real scale = (real)(p->hx * p->hy * p->hz / ((double)p->lx * p->ly * p->lz));
@@ -1134,13 +1135,13 @@ pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al
     const real scale = (real)0;  // taken from each member's GroupArgs
     HIP_TRY(launch_z_r2c<real>(nh, nullptr, nz, nz, nullptr, nh, (long)nx * ny, tw, st, args, n, al_in),
             "grouped z forward pass");
-    HIP_TRY(launch_strided<real>(ly, false, nullptr, nullptr, ny, ly, nh, nh, nh, (long)ny * nh, (long)ly * nh, nx,
+    HIP_TRY(launch_strided<real>(ly, false, nullptr, nullptr, ny, ly, nh, (long)nx * nh, nh, (long)ny * nh, nh, nx,
                                  tw, st, args + n, n),
             "grouped y forward pass");
     HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, nullptr, nullptr, tw, st, args + 2 * n, n,
                                shared_table, p->nval),
             "grouped x pass with spectral product");
-    HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, nh, nh, nh, (long)ly * nh, (long)ny * nh, nx,
+    HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, (long)nx * nh, nh, nh, nh, (long)ny * nh, nx,
                                  tw, st, args + 3 * n, n),
             "grouped y inverse pass");
     HIP_TRY(launch_z_c2r<real>(nh, nullptr, nh, nullptr, nz, nz, (long)nx * ny, scale, tw, st, args + 4 * n, n,
