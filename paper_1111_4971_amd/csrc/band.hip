@@ -13,7 +13,7 @@
 // points of each orbit (the other two are their conjugates), and the outputs
 // are packed the same way before the inverse transforms.
 //
-//   B1 y forward of packed pairs, rho -> A (nx, ly, ceil(nz/2)) complex  [strided_pair_kernel<fwd>]
+//   B1 y forward of packed pairs, rho -> A (ly, nx, ceil(nz/2)) complex  [strided_pair_kernel<fwd>]
 //   B2 x forward, split, banded product, pack, x inverse, A -> B         [xband0_kernel (N = 0),
 //                                                                         xband1_kernel / xband_kernel]
 //   B3 y inverse, unpack to the real planes, scaled                      [strided_pair_kernel<inv>]
@@ -145,7 +145,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
     const bool self = (ky == 0) || (2 * ky == ly);
     const int nzp = (nz + 1) / 2;
     const int z0 = 2 * to * tile;   // to <= T output columns per block
-    const long xs = (long)ly * nzp;
+    const long xs = nzp;
     const real* trow = table + (long)ky * (nb + 1) * 10 * NKX;
     for (int idx = threadIdx.x; idx < 10 * NKX; idx += NT) sK[idx] = trow[idx];   // distance 0 (barriers follow)
     LdsCol<C, TS> view{lds + l * N * TS + c};
@@ -175,7 +175,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
         if (ch > 0) __syncthreads();   // previous chunk's products have read the LDS
         const int pc = pbase + ch * T + c;
         const bool act = ch * T + c < ncolp && pc >= 0 && pc < nzp;
-        const C* line = in + (act ? (long)kyl * nzp + pc : 0);
+        const C* line = in + (act ? (long)kyl * nx * nzp + pc : 0);
         fft_line<N, false, false>(
             t, tw, [&](int e) -> C { return (act && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
             [&](int e, C v) { view.set(e, v); }, view);
@@ -290,7 +290,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
     // inverse x transforms of the output columns c < to, rows i < nx
     const int pco = to * tile + c;
     const bool oact = c < to && pco < nzp && !(l == 1 && self);
-    C* oline = out + (oact ? (long)kyl * nzp + pco : 0);
+    C* oline = out + (oact ? (long)kyl * nx * nzp + pco : 0);
     fft_line<N, true, true>(
         t, tw, [&](int e) -> C { return view.get(e); },
         [&](int e, C v) {
@@ -331,9 +331,9 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     const int nzp = (nz + 1) / 2;
     const int pc = tile * T + c;
     const bool active = pc < nzp;
-    const long xs = (long)ly * nzp;
-    const C* iline = in + (active ? (long)kyl * nzp + pc : 0);
-    C* oline = out + (active ? (long)kyl * nzp + pc : 0);
+    const long xs = nzp;
+    const C* iline = in + (active ? (long)kyl * nx * nzp + pc : 0);
+    C* oline = out + (active ? (long)kyl * nx * nzp + pc : 0);
     LdsCol<C, T> view{lds + l * N * T + c};
 
     fft_line<N, false, false>(
@@ -409,7 +409,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     const bool self = (ky == 0) || (2 * ky == ly);
     const int nzp = (nz + 1) / 2;
     const int z0 = 2 * to * tile;
-    const long xs = (long)ly * nzp;
+    const long xs = nzp;
     const real* trow = table + (long)ky * (nb + 1) * 10 * NKX;
     LdsCol<C, TS> view{lds + l * N * TS + c};
 
@@ -419,7 +419,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     {
         const int pc = pbase + c;
         const bool act = c < ncolp && pc >= 0 && pc < nzp;
-        const C* line = in + (act ? (long)kyl * nzp + pc : 0);
+        const C* line = in + (act ? (long)kyl * nx * nzp + pc : 0);
         fft_line<N, false, false>(
             t, tw, [&](int e) -> C { return (act && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
             [&](int e, C v) { view.set(e, v); }, view);
@@ -504,7 +504,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
 
     const int pco = to * tile + c;
     const bool oact = c < to && pco < nzp && !(l == 1 && self);
-    C* oline = out + (oact ? (long)kyl * nzp + pco : 0);
+    C* oline = out + (oact ? (long)kyl * nx * nzp + pco : 0);
     fft_line<N, true, true>(
         t, tw, [&](int e) -> C { return view.get(e); },
         [&](int e, C v) {

@@ -518,7 +518,7 @@ pipe_status_t run_band_passes(pipe_plan_s* p, const void* rho, void* phi, void* 
     char* B = A + align256((size_t)nx * ly * nzp * cb);
     const TwiddleBank& tw = p->ctx->tw;
     if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event");
-    HIP_TRY(launch_strided_pair<real>(ly, false, rho, A, ny, ly, nz, nzp, (long)ny * nz, (long)ly * nzp, nx, nz,
+    HIP_TRY(launch_strided_pair<real>(ly, false, rho, A, ny, ly, nz, (long)nx * nzp, (long)ny * nz, nzp, nx, nz,
                                       (real)1, tw, st),
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
@@ -528,7 +528,7 @@ pipe_status_t run_band_passes(pipe_plan_s* p, const void* rho, void* phi, void* 
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
     // 1/2 undoes the factor 2 of the split in the x pass
     const real scale = (real)(0.5 * p->hx * p->hy * p->hz / ((double)p->lx * p->ly));
-    HIP_TRY(launch_strided_pair<real>(ly, true, B, phi, ly, ny, nz, nzp, (long)ny * nz, (long)ly * nzp, nx, nz, scale,
+    HIP_TRY(launch_strided_pair<real>(ly, true, B, phi, ly, ny, nz, (long)nx * nzp, (long)ny * nz, nzp, nx, nz, scale,
                                       tw, st),
             "y inverse pass");
     if (ev)

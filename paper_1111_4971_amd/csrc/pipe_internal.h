@@ -116,8 +116,8 @@ hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, i
                                long out_es, long ncols, long in_ss, long out_ss, long nslabs, real scale,
                                const TwiddleBank& tw, hipStream_t s);
 // x forward, split of the packed plane pairs, sum over plane distances
-// |d| <= nb of the orbit products, packing, x inverse: in, out (nx, ly,
-// ceil(nz/2)) packed complex (distinct buffers); table: the banded
+// |d| <= nb of the orbit products, packing, x inverse: in, out (ly, nx,
+// ceil(nz/2)) packed complex, ky-major (distinct buffers); table: the banded
 // coefficients (launch_band_coefficients).  The output carries a factor 2.
 // The coefficient matrices are symmetric, so the adjoint is the same launch.
 // For nb >= 1 two x-pass kernels exist: single_window (the whole input window of
