@@ -261,6 +261,7 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
 // P3: for one ky pair (ky, ly-ky) and T consecutive kz: forward x transform of
 // the nx nonzero rows, the mixed product on each orbit {+-kx} x {+-ky} (see
 // orbit_product), inverse x transform, rows i < nx written back in place.  The
+// data is the ky-major (ly, nx, lz/2) array, so a line's rows are lz/2 apart.  The
 // spectra are stored tile-blocked (see xprod_tile); the kz = lz/2 values sit in
 // `nyq`.  NV = 9: the four terms; NV = 1: T_cc alone (free space), where the
 // product is a real scaling and its own adjoint.
@@ -302,7 +303,7 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     const bool self = (ky == 0) || (2 * ky == ly);
     const long kz = (long)tile * T + c;
     const bool active = kz < nh;
-    const long xs = nh;
+    const long xs = nh;   // row (x) stride of the ky-major array
     const gptr<C> line = to_global(data) + (active ? (long)kyl * nx * nh + kz : 0);
     LdsCol<C, T> view{lds + l * N * T + c};
 
