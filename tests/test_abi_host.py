@@ -205,3 +205,43 @@ def test_fft3d_rejects_partial_overlap():
     L = pipe.lib()
     a, b = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x100000 + 16)
     assert L.pipe_fft3d(8, 8, 8, 8, b"fff", a, b, None) == 6
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include <string.h>
+#include "pipe_poisson.h"
+int main(void) {
+    pipe_plan_t plan = 0;
+    /* zero nodes: rejected by validation, before any device call */
+    pipe_status_t st = pipe_green_plan(0, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, PIPE_GREEN_IGF_Z, &plan);
+    if (st != PIPE_ERR_INVALID_ARG || plan != 0) return 1;
+    if (strcmp(pipe_status_string(st), "PIPE_ERR_INVALID_ARG") != 0) return 2;
+    if (strlen(pipe_last_error()) == 0) return 3;
+    printf("%s: %s\n", pipe_status_string(st), pipe_last_error());
+    return 0;
+}
+"""
+
+
+@needs_lib
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/pipe_poisson.h compiles as C99 (no C++ in the boundary), and a C
+    program linked against libpipe.so gets the documented status for a bad call."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "use_abi.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "use_abi"
+    libdir = os.path.dirname(LIB)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(root, "include"), str(src),
+                        "-L", libdir, "-lpipe", "-Wl,-rpath," + libdir, "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert r.stdout.startswith("PIPE_ERR_INVALID_ARG")
