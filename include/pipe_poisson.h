@@ -124,9 +124,13 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
  * on scratch buffers and keeps the fastest: one solve at a time (latency)
  * with PIPE_AUTOTUNE, one grouped launch of 16 concurrent solves (throughput,
  * the batched form) with PIPE_AUTOTUNE_BATCH.  The choice is cached for the
- * process per (mesh, precision, mode) and appended to the file named by the
- * environment variable PIPE_TUNE_CACHE, if set, which later processes read
- * (one line per entry: nx ny nz real_bytes members lx ly lz).
+ * process per (device architecture, mesh, precision, values per spectra
+ * orbit, mode) and appended to the file named by the environment variable
+ * PIPE_TUNE_CACHE, if set, which later processes read (one line per entry:
+ * "pipe-tune-v2 arch nx ny nz real_bytes nval members lx ly lz"; nval is 9 for
+ * pipe plans and 1 for free-space plans, members 1 or 16).  An entry whose
+ * lengths this mesh cannot use (see the rules above) is ignored and the
+ * lengths are tuned again; malformed lines are skipped.
  */
 pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, double hz,
                                  double a, double b, int kind, int mx, int my,
@@ -222,15 +226,27 @@ pipe_status_t pipe_batch_workspace(pipe_batch_t batch, size_t* bytes);
 
 /*
  * pipe_batch_solve -- phi[s] = A_s rho[s] for every member s.  rho and phi
- * are host arrays of count device pointers; the graph is rebuilt only when
- * the pointers or workspace differ from the previous call.  Asynchronous on
- * hip_stream.  Errors: INVALID_ARG, ALIASING, HIP.
+ * are host arrays of count device pointers.  The grouped kernels read their
+ * per-member pointers from a device descriptor array: when the pointers or the
+ * workspace differ from the previous call, the new descriptors are copied on
+ * hip_stream (ordered after the previous replay, on whatever stream it ran)
+ * and the captured graph is replayed unchanged.  The graph is captured again
+ * only on the first call, when a banded member's pointers or the workspace of
+ * a batch holding banded members change, or when the 2-element alignment of a
+ * shape group's rho or phi pointers changes.  Asynchronous on hip_stream.
+ * Replays on different streams are ordered by the library (each waits for the
+ * descriptor copy it needs).  Errors: INVALID_ARG, ALIASING, HIP.
  */
 pipe_status_t pipe_batch_solve(pipe_batch_t batch, const void* const* rho, void* const* phi,
                                void* workspace, void* hip_stream);
 
 /* Destroy a plan or batch.  A handle that is not live (e.g. destroyed twice)
- * is rejected with INVALID_ARG.  Waits for the device before freeing. */
+ * is rejected with INVALID_ARG.  Before freeing, waits for the work this
+ * handle queued itself: every solve queued on a plan (one event per stream it
+ * was used on, recorded after the solve's last kernel; solves queued while
+ * their stream was being captured into a graph are the caller's to order), or
+ * a batch's last replay and descriptor copy.  Other work on the device is not
+ * waited for (the HIP runtime's free itself may still synchronise). */
 pipe_status_t pipe_plan_destroy(pipe_plan_t plan);
 pipe_status_t pipe_batch_destroy(pipe_batch_t batch);
 

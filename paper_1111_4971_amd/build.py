@@ -15,7 +15,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpipe.so")
-SOURCES = ["passes.hip", "band.hip", "fft3d.hip", "green.hip", "pipe_api.cpp"]
+# (source, unit): the kernel files are compiled as two units each, FP32 kernels
+# with the precision-independent code (PIPE_TU=1) and FP64 kernels (PIPE_TU=2)
+SOURCES = [("passes.hip", 1), ("passes.hip", 2), ("band.hip", 1), ("band.hip", 2), ("fft3d.hip", 1),
+           ("fft3d.hip", 2), ("green.hip", 0), ("pipe_api.cpp", 0)]
 ARCH = os.environ.get("PIPE_OFFLOAD_ARCH", "gfx950")
 
 
@@ -33,9 +36,11 @@ def flags():
             "-I" + os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 
 
-def _compile(src):
-    out = os.path.join(OBJ, src + ".o")
-    cmd = [hipcc()] + flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
+def _compile(unit):
+    src, tu = unit
+    out = os.path.join(OBJ, "%s.%d.o" % (src, tu))
+    cmd = [hipcc()] + flags() + (["-DPIPE_TU=%d" % tu] if tu else []) + ["-x", "hip", "-c",
+                                                                        os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

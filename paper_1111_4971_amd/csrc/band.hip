@@ -19,6 +19,15 @@
 //   B3 y inverse, unpack to the real planes, scaled                      [strided_pair_kernel<inv>]
 #include "pass_common.h"
 
+// Compiled as one unit (PIPE_TU undefined) or as two: PIPE_TU = 1 (FP32
+// kernels and the precision-independent functions), PIPE_TU = 2 (FP64 kernels).
+#if !defined(PIPE_TU) || PIPE_TU == 1
+#define PIPE_TU_FP32 1
+#endif
+#if !defined(PIPE_TU) || PIPE_TU == 2
+#define PIPE_TU_FP64 1
+#endif
+
 namespace pipe {
 
 // y pass between real planes (pairs of z columns) and packed complex columns.
@@ -546,6 +555,7 @@ void strided_real_kernel(const void* in, void* out, int n_in, int n_out, long in
         view);
 }
 
+#if PIPE_TU_FP32
 // The four terms' 2-D spectra of one plane distance, 9 values per orbit in
 // the 3-D orbit table's order (0 T_cc, 1-2 T_cr, 3-4 T_rc, 5-6 T_rr(kx,ky),
 // 7-8 T_rr(-kx,ky)), FP64, planar: value p of (kyo, d, kxo) at
@@ -575,6 +585,7 @@ __global__ void compress_band_kernel(const double2* __restrict__ S, double* tmp,
         }
     }
 }
+#endif
 
 // K0..K9 of xband_kernel from the nine values (cc; cr = p + iq; rc = u + iv;
 // rr = m + in; rr(-kx) = m2 + i n2), computed in FP64 and rounded once:
@@ -654,16 +665,18 @@ hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, i
     return hipErrorInvalidValue;
 }
 
+#if PIPE_TU_FP32
 int band_tile(int lx, int real_bytes) {
     switch (lx) {
 #define X(N_) \
     case N_: return real_bytes == 8 ? band_T<double, N_>() : band_T<float, N_>();
-        PIPE_FOR_EACH_N(X)
+        PIPE_FOR_EACH_BAND_N(X)
 #undef X
     }
     return 0;
 }
 
+#endif
 // Output columns per block of xband_kernel: as many as leave the input window
 // (to + nb + (nb odd) packed columns) inside one chunk of T, while that keeps
 // at least half the tile; otherwise T, with the window taken in several chunks.
@@ -679,15 +692,17 @@ static int band_small_columns(int T, int nb) {
     return 4 * to >= T && to >= 1 ? to : 0;
 }
 
+#if PIPE_TU_FP32
 int band_small_columns_for(int lx, int real_bytes, int nb) {
     switch (lx) {
 #define X(N_) \
     case N_: return band_small_columns(real_bytes == 8 ? band0_T<double, N_>() : band0_T<float, N_>(), nb);
-        PIPE_FOR_EACH_N(X)
+        PIPE_FOR_EACH_BAND_N(X)
 #undef X
     }
     return 0;
 }
+#endif
 
 template <typename real>
 hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
@@ -720,12 +735,13 @@ hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int n
         }                                                                                            \
         return hipGetLastError();                                                                    \
     }
-        PIPE_FOR_EACH_N(X)
+        PIPE_FOR_EACH_BAND_N(X)
 #undef X
     }
     return hipErrorInvalidValue;
 }
 
+#if PIPE_TU_FP32
 static unsigned blocks_for(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_compress_band(const void* spec, double* tmp, int term, int lx, int ly, int D, hipStream_t st) {
@@ -750,6 +766,7 @@ hipError_t launch_band_coefficients(const double* tmp, void* table, int real_byt
                            (float*)table, rows, kxo_n);
     return hipGetLastError();
 }
+#endif
 
 #define PIPE_INST(real)                                                                                      \
     template hipError_t launch_strided_pair<real>(int, bool, const void*, void*, int, int, long, long, long, \
@@ -758,8 +775,13 @@ hipError_t launch_band_coefficients(const double* tmp, void* table, int real_byt
                                                   long, long, long, real, const TwiddleBank&, hipStream_t);  \
     template hipError_t launch_xband<real>(int, const void*, void*, int, int, int, int, const real*,         \
                                            const TwiddleBank&, hipStream_t, bool);
+
+#if PIPE_TU_FP32
 PIPE_INST(float)
+#endif
+#if PIPE_TU_FP64
 PIPE_INST(double)
+#endif
 #undef PIPE_INST
 
 }  // namespace pipe

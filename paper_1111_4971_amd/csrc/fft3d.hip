@@ -60,7 +60,11 @@ hipError_t launch_lines(int n, bool inverse, const void* in, void* out, long nli
     return hipErrorInvalidValue;
 }
 
+#if !defined(PIPE_TU) || PIPE_TU == 1
 template hipError_t launch_lines<float>(int, bool, const void*, void*, long, const TwiddleBank&, hipStream_t);
+#endif
+#if !defined(PIPE_TU) || PIPE_TU == 2
 template hipError_t launch_lines<double>(int, bool, const void*, void*, long, const TwiddleBank&, hipStream_t);
+#endif
 
 }  // namespace pipe

@@ -1,13 +1,14 @@
 // fft_engine.h -- register/LDS Stockham FFT building blocks for gfx950.
 //
-// A length-N line is processed by P = N/E threads, each holding E complex
-// values in registers.  Every stage of radix R applies E/R radix-R butterflies
-// per thread (Stockham autosort: inputs j + r N/R, twiddles W_{Ns R}^{r (j mod Ns)},
-// outputs (j div Ns) Ns R + (j mod Ns) + r Ns).  Between stages the line is
-// exchanged through LDS.  The first stage reads its inputs straight from any
-// source (global memory with zero padding, or LDS) and the last stage writes
-// element j + r N/R, i.e. natural order, straight to any sink, so a transform
-// costs (stages - 1) LDS round trips.
+// A length-N line (N = 2^p 3^q, 8 <= N <= 1024) is processed by P = N/E
+// threads, each holding E complex values in registers.  Every stage of radix R
+// (2, 3, 4, 8, 9 or 16) applies E/R radix-R butterflies per thread (Stockham
+// autosort: inputs j + r N/R, twiddles W_{Ns R}^{r (j mod Ns)}, outputs
+// (j div Ns) Ns R + (j mod Ns) + r Ns).  Between stages the line is exchanged
+// through LDS.  The first stage reads its inputs straight from any source
+// (global memory with zero padding, or LDS) and the last stage writes element
+// j + r N/R, i.e. natural order, straight to any sink, so a transform costs
+// (stages - 1) LDS round trips.
 //
 // Direction: forward uses W = e^{-2 pi i/N}, inverse W^{-1}; both unscaled.
 // Twiddles come from a per-length stage table (stage_tw_offset) whose values
@@ -135,47 +136,108 @@ template <bool INV, typename C> __device__ __forceinline__ void dft16(C* v) {
     }
 }
 
+template <bool INV, typename C> __device__ __forceinline__ void dft9(C* v) {
+    using R = decltype(C::x);
+    // n = n1 + 3 n2, k = k2 + 3 k1:  three DFT3 over n2, twiddle W9^{n1 k2}, three DFT3 over n1
+    C a[3][3];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+#pragma unroll
+        for (int n2 = 0; n2 < 3; ++n2) a[n1][n2] = v[n1 + 3 * n2];
+        dft3<INV>(a[n1]);
+    }
+    // W9^m = cos(2 pi m/9) -+ i sin(2 pi m/9) for m = n1 k2 in {1, 2, 4}
+    const R sg = INV ? (R)1 : (R)-1;
+    const C w1 = cmake<C>((R)0.766044443118978035202392650555416674, sg * (R)0.642787609686539326322643409907263433);
+    const C w2 = cmake<C>((R)0.173648177666930348851716626769314796, sg * (R)0.984807753012208059366743024589523014);
+    const C w4 = cmake<C>((R)-0.93969262078590838405410927732473147, sg * (R)0.342020143325668733044099614682259581);
+    a[1][1] = cmul(a[1][1], w1);
+    a[1][2] = cmul(a[1][2], w2);
+    a[2][1] = cmul(a[2][1], w2);
+    a[2][2] = cmul(a[2][2], w4);
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2) {
+        C b[3] = {a[0][k2], a[1][k2], a[2][k2]};
+        dft3<INV>(b);
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) v[k2 + 3 * k1] = b[k1];
+    }
+}
+
 template <int R, bool INV, typename C> __device__ __forceinline__ void dft(C* v) {
     if constexpr (R == 2) dft2<INV>(v);
     else if constexpr (R == 3) dft3<INV>(v);
     else if constexpr (R == 4) dft4<INV>(v);
     else if constexpr (R == 8) dft8<INV>(v);
+    else if constexpr (R == 9) dft9<INV>(v);
     else if constexpr (R == 16) dft16<INV>(v);
     else static_assert(R == 2, "unsupported radix");
 }
 
 // ---------------------------------------------------------------- length plans
-// E = values per thread, radices applied first to last (product = N, each divides E).
+// E = values per thread, then the radices applied first to last (product N,
+// each dividing E).  E stays <= 24 so that a z-pass thread can hold two lines'
+// worth of FP64 values (current and prefetched); single-stage plans have
+// P = 1, so a line is never shared by threads of one stage (in-place safe).
 
 template <int N> struct Plan;
-#define PIPE_PLAN(N_, E_, S_, R0_, R1_, R2_, R3_)                                  \
-    template <> struct Plan<N_> {                                                   \
-        static constexpr int E = E_, S = S_;                                        \
-        static constexpr int radix(int s) {                                         \
-            return s == 0 ? R0_ : s == 1 ? R1_ : s == 2 ? R2_ : R3_;                \
-        }                                                                           \
+#define PIPE_PLAN(N_, E_, ...)                                                         \
+    template <> struct Plan<N_> {                                                      \
+        static constexpr int E = E_;                                                   \
+        static constexpr int rad[] = {__VA_ARGS__};                                    \
+        static constexpr int S = (int)(sizeof(rad) / sizeof(int));                     \
+        static constexpr int radix(int s) { return rad[s]; }                           \
     };
-PIPE_PLAN(8, 8, 1, 8, 1, 1, 1)
-PIPE_PLAN(12, 12, 2, 3, 4, 1, 1)
-PIPE_PLAN(16, 16, 1, 16, 1, 1, 1)
-PIPE_PLAN(24, 24, 2, 3, 8, 1, 1)
-PIPE_PLAN(32, 8, 2, 4, 8, 1, 1)
-PIPE_PLAN(48, 12, 3, 3, 4, 4, 1)
-PIPE_PLAN(64, 8, 2, 8, 8, 1, 1)
-PIPE_PLAN(96, 24, 3, 3, 4, 8, 1)
-PIPE_PLAN(128, 16, 2, 8, 16, 1, 1)
-PIPE_PLAN(192, 24, 3, 3, 8, 8, 1)
-PIPE_PLAN(256, 16, 2, 16, 16, 1, 1)
-PIPE_PLAN(384, 24, 4, 3, 8, 8, 2)
-PIPE_PLAN(512, 8, 3, 8, 8, 8, 1)
-PIPE_PLAN(768, 24, 4, 3, 8, 8, 4)
-PIPE_PLAN(1024, 16, 3, 16, 16, 4, 1)
+PIPE_PLAN(8, 8, 8)
+PIPE_PLAN(9, 9, 9)
+PIPE_PLAN(12, 12, 3, 4)
+PIPE_PLAN(16, 16, 16)
+PIPE_PLAN(18, 6, 3, 3, 2)
+PIPE_PLAN(24, 24, 3, 8)
+PIPE_PLAN(27, 9, 9, 3)
+PIPE_PLAN(32, 8, 4, 8)
+PIPE_PLAN(36, 12, 3, 3, 4)
+PIPE_PLAN(48, 12, 3, 4, 4)
+PIPE_PLAN(54, 18, 9, 3, 2)
+PIPE_PLAN(64, 8, 8, 8)
+PIPE_PLAN(72, 24, 3, 3, 8)
+PIPE_PLAN(81, 9, 9, 9)
+PIPE_PLAN(96, 24, 3, 4, 8)
+PIPE_PLAN(108, 12, 3, 3, 3, 4)
+PIPE_PLAN(128, 16, 8, 16)
+PIPE_PLAN(144, 12, 3, 3, 4, 4)
+PIPE_PLAN(162, 18, 9, 9, 2)
+PIPE_PLAN(192, 24, 3, 8, 8)
+PIPE_PLAN(216, 24, 3, 3, 3, 8)
+PIPE_PLAN(243, 9, 9, 9, 3)
+PIPE_PLAN(256, 16, 16, 16)
+PIPE_PLAN(288, 24, 3, 3, 8, 4)
+PIPE_PLAN(324, 18, 9, 9, 2, 2)
+PIPE_PLAN(384, 24, 3, 8, 8, 2)
+PIPE_PLAN(432, 24, 3, 3, 3, 8, 2)
+PIPE_PLAN(486, 18, 9, 9, 3, 2)
+PIPE_PLAN(512, 8, 8, 8, 8)
+PIPE_PLAN(576, 24, 3, 3, 8, 8)
+PIPE_PLAN(648, 18, 9, 9, 2, 2, 2)
+PIPE_PLAN(729, 9, 9, 9, 9)
+PIPE_PLAN(768, 24, 3, 8, 8, 4)
+PIPE_PLAN(864, 24, 3, 3, 3, 8, 4)
+PIPE_PLAN(972, 18, 9, 9, 3, 2, 2)
+PIPE_PLAN(1024, 16, 16, 16, 4)
 #undef PIPE_PLAN
 
 template <int N> __host__ __device__ constexpr int plan_ns(int s) {
     int ns = 1;
     for (int i = 0; i < s; ++i) ns *= Plan<N>::radix(i);
     return ns;
+}
+
+template <int N> constexpr bool plan_ok() {
+    constexpr int E = Plan<N>::E, S = Plan<N>::S;
+    if (N % E != 0 || plan_ns<N>(S) != N) return false;
+    for (int s = 0; s < S; ++s)
+        if (E % Plan<N>::radix(s) != 0) return false;
+    return S > 1 || E == N;
 }
 
 // Stage twiddle table of length N: stage s >= 1 (radix R, span NS) owns R - 1
@@ -235,46 +297,32 @@ __device__ __forceinline__ void stage_store(const C* v, int t, Dst dst) {
     }
 }
 
+// Stage s of the transform from its inputs in registers: twiddle and
+// butterflies, then the last stage stores to dst, any other stage exchanges
+// through LDS and continues with stage s + 1.
+template <int N, int s, bool INV, typename C, typename Dst, typename Lds>
+__device__ __forceinline__ void fft_stages(C* v, int t, const C* __restrict__ tw, Dst dst, Lds lds) {
+    constexpr int R = Plan<N>::radix(s), NS = plan_ns<N>(s);
+    stage_compute<N, R, NS, INV>(v, t, tw);
+    if constexpr (s == Plan<N>::S - 1) {
+        stage_store<N, R, NS>(v, t, dst);
+    } else {
+        stage_store<N, R, NS>(v, t, [&](int e, C x) { lds.set(e, x); });
+        __syncthreads();
+        stage_load<N, Plan<N>::radix(s + 1)>(v, t, [&](int e) { return lds.get(e); });
+        __syncthreads();
+        fft_stages<N, s + 1, INV>(v, t, tw, dst, lds);
+    }
+}
+
 // Whole transform from stage-0 inputs already in registers (v, loaded by
 // stage_load<N, radix(0)>).  dst is the element accessor of the last store;
 // lds.get(e) / lds.set(e, v) address this thread's line in LDS.  Every thread
 // of the block must call this (it contains barriers).
 template <int N, bool INV, typename C, typename Dst, typename Lds>
 __device__ __forceinline__ void fft_line_regs(C* v, int t, const C* __restrict__ tw, Dst dst, Lds lds) {
-    constexpr int S = Plan<N>::S;
-    constexpr int R0 = Plan<N>::radix(0);
-    stage_compute<N, R0, 1, INV>(v, t, tw);
-    if constexpr (S == 1) {
-        stage_store<N, R0, plan_ns<N>(0)>(v, t, dst);
-    } else {
-        stage_store<N, R0, 1>(v, t, [&](int e, C x) { lds.set(e, x); });
-        __syncthreads();
-        constexpr int R1 = Plan<N>::radix(1);
-        stage_load<N, R1>(v, t, [&](int e) { return lds.get(e); });
-        __syncthreads();
-        stage_compute<N, R1, plan_ns<N>(1), INV>(v, t, tw);
-        if constexpr (S == 2) {
-            stage_store<N, R1, plan_ns<N>(1)>(v, t, dst);
-        } else {
-            stage_store<N, R1, plan_ns<N>(1)>(v, t, [&](int e, C x) { lds.set(e, x); });
-            __syncthreads();
-            constexpr int R2 = Plan<N>::radix(2);
-            stage_load<N, R2>(v, t, [&](int e) { return lds.get(e); });
-            __syncthreads();
-            stage_compute<N, R2, plan_ns<N>(2), INV>(v, t, tw);
-            if constexpr (S == 3) {
-                stage_store<N, R2, plan_ns<N>(2)>(v, t, dst);
-            } else {
-                stage_store<N, R2, plan_ns<N>(2)>(v, t, [&](int e, C x) { lds.set(e, x); });
-                __syncthreads();
-                constexpr int R3 = Plan<N>::radix(3);
-                stage_load<N, R3>(v, t, [&](int e) { return lds.get(e); });
-                __syncthreads();
-                stage_compute<N, R3, plan_ns<N>(3), INV>(v, t, tw);
-                stage_store<N, R3, plan_ns<N>(3)>(v, t, dst);
-            }
-        }
-    }
+    static_assert(plan_ok<N>(), "inconsistent length plan");
+    fft_stages<N, 0, INV>(v, t, tw, dst, lds);
 }
 
 // Whole transform.  src/dst are element accessors for the first load and the

@@ -42,8 +42,17 @@ constexpr int ce_max(int a, int b) { return a > b ? a : b; }
 #define PIPE_TW_LDS 1        // stage twiddle tables in LDS at block start
 #endif
 
-// Every supported FFT length, for the launchers' switch statements.
-#define PIPE_FOR_EACH_N(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+// Every supported FFT length (every 2^p 3^q in [8, 1024]), for the launchers'
+// switch statements; must list the same lengths as kFftLengths.
+#define PIPE_FOR_EACH_N(X)                                                                               \
+    X(8) X(9) X(12) X(16) X(18) X(24) X(27) X(32) X(36) X(48) X(54) X(64) X(72) X(81) X(96) X(108)      \
+    X(128) X(144) X(162) X(192) X(216) X(243) X(256) X(288) X(324) X(384) X(432) X(486) X(512) X(576) \
+    X(648) X(729) X(768) X(864) X(972) X(1024)
+// The lengths the banded x pass takes: its orbit items tile E/4 per thread, so
+// N and the plan's E must be multiples of 4; must match kBandLengths.
+#define PIPE_FOR_EACH_BAND_N(X)                                                                          \
+    X(8) X(12) X(16) X(24) X(32) X(36) X(48) X(64) X(72) X(96) X(108) X(128) X(144) X(192) X(216)       \
+    X(256) X(288) X(384) X(432) X(512) X(576) X(768) X(864) X(1024)
 
 // Column tile of the y passes: PIPE_STRIDED_TMAX columns per row segment,
 // halved until the block's LDS (N x T complex) fits in PIPE_LDS_CAP.

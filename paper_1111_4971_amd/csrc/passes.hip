@@ -25,28 +25,37 @@
 
 namespace pipe {
 
-template <> const float2* TwiddleBank::get<float2>(int n) const {
-    for (int i = 0; i < kNumTw; ++i)
-        if (kTwLengths[i] == n) return reinterpret_cast<const float2*>(d32) + offset[i];
+// One source, compiled as one unit (PIPE_TU undefined) or as two: PIPE_TU = 1
+// (the FP32 kernels and the precision-independent functions) and PIPE_TU = 2
+// (the FP64 kernels), which halves the longest compile.
+#if !defined(PIPE_TU) || PIPE_TU == 1
+#define PIPE_TU_FP32 1
+#endif
+#if !defined(PIPE_TU) || PIPE_TU == 2
+#define PIPE_TU_FP64 1
+#endif
+
+#if PIPE_TU_FP32
+template <typename C> static const C* bank_base(const TwiddleBank& b);
+template <> const float2* bank_base<float2>(const TwiddleBank& b) { return reinterpret_cast<const float2*>(b.d32); }
+template <> const double2* bank_base<double2>(const TwiddleBank& b) { return reinterpret_cast<const double2*>(b.d64); }
+
+template <typename C> const C* TwiddleBank::get(int n) const {
+    for (int i = 0; i < kNumFft; ++i) {
+        if (kFftLengths[i] == n) return bank_base<C>(*this) + offset[i];
+        if (2 * kFftLengths[i] == n) return bank_base<C>(*this) + offset2[i];
+    }
     return nullptr;
 }
-template <> const double2* TwiddleBank::get<double2>(int n) const {
-    for (int i = 0; i < kNumTw; ++i)
-        if (kTwLengths[i] == n) return reinterpret_cast<const double2*>(d64) + offset[i];
+template <typename C> const C* TwiddleBank::stage(int n) const {
+    for (int i = 0; i < kNumFft; ++i)
+        if (kFftLengths[i] == n) return bank_base<C>(*this) + soffset[i];
     return nullptr;
 }
-template <> const float2* TwiddleBank::stage<float2>(int n) const {
-    if (!fft_length_ok(n)) return nullptr;
-    for (int i = 0; i < kNumTw; ++i)
-        if (kTwLengths[i] == n) return reinterpret_cast<const float2*>(d32) + soffset[i];
-    return nullptr;
-}
-template <> const double2* TwiddleBank::stage<double2>(int n) const {
-    if (!fft_length_ok(n)) return nullptr;
-    for (int i = 0; i < kNumTw; ++i)
-        if (kTwLengths[i] == n) return reinterpret_cast<const double2*>(d64) + soffset[i];
-    return nullptr;
-}
+template const float2* TwiddleBank::get<float2>(int) const;
+template const double2* TwiddleBank::get<double2>(int) const;
+template const float2* TwiddleBank::stage<float2>(int) const;
+template const double2* TwiddleBank::stage<double2>(int) const;
 
 template <int N> static int stage_exponents(int* m) {
     int i = 0;
@@ -67,6 +76,7 @@ int fft_stage_exponents(int n, int* m_out) {
     }
     return -1;
 }
+#endif
 
 // The z passes are persistent: block b handles line groups b, b + gridDim.x, ...
 // (LPW lines per group) and issues the global loads of its next group before
@@ -505,6 +515,7 @@ template <typename real, int N> constexpr int xprod_T() {
     return t;
 }
 
+#if PIPE_TU_FP32
 int xprod_tile(int lx, int real_bytes) {
     switch (lx) {
 #define X(N_) \
@@ -514,6 +525,7 @@ int xprod_tile(int lx, int real_bytes) {
     }
     return 0;
 }
+#endif
 
 template <typename real>
 hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh, const real* table,
@@ -555,8 +567,12 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
                                              const GroupArgs*, int);                                    \
     template hipError_t launch_xprod<real>(int, bool, void*, int, int, int, const real*, const real*,  \
                                            const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool, int);
+#if PIPE_TU_FP32
 PIPE_INST(float)
+#endif
+#if PIPE_TU_FP64
 PIPE_INST(double)
+#endif
 #undef PIPE_INST
 
 }  // namespace pipe

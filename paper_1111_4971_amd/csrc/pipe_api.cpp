@@ -14,6 +14,7 @@
 #include <mutex>
 #include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pipe_poisson.h"
@@ -77,23 +78,25 @@ pipe_status_t device_ctx(int dev, DeviceCtx** out) {
     if (dev < 0 || dev >= 64) return fail(PIPE_ERR_NO_DEVICE, "device index %d out of range", dev);
     DeviceCtx& c = g_ctx[dev];
     if (!c.ready) {
-        // natural tables (exponent m at offset + m), then the stage tables of
-        // the FFT lengths (exponents from fft_stage_exponents)
+        // natural tables of lengths N and 2N (exponent m at offset + m), then
+        // the stage tables of the FFT lengths (exponents from fft_stage_exponents)
         std::vector<int> m_of;   // exponent of every entry
         std::vector<int> n_of;   // its table length
-        for (int i = 0; i < kNumTw; ++i) {
-            const int n = kTwLengths[i];
-            c.tw.offset[i] = m_of.size();
-            for (int m = 0; m < n; ++m) {
-                m_of.push_back(m);
-                n_of.push_back(n);
+        for (int i = 0; i < kNumFft; ++i) {
+            for (int twice = 0; twice < 2; ++twice) {
+                const int n = kFftLengths[i] << twice;
+                (twice ? c.tw.offset2[i] : c.tw.offset[i]) = m_of.size();
+                for (int m = 0; m < n; ++m) {
+                    m_of.push_back(m);
+                    n_of.push_back(n);
+                }
             }
         }
         std::vector<int> ms(4096);
-        for (int i = 0; i < kNumTw; ++i) {
-            const int n = kTwLengths[i];
+        for (int i = 0; i < kNumFft; ++i) {
+            const int n = kFftLengths[i];
             c.tw.soffset[i] = m_of.size();
-            const int cnt = fft_length_ok(n) ? fft_stage_exponents(n, ms.data()) : 0;
+            const int cnt = fft_stage_exponents(n, ms.data());
             for (int q = 0; q < cnt; ++q) {
                 m_of.push_back(ms[q]);
                 n_of.push_back(n);
@@ -150,6 +153,12 @@ int pick_length(int need) {
     return -1;
 }
 
+int pick_band_length(int need) {
+    for (int v : kBandLengths)
+        if (v >= need) return v;
+    return -1;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- plan
@@ -175,6 +184,9 @@ struct pipe_plan_s {
     // event timing (pipe_plan_timing): 6 events per recorded solve
     std::vector<hipEvent_t> tev;
     int tmax = 0, tn = 0;
+    // one event per stream the plan has solved on, recorded after each solve's
+    // last kernel: destroy waits on these rather than on the whole device
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
 
 namespace {
@@ -246,8 +258,11 @@ pipe_status_t validate(int nx, int ny, int nz, double hx, double hy, double hz, 
             return PIPE_OK;
         }
         if (*L < 2 * n - 1) return fail(PIPE_ERR_INVALID_ARG, "%s: padded length %d < 2n - 1 = %d", nm, *L, 2 * n - 1);
-        if (*L % 2) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "%s: padded length %d must be even", nm, *L);
-        if (!fft_length_ok(half ? *L / 2 : *L)) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "%s: padded length %d not supported", nm, *L);
+        // z is transformed real-to-complex as lz/2 packed pairs, so lz must be even
+        if (half && *L % 2) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "%s: padded length %d must be even", nm, *L);
+        if (!fft_length_ok(half ? *L / 2 : *L))
+            return fail(PIPE_ERR_UNSUPPORTED_SIZE, "%s: padded length %d is not of the form 2^p 3^q in [%d, %d]", nm,
+                        *L, half ? 16 : 8, half ? 2048 : 1024);
         return PIPE_OK;
     };
     pipe_status_t st;
@@ -404,10 +419,33 @@ pipe_status_t build_band_spectra(pipe_plan_s* p, hipStream_t st, int nband, doub
     return PIPE_OK;
 }
 
+std::mutex g_use_mu;
+
+// Record that a solve on stream st has just been queued (skipped while the
+// stream is being captured into a graph: the caller then owns the ordering).
+hipError_t note_use(pipe_plan_s* p, hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess || cs != hipStreamCaptureStatusNone) return e;
+    std::lock_guard<std::mutex> lk(g_use_mu);
+    for (auto& u : p->uses)
+        if (u.first == st) return hipEventRecord(u.second, st);
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    p->uses.push_back({st, ev});
+    return hipEventRecord(ev, st);
+}
+
 void plan_free(pipe_plan_s* p) {
     if (!p) return;
     (void)hipSetDevice(p->device);
-    (void)hipDeviceSynchronize();
+    // wait for this plan's own queued solves only
+    for (auto& u : p->uses) {
+        (void)hipEventSynchronize(u.second);
+        (void)hipEventDestroy(u.second);
+    }
+    for (hipEvent_t e : p->tev) (void)hipEventSynchronize(e);
     for (hipEvent_t e : p->tev) (void)hipEventDestroy(e);
     if (p->table) (void)hipFree(p->table);
     if (p->green) (void)hipFree(p->green);
@@ -551,6 +589,10 @@ pipe_status_t solve_impl(pipe_plan_t plan, const void* rho, void* phi, void* ws,
     else
         s = plan->rb == 8 ? run_passes<double>(plan, rho, phi, ws, st, adjoint, ev)
                           : run_passes<float>(plan, rho, phi, ws, st, adjoint, ev);
+    if (s == PIPE_OK) {
+        const hipError_t e = note_use(plan, st);
+        if (e != hipSuccess) s = hip_fail(e, "solve completion event");
+    }
     if (cur != plan->device) (void)hipSetDevice(cur);
     return s;
 }
@@ -568,25 +610,47 @@ pipe_status_t solve_impl(pipe_plan_t plan, const void* rho, void* phi, void* ws,
 namespace {
 
 struct TuneKey {
-    int nx, ny, nz, rb, members;
+    std::string arch;   // device architecture (gcnArchName): timings do not carry across chips
+    int nx, ny, nz, rb, nval, members;
     bool operator<(const TuneKey& o) const {
-        return std::tie(nx, ny, nz, rb, members) < std::tie(o.nx, o.ny, o.nz, o.rb, o.members);
+        return std::tie(arch, nx, ny, nz, rb, nval, members) <
+               std::tie(o.arch, o.nx, o.ny, o.nz, o.rb, o.nval, o.members);
     }
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, std::array<int, 3>> g_tune;
-bool g_tune_loaded = false;
+std::string g_tune_loaded;   // the cache file read last (re-read when PIPE_TUNE_CACHE names another)
 
+// Padded lengths a cached entry may hold for this mesh: the same rules as
+// explicit lengths in validate() (even, >= 2n - 1, a supported transform).
+bool tuned_lengths_ok(const TuneKey& k, const std::array<int, 3>& v) {
+    const int n[3] = {k.nx, k.ny, k.nz};
+    for (int d = 0; d < 3; ++d) {
+        const int L = v[d];
+        if (L < 2 * n[d] - 1 || (d == 2 && L % 2)) return false;
+        if (!fft_length_ok(d == 2 ? L / 2 : L)) return false;
+    }
+    return true;
+}
+
+// Cache file: one entry per line, "pipe-tune-v2 arch nx ny nz real_bytes nval
+// members lx ly lz"; other lines are skipped.
 void tune_cache_load() {
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
     const char* path = getenv("PIPE_TUNE_CACHE");
-    if (!path) return;
+    if (!path || g_tune_loaded == path) return;
+    g_tune_loaded = path;
     FILE* f = fopen(path, "r");
     if (!f) return;
-    int nx, ny, nz, rb, mem, lx, ly, lz;
-    while (fscanf(f, "%d %d %d %d %d %d %d %d", &nx, &ny, &nz, &rb, &mem, &lx, &ly, &lz) == 8)
-        g_tune[{nx, ny, nz, rb, mem}] = {lx, ly, lz};
+    char line[512], arch[128];
+    while (fgets(line, sizeof line, f)) {
+        TuneKey k;
+        std::array<int, 3> v;
+        if (sscanf(line, "pipe-tune-v2 %127s %d %d %d %d %d %d %d %d %d", arch, &k.nx, &k.ny, &k.nz, &k.rb, &k.nval,
+                   &k.members, &v[0], &v[1], &v[2]) != 10)
+            continue;
+        k.arch = arch;
+        if (tuned_lengths_ok(k, v)) g_tune[k] = v;
+    }
     fclose(f);
 }
 
@@ -595,21 +659,33 @@ void tune_cache_store(const TuneKey& k, const std::array<int, 3>& v) {
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%d %d %d %d %d %d %d %d\n", k.nx, k.ny, k.nz, k.rb, k.members, v[0], v[1], v[2]);
+    fprintf(f, "pipe-tune-v2 %s %d %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.nx, k.ny, k.nz, k.rb, k.nval,
+            k.members, v[0], v[1], v[2]);
     fclose(f);
 }
 
-// supported lengths >= need: the smallest, the smallest power of two, the smallest 3 * 2^k
+std::string device_arch(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    for (char& c : a)
+        if (c == ' ') c = '_';
+    return a.empty() ? "unknown" : a;
+}
+
+// supported lengths >= need: the smallest, the smallest even one, the smallest
+// power of two and the smallest 3 * 2^k (each a different radix plan)
 std::vector<int> length_candidates(int need) {
     std::vector<int> out;
-    int best = -1, pow2 = -1, three = -1;
+    int best = -1, even = -1, pow2 = -1, three = -1;
     for (int v : kFftLengths) {
         if (v < need) continue;
         if (best < 0) best = v;
+        if (even < 0 && v % 2 == 0) even = v;
         if (pow2 < 0 && (v & (v - 1)) == 0) pow2 = v;
-        if (three < 0 && v % 3 == 0) three = v;
+        if (three < 0 && v % 3 == 0 && ((v / 3) & (v / 3 - 1)) == 0) three = v;
     }
-    for (int v : {best, pow2, three})
+    for (int v : {best, even, pow2, three})
         if (v > 0 && std::find(out.begin(), out.end(), v) == out.end()) out.push_back(v);
     return out;
 }
@@ -625,11 +701,15 @@ pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al
 // launch of that many concurrent solves (throughput, as in a batch).
 pipe_status_t autotune_lengths(pipe_plan_s* tmpl, int members, hipStream_t st, int* lx, int* ly, int* lz,
                                double* ms_out) {
-    const TuneKey key{tmpl->nx, tmpl->ny, tmpl->nz, tmpl->rb, members};
+    const TuneKey key{device_arch(tmpl->device), tmpl->nx, tmpl->ny, tmpl->nz, tmpl->rb, tmpl->nval, members};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_cache_load();
         auto it = g_tune.find(key);
+        if (it != g_tune.end() && !tuned_lengths_ok(key, it->second)) {
+            g_tune.erase(it);   // unusable entry: tune again
+            it = g_tune.end();
+        }
         if (it != g_tune.end()) {
             *lx = it->second[0];
             *ly = it->second[1];
@@ -857,8 +937,18 @@ pipe_status_t pipe_green_plan_banded(int nx, int ny, int nz, double hx, double h
     *out = nullptr;
     const bool keep = (kind & PIPE_KEEP_GREEN) != 0;
     kind &= 0xff;
+    // the banded x pass takes a subset of the transform lengths
+    if (lx == 0 && nx >= 1 && nx <= 512) {
+        lx = pick_band_length(2 * nx);
+        if (lx < 0) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "lx: no banded padded length for nx = %d", nx);
+    }
     pipe_status_t s = validate(nx, ny, nz, hx, hy, hz, a, b, x0, y0, kind, mx, my, &lx, &ly, nullptr);
     if (s != PIPE_OK) return s;
+    if (!band_length_ok(lx))
+        return fail(PIPE_ERR_UNSUPPORTED_SIZE,
+                    "lx: banded plans take padded lengths divisible by 4 with a plan of 4k values per thread "
+                    "(8, 12, 16, 24, 32, 36, 48, 64, 72, 96, 108, 128, 144, 192, 216, 256, 288, 384, 432, 512, "
+                    "576, 768, 864, 1024); got %d", lx);
     if (nband < 0 && !(tol > 0.0 && tol < 1.0))
         return fail(PIPE_ERR_INVALID_ARG, "automatic band selection needs 0 < tol < 1 (got %g)", tol);
     int ndev = 0;
@@ -1102,9 +1192,18 @@ struct pipe_batch_s {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // descriptors: staged in pinned host memory and copied on the caller's
+    // stream, so new pointers need no new graph (only the banded members and
+    // the vector-access flags are captured as launch arguments)
+    GroupArgs* hargs = nullptr;
+    size_t nargs = 0;
+    hipEvent_t uploaded = nullptr;        // after the last descriptor copy
+    hipEvent_t launched = nullptr;        // after the last graph launch
+    bool any_upload = false, any_launch = false;
     std::vector<const void*> last_rho;
     std::vector<void*> last_phi;
     void* last_ws = nullptr;
+    std::vector<char> cap_flags;          // per group: aligned input, aligned output (as captured)
 };
 
 namespace {
@@ -1117,12 +1216,17 @@ void batch_drop_graph(pipe_batch_s* b) {
 
 void batch_free(pipe_batch_s* b) {
     (void)hipSetDevice(b->device);
-    (void)hipDeviceSynchronize();
+    // wait for this batch's own work only (its last replay and descriptor copy)
+    if (b->any_launch) (void)hipEventSynchronize(b->launched);
+    if (b->any_upload) (void)hipEventSynchronize(b->uploaded);
     batch_drop_graph(b);
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+    if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+    if (b->launched) (void)hipEventDestroy(b->launched);
     for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->dargs) (void)hipFree(b->dargs);
+    if (b->hargs) (void)hipHostFree(b->hargs);
     delete b;
 }
 
@@ -1191,7 +1295,12 @@ pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
     if (e == hipSuccess && cur != b->device) e = hipSetDevice(b->device);
+    b->nargs = entries;
     if (e == hipSuccess) e = dev_alloc((void**)&b->dargs, entries * sizeof(GroupArgs));
+    if (e == hipSuccess && fault_inject_alloc()) e = hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->hargs, entries * sizeof(GroupArgs), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->launched, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     for (size_t k = 0; e == hipSuccess && k < b->groups.size(); ++k) {
         hipStream_t st;
@@ -1239,16 +1348,27 @@ pipe_status_t pipe_batch_solve(pipe_batch_t b, const void* const* rho, void* con
     int cur = -1;
     HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
     if (cur != b->device) HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
+    hipStream_t caller = (hipStream_t)stream;
     bool same = b->exec && b->last_ws == ws;
     for (size_t i = 0; same && i < n; ++i) same = b->last_rho[i] == rho[i] && b->last_phi[i] == phi[i];
     pipe_status_t s = PIPE_OK;
     if (!same) {
-        batch_drop_graph(b);
         // per-member pointers of the five grouped passes
         std::vector<GroupArgs> host;
+        std::vector<char> flags;
+        bool banded_moved = false;
         for (auto& g : b->groups) {
             const size_t m = g.members.size();
+            bool al_in = true, al_out = true;
+            for (int i : g.members) {
+                al_in = al_in && ((uintptr_t)rho[i] % (2 * b->rb) == 0);
+                al_out = al_out && ((uintptr_t)phi[i] % (2 * b->rb) == 0);
+            }
+            flags.push_back((char)(al_in | (al_out << 1)));
             if (g.banded) {   // launched directly with its own pointers
+                const int i = g.members[0];
+                if (!b->exec || b->last_ws != ws || b->last_rho[i] != rho[i] || b->last_phi[i] != phi[i])
+                    banded_moved = true;
                 host.insert(host.end(), 5 * m, GroupArgs{nullptr, nullptr, nullptr, nullptr, 0.0});
                 continue;
             }
@@ -1267,28 +1387,39 @@ pipe_status_t pipe_batch_solve(pipe_batch_t b, const void* const* rho, void* con
             }
             host.insert(host.end(), a.begin(), a.end());
         }
-        // an earlier replay may still be reading the descriptors
-        hipError_t e = hipDeviceSynchronize();
-        if (e == hipSuccess)
-            e = hipMemcpy(b->dargs, host.data(), host.size() * sizeof(GroupArgs), hipMemcpyHostToDevice);
-        if (e != hipSuccess) s = hip_fail(e, "batch descriptor upload");
-        if (s == PIPE_OK) {
-            e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
-            if (e != hipSuccess) s = hip_fail(e, "graph capture");
+        const bool recapture = !b->exec || banded_moved || flags != b->cap_flags;
+        hipError_t e = hipSuccess;
+        // The staging buffer may still feed the previous copy; the device array may
+        // still be read by the previous replay (possibly on another stream).
+        if (b->any_upload) e = hipEventSynchronize(b->uploaded);
+        if (e == hipSuccess && b->any_launch) e = hipStreamWaitEvent(caller, b->launched, 0);
+        if (e == hipSuccess) {
+            memcpy(b->hargs, host.data(), host.size() * sizeof(GroupArgs));
+            e = hipMemcpyAsync(b->dargs, b->hargs, host.size() * sizeof(GroupArgs), hipMemcpyHostToDevice, caller);
         }
-        if (s == PIPE_OK) {
+        if (e == hipSuccess) e = hipEventRecord(b->uploaded, caller);
+        if (e == hipSuccess) b->any_upload = true;
+        if (e != hipSuccess) s = hip_fail(e, "batch descriptor upload");
+        if (s == PIPE_OK && recapture) {
+            // an earlier replay of the old graph may still run
+            if (b->any_launch) e = hipEventSynchronize(b->launched);
+            if (e != hipSuccess) s = hip_fail(e, "batch graph wait");
+            if (s == PIPE_OK) batch_drop_graph(b);
+            if (s == PIPE_OK) {
+                e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+                if (e != hipSuccess) s = hip_fail(e, "graph capture");
+            }
+        }
+        if (s == PIPE_OK && recapture) {
             hipError_t ce = hipEventRecord(b->events[0], b->cap);
             for (size_t k = 0; ce == hipSuccess && s == PIPE_OK && k < b->groups.size(); ++k) {
                 auto& g = b->groups[k];
                 hipStream_t st = b->streams[k];
                 ce = hipStreamWaitEvent(st, b->events[0], 0);
                 if (ce != hipSuccess) break;
-                bool al_in = true, al_out = true, shared = true;
-                for (int i : g.members) {
-                    al_in = al_in && ((uintptr_t)rho[i] % (2 * b->rb) == 0);
-                    al_out = al_out && ((uintptr_t)phi[i] % (2 * b->rb) == 0);
-                    shared = shared && b->plans[i] == b->plans[g.members[0]];
-                }
+                bool shared = true;
+                for (int i : g.members) shared = shared && b->plans[i] == b->plans[g.members[0]];
+                const bool al_in = flags[k] & 1, al_out = (flags[k] >> 1) & 1;
                 const GroupArgs* args = b->dargs + b->args_off[k];
                 const int m = (int)g.members.size();
                 if (g.banded) {
@@ -1318,15 +1449,24 @@ pipe_status_t pipe_batch_solve(pipe_batch_t b, const void* const* rho, void* con
                     s = hip_fail(e, "graph instantiate");
                 }
             }
+            if (s == PIPE_OK) b->cap_flags = flags;
         }
         if (s == PIPE_OK) {
             b->last_rho.assign(rho, rho + n);
             b->last_phi.assign(phi, phi + n);
             b->last_ws = ws;
+        } else {
+            b->last_rho.clear();   // force a fresh upload (and capture, if needed) next time
+            b->last_phi.clear();
+            b->last_ws = nullptr;
         }
     }
     if (s == PIPE_OK) {
-        hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+        // the descriptors may have been copied on another stream
+        hipError_t e = b->any_upload ? hipStreamWaitEvent(caller, b->uploaded, 0) : hipSuccess;
+        if (e == hipSuccess) e = hipGraphLaunch(b->exec, caller);
+        if (e == hipSuccess) e = hipEventRecord(b->launched, caller);
+        if (e == hipSuccess) b->any_launch = true;
         if (e != hipSuccess) s = hip_fail(e, "graph launch");
     }
     if (cur != b->device) (void)hipSetDevice(cur);

@@ -6,26 +6,36 @@
 
 namespace pipe {
 
-// Supported complex FFT lengths (2^p 3^q); the twiddle bank also holds 1536, 2048
-// for the real-to-complex post-processing of z lines of length 2 * 768, 2 * 1024.
-constexpr int kFftLengths[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
-constexpr int kTwLengths[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048};
-constexpr int kNumTw = sizeof(kTwLengths) / sizeof(int);
+// Supported complex FFT lengths: every 2^p 3^q in [8, 1024] (the plans are in
+// fft_engine.h).  The twiddle bank also holds natural tables of length 2N for
+// the real-to-complex post-processing of z lines of length 2N.
+constexpr int kFftLengths[] = {8,   9,   12,  16,  18,  24,  27,  32,  36,  48,  54,  64,
+                               72,  81,  96,  108, 128, 144, 162, 192, 216, 243, 256, 288,
+                               324, 384, 432, 486, 512, 576, 648, 729, 768, 864, 972, 1024};
+constexpr int kNumFft = sizeof(kFftLengths) / sizeof(int);
+// Lengths the banded x pass supports (N and E multiples of 4).
+constexpr int kBandLengths[] = {8,   12,  16,  24,  32,  36,  48,  64,  72,  96,  108, 128,
+                                144, 192, 216, 256, 288, 384, 432, 512, 576, 768, 864, 1024};
 
 inline bool fft_length_ok(int n) {
     for (int v : kFftLengths) if (v == n) return true;
     return false;
 }
+inline bool band_length_ok(int n) {
+    for (int v : kBandLengths) if (v == n) return true;
+    return false;
+}
 
-// Per-device twiddle bank: for every N in kTwLengths the natural table
-// tw[m] = exp(-2 pi i m / N), m < N (get), and for every FFT length the
-// stage table of the transform engine (stage; see stage_tw_offset), both in
-// one allocation per precision.
+// Per-device twiddle bank: for every FFT length N the natural tables
+// tw[m] = exp(-2 pi i m / L), m < L, for L = N and L = 2N (get), and the stage
+// table of the transform engine (stage; see stage_tw_offset), all in one
+// allocation per precision.
 struct TwiddleBank {
     void* d64 = nullptr;   // double2
     void* d32 = nullptr;   // float2
-    size_t offset[kNumTw] = {};
-    size_t soffset[kNumTw] = {};
+    size_t offset[kNumFft] = {};    // natural table of length N
+    size_t offset2[kNumFft] = {};   // natural table of length 2N
+    size_t soffset[kNumFft] = {};   // stage table of length N
     size_t total = 0;
     template <typename C> const C* get(int n) const;
     template <typename C> const C* stage(int n) const;

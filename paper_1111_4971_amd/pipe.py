@@ -130,6 +130,21 @@ def _dtype(real_bytes):
     return torch.float64 if real_bytes == 8 else torch.float32
 
 
+def _check_workspace_tensor(ws, need, device, owner):
+    torch = _torch()
+    if not isinstance(ws, torch.Tensor):
+        raise TypeError("workspace: expected a tensor")
+    if not ws.is_contiguous():
+        raise ValueError("workspace: must be contiguous")
+    nbytes = ws.numel() * ws.element_size()
+    if nbytes < need:
+        raise ValueError("workspace: %d bytes, %s needs %d" % (nbytes, owner, need))
+    if not ws.is_cuda or ws.device != device:
+        raise TypeError("workspace: expected a CUDA tensor on %s" % device)
+    if ws.data_ptr() % 256:
+        raise ValueError("workspace: must be 256-byte aligned")
+
+
 class GreenPlan:
     """Cached Green spectra for one mesh (pipe_green_plan_ex).
 
@@ -181,33 +196,72 @@ class GreenPlan:
             raise PipeError(1, "plan already destroyed")
         return self._h
 
-    def workspace(self, device="cuda"):
+    def workspace(self, device="cuda", stream=None):
+        """The plan's cached workspace for one stream (256-byte aligned view).
+
+        Solves that run concurrently must not share a workspace, so the cache
+        holds one buffer per (device, stream); stream None means the current
+        stream of that device."""
         torch = _torch()
-        if self._ws is None or self._ws.device != torch.device(device):
-            self._ws = torch.empty(self.info.workspace_bytes + 256, dtype=torch.uint8, device=device)
-        return self._aligned(self._ws)
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        key = (dev.index, s.cuda_stream)
+        if self._ws is None:
+            self._ws = {}
+        t = self._ws.get(key)
+        if t is None:
+            t = torch.empty(self.info.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+            self._ws[key] = t
+        return self._aligned(t)
 
     @staticmethod
     def _aligned(t):
         off = (-t.data_ptr()) % 256
         return t[off:]
 
-    def _prep(self, x):
+    def _check_array(self, x, what):
         torch = _torch()
-        if not isinstance(x, torch.Tensor) or not x.is_cuda:
-            raise TypeError("expected a CUDA tensor")
+        if not isinstance(x, torch.Tensor):
+            raise TypeError("%s: expected a tensor" % what)
         if tuple(x.shape) != self.shape:
-            raise ValueError("expected shape %s, got %s" % (self.shape, tuple(x.shape)))
+            raise ValueError("%s: expected shape %s, got %s" % (what, self.shape, tuple(x.shape)))
         if x.dtype != self.dtype:
-            raise TypeError("expected %s, got %s" % (self.dtype, x.dtype))
+            raise TypeError("%s: expected %s, got %s" % (what, self.dtype, x.dtype))
+        if not x.is_cuda:
+            raise TypeError("%s: expected a CUDA tensor" % what)
+
+    def _prep(self, x):
+        self._check_array(x, "input")
         return x.contiguous()
 
-    def _run(self, fn, x, out, workspace, stream):
+    def _check_out(self, out, x):
+        self._check_array(out, "out")
+        if not out.is_contiguous():
+            raise ValueError("out: must be contiguous")
+        if out.device != x.device:
+            raise ValueError("out: on %s, input on %s" % (out.device, x.device))
+
+    def _check_workspace(self, ws, x):
+        _check_workspace_tensor(ws, self.info.workspace_bytes, x.device, "the plan")
+
+    def _buffers(self, x, out, workspace, stream):
         torch = _torch()
         x = self._prep(x)
         if out is None:
             out = torch.empty_like(x)
-        ws = workspace if workspace is not None else self.workspace(x.device)
+        else:
+            self._check_out(out, x)
+        if workspace is None:
+            ws = self.workspace(x.device, stream)
+        else:
+            self._check_workspace(workspace, x)
+            ws = workspace
+        return x, out, ws
+
+    def _run(self, fn, x, out, workspace, stream):
+        x, out, ws = self._buffers(x, out, workspace, stream)
         check(fn(self.handle, _P(x.data_ptr()), _P(out.data_ptr()), _P(ws.data_ptr()), _stream_ptr(stream)))
         return out
 
@@ -218,10 +272,7 @@ class GreenPlan:
         return self._run(lib().pipe_poisson_adjoint, dphi, out, workspace, stream)
 
     def solve_timed(self, rho, out=None, workspace=None, stream=None):
-        torch = _torch()
-        x = self._prep(rho)
-        out = torch.empty_like(x) if out is None else out
-        ws = workspace if workspace is not None else self.workspace(x.device)
+        x, out, ws = self._buffers(rho, out, workspace, stream)
         ms = (ctypes.c_float * 5)()
         check(lib().pipe_poisson_solve_timed(self.handle, _P(x.data_ptr()), _P(out.data_ptr()),
                                              _P(ws.data_ptr()), _stream_ptr(stream), ms))
@@ -328,19 +379,56 @@ class Batch:
         check(lib().pipe_batch_workspace(h, ctypes.byref(n)))
         self.workspace_bytes = n.value
         self._ws = None
+        self._outs = None
 
-    def workspace(self, device="cuda"):
+    def workspace(self, device="cuda", stream=None):
+        """The batch's cached workspace for one stream (see GreenPlan.workspace)."""
         torch = _torch()
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        key = (dev.index, s.cuda_stream)
         if self._ws is None:
-            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
-        return GreenPlan._aligned(self._ws)
+            self._ws = {}
+        t = self._ws.get(key)
+        if t is None:
+            t = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+            self._ws[key] = t
+        return GreenPlan._aligned(t)
 
     def solve(self, rhos, outs=None, workspace=None, stream=None):
+        """phi_s = A_s rho_s for every member.  outs=None reuses the batch's own
+        output tensors from the previous call (new ones only on the first call
+        or when the input device changes), so repeated calls replay the
+        captured graph unchanged; copy the results if they must outlive the
+        next call."""
         torch = _torch()
-        if outs is None:
-            outs = [torch.empty_like(r) for r in rhos]
-        ws = workspace if workspace is not None else self.workspace()
         n = len(self.plans)
+        rhos = list(rhos)
+        if len(rhos) != n:
+            raise ValueError("expected %d charge arrays, got %d" % (n, len(rhos)))
+        for i, (p, r) in enumerate(zip(self.plans, rhos)):
+            p._check_array(r, "rhos[%d]" % i)
+            if not r.is_contiguous():
+                raise ValueError("rhos[%d]: must be contiguous" % i)
+            if r.device != rhos[0].device:
+                raise ValueError("rhos[%d]: every member must be on one device" % i)
+        if outs is None:
+            if self._outs is None or self._outs[0].device != rhos[0].device:
+                self._outs = [torch.empty_like(r) for r in rhos]
+            outs = self._outs
+        else:
+            outs = list(outs)
+            if len(outs) != n:
+                raise ValueError("expected %d output arrays, got %d" % (n, len(outs)))
+            for i, (p, r, o) in enumerate(zip(self.plans, rhos, outs)):
+                p._check_out(o, r)
+        if workspace is None:
+            ws = self.workspace(rhos[0].device, stream)
+        else:
+            _check_workspace_tensor(workspace, self.workspace_bytes, rhos[0].device, "the batch")
+            ws = workspace
         ra = (_P * n)(*[r.data_ptr() for r in rhos])
         pa = (_P * n)(*[o.data_ptr() for o in outs])
         check(lib().pipe_batch_solve(self._h, ra, pa, _P(ws.data_ptr()), _stream_ptr(stream)))

@@ -61,7 +61,7 @@ def _plan(*args, **kw):
     ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0x20), {}, 1),                  # unknown precision
     ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"mx": 0}, 1),              # no modes
     ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"lx": 6}, 1),              # L < 2n - 1
-    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"lx": 9}, 2),              # odd L
+    ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"lz": 27}, 2),             # odd lz (z is real-to-complex)
     ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"lx": 10}, 2),             # 10 = 2 * 5 unsupported
     ((4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0), {"lz": 2048 * 2}, 2),       # beyond the largest length
     ((2000, 4, 4, 1e-4, 0.1, 0.1, 1.0, 1.0, 0), {}, 2),                 # no padded length for n
@@ -245,3 +245,84 @@ def test_header_is_plain_c_and_links(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert r.stdout.startswith("PIPE_ERR_INVALID_ARG")
+
+
+def _fake_plan(shape=(4, 3, 5), real_bytes=8, ws_bytes=4096):
+    """A GreenPlan whose sizes are set by hand (no device, no library call), to
+    exercise the binding's buffer checks on the host."""
+    p = pipe.GreenPlan.__new__(pipe.GreenPlan)
+    p._h = None
+    p._ws = None
+    p.shape = shape
+    p.info = pipe.PlanInfo()
+    p.info.real_bytes = real_bytes
+    p.info.workspace_bytes = ws_bytes
+    p.dtype = pipe._dtype(real_bytes)
+    return p
+
+
+@pytest.mark.parametrize("make,exc", [
+    (lambda torch: [[1.0]], TypeError),                                          # not a tensor
+    (lambda torch: torch.zeros((4, 3, 6), dtype=torch.float64), ValueError),     # wrong shape
+    (lambda torch: torch.zeros((4, 3, 5), dtype=torch.float32), TypeError),      # wrong dtype
+    (lambda torch: torch.zeros((4, 3, 5), dtype=torch.float64), TypeError),      # host memory
+])
+def test_binding_rejects_bad_arrays(make, exc):
+    torch = pytest.importorskip("torch")
+    p = _fake_plan()
+    with pytest.raises(exc):
+        p._check_array(make(torch), "rho")
+
+
+@pytest.mark.parametrize("make,exc", [
+    (lambda torch: None, TypeError),                                             # not a tensor
+    (lambda torch: torch.zeros(4095, dtype=torch.uint8), ValueError),            # one byte short
+    (lambda torch: torch.zeros((2, 4096), dtype=torch.uint8)[:, :2048], ValueError),  # not contiguous
+    (lambda torch: torch.zeros(4096, dtype=torch.uint8), TypeError),             # host memory
+])
+def test_binding_rejects_bad_workspaces(make, exc):
+    torch = pytest.importorskip("torch")
+    with pytest.raises(exc):
+        pipe._check_workspace_tensor(make(torch), 4096, torch.device("cpu"), "the plan")
+
+
+def test_fp32_plan_rejects_fp64_output():
+    torch = pytest.importorskip("torch")
+    p = _fake_plan(real_bytes=4)
+    with pytest.raises(TypeError):
+        p._check_array(torch.zeros((4, 3, 5), dtype=torch.float64), "out")
+
+
+def _smooth23(n):
+    for p in (2, 3):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+@needs_lib
+@pytest.mark.skipif(_has_device(), reason="checks validation outcomes on a host without a device")
+def test_every_23_smooth_padded_length_is_accepted():
+    """Padded lengths (Appendix: any N >= J + K - 1 is valid): lx and ly may be
+    any 2^p 3^q in [8, 1024], lz any even length whose half is one; every other
+    length is UNSUPPORTED_SIZE.  On a host with no device an accepted length
+    gets as far as the device check (NO_DEVICE)."""
+    for L in range(8, 1025):
+        want = 4 if _smooth23(L) else 2
+        assert _plan(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0, lx=L)[0] == want, ("lx", L)
+        assert _plan(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0, ly=L)[0] == want, ("ly", L)
+    for L in range(8, 2049):
+        want = 4 if (L % 2 == 0 and _smooth23(L // 2) and L // 2 >= 8) else 2
+        assert _plan(4, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0, lz=L)[0] == want, ("lz", L)
+
+
+@needs_lib
+@pytest.mark.skipif(_has_device(), reason="checks validation outcomes on a host without a device")
+@pytest.mark.parametrize("lx,expect", [(36, 4), (144, 4), (864, 4), (18, 2), (81, 2), (162, 2), (972, 2), (0, 4)])
+def test_banded_plan_lengths(lx, expect):
+    """Banded plans take the lengths whose x-pass items tile evenly (multiples of 4)."""
+    L = pipe.lib()
+    h = ctypes.c_void_p()
+    st = L.pipe_green_plan_banded(9, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0.0, 0.0, 0, 8, 8, lx, 0, 1, 1e-6, None,
+                                  ctypes.byref(h))
+    assert st == expect, (lx, st, L.pipe_last_error())

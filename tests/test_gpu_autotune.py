@@ -29,7 +29,10 @@ def test_autotuned_lengths_same_result_and_cached(tmp_path):
     log("autotune: tuned plan")
     tuned = pipe.GreenPlan(nx, ny, nz, hx, hy, hz, a, b, kind=pipe.IGF_Z, precision="fp32", autotune=True)
     i = tuned.info
-    assert i.lx in (96, 128) and i.ly in (96, 128, 80) and i.lz in (192, 256)
+    # candidates per dimension: the smallest 2^p 3^q >= 2n, the smallest even one,
+    # the smallest power of two, the smallest 3 * 2^k (x: 96, 128; y: 81, 96, 128;
+    # z: lz/2 >= nz: 96, 128)
+    assert i.lx in (96, 128) and i.ly in (81, 96, 128) and i.lz in (192, 256)
     assert i.lx >= 2 * nx and i.ly >= 2 * ny and i.lz >= 2 * nz
     assert i.tune_ms > 0
     default = pipe.GreenPlan(nx, ny, nz, hx, hy, hz, a, b, kind=pipe.IGF_Z, precision="fp32")
@@ -44,10 +47,44 @@ def test_autotuned_lengths_same_result_and_cached(tmp_path):
     assert again.info.tune_ms == 0.0
     assert (again.info.lx, again.info.ly, again.info.lz) == (i.lx, i.ly, i.lz)
     lines = cache.read_text().split("\n")
-    assert any(l.split()[:5] == ["48", "40", "96", "4", "1"] and l.split()[5:] == [str(i.lx), str(i.ly), str(i.lz)]
-               for l in lines if l.strip())
+    arch = torch.cuda.get_device_properties(0).gcnArchName.replace(" ", "_")
+    assert any(l.split()[:8] == ["pipe-tune-v2", arch, "48", "40", "96", "4", "9", "1"]
+               and l.split()[8:] == [str(i.lx), str(i.ly), str(i.lz)] for l in lines if l.strip())
     log("autotune: throughput mode")
     tb = pipe.GreenPlan(nx, ny, nz, hx, hy, hz, a, b, kind=pipe.IGF_Z, precision="fp32", autotune="batch")
     assert tb.info.tune_ms > 0
     got_b = tb.solve(x).double().cpu().numpy()
     assert rel_l2(got_b, ref) <= 1e-5 and rel_max(got_b, ref) <= 1e-5
+
+
+def test_bad_cache_entries_are_tuned_again(tmp_path):
+    """Cache lines whose lengths the plan cannot use (unsupported, odd, shorter
+    than 2n - 1) are ignored: the plan tunes again and stays correct."""
+    import torch
+    from oracle import fourterm
+    from paper_1111_4971_amd import pipe
+    arch = torch.cuda.get_device_properties(0).gcnArchName.replace(" ", "_")
+    nx, ny, nz = 20, 14, 30
+    cache = tmp_path / "bad.txt"
+    cache.write_text("\n".join([
+        "pipe-tune-v2 %s %d %d %d 4 9 1 100 32 64" % (arch, nx, ny, nz),    # lx = 100: no such transform
+        "pipe-tune-v2 %s %d %d %d 8 9 1 40 28 40" % (arch, nx, ny, nz),     # lz = 40 < 2 nz - 1
+        "pipe-tune-v2 %s %d %d %d 4 1 1 41 28 64" % (arch, nx, ny, nz),     # odd lx (free-space key)
+        "48 40 96 4 1 96 96 192",                                           # old format: skipped
+        "garbage"]) + "\n")
+    os.environ["PIPE_TUNE_CACHE"] = str(cache)
+    a, b = 1.0, 1.1
+    hx, hy, hz = a / (nx + 1), b / (ny + 1), 0.07
+    rho = np.random.default_rng(5).standard_normal((nx, ny, nz))
+    for prec in ("fp32", "fp64"):
+        log("autotune: bad cache entries %s" % prec)
+        p = pipe.GreenPlan(nx, ny, nz, hx, hy, hz, a, b, kind=pipe.IGF_Z, precision=prec, autotune=True)
+        i = p.info
+        assert i.tune_ms > 0
+        assert i.lx >= 2 * nx - 1 and i.ly >= 2 * ny - 1 and i.lz >= 2 * nz - 1
+        x = torch.from_numpy(rho).to("cuda", p.dtype)
+        got = p.solve(x).double().cpu().numpy()
+        ref = fourterm.solve(oracle_input(rho, prec), hx, hy, hz, a, b, 2 * nx, 2 * ny, pipe.IGF_Z)
+        tol = 1e-12 if prec == "fp64" else 1e-5
+        assert rel_l2(got, ref) <= tol and rel_max(got, ref) <= tol
+    os.environ.pop("PIPE_TUNE_CACHE", None)

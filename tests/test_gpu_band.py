@@ -297,3 +297,47 @@ def test_banded_plans_in_a_batch(torch_cuda):
         torch.cuda.synchronize()
         for p, r, o in zip(plans, rhos, outs):
             assert torch.equal(o, p.solve(r))
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant,nb", [("single", 0), ("single", 1), ("chunked", 1), ("single", 3),
+                                        ("chunked", 3)])
+def test_band_at_lx_512(torch_cuda, monkeypatch, kind, prec, variant, nb):
+    """The banded x pass at lx = 512 (the padded length of the 256-node meshes
+    the banded benchmark leg runs) against the oracle's Eq. 10 with the Green
+    array cut at N planes (Eq. 18), both x-pass kernels (N = 0 has one)."""
+    from oracle import fourterm
+    monkeypatch.setenv("PIPE_BAND_KERNEL", variant)
+    shape = (256, 5, 19)
+    nx, ny, nz = shape
+    rho = np.random.default_rng(512 + nb).standard_normal(shape)
+    h = (A / (nx + 1), 0.9 * B / (ny + 1), 0.05)
+    log("band lx=512 %s kind=%d kernel %s N=%d" % (prec, kind, variant, nb))
+    from paper_1111_4971_amd import pipe
+    plan = pipe.GreenPlan(nx, ny, nz, *h, A, B, kind=kind, precision=prec, mx=2 * nx + 1, my=2 * ny + 3, band=nb)
+    assert plan.info.lx == 512 and plan.band == nb
+    got = gpu_solve(plan, rho)
+    ref = fourterm.solve(oracle_input(rho, prec), *h, A, B, 2 * nx + 1, 2 * ny + 3, kind, band=nb)
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("lx,ly,nb", [(36, 27, 1), (144, 0, 2), (108, 81, 0), (216, 18, 3), (864, 9, 1)])
+def test_band_at_smooth_lengths(torch_cuda, prec, lx, ly, nb):
+    """Banded plans at x lengths with radix-3 and five-stage plans and odd y
+    lengths, against the oracle's Eq. 10 with the Green array cut at N."""
+    from oracle import fourterm
+    from paper_1111_4971_amd import pipe
+    nx = (lx + 1) // 2
+    ny = (ly + 1) // 2 if ly else 5
+    shape = (nx, ny, 13)
+    rho = np.random.default_rng(lx + nb).standard_normal(shape)
+    h = (A / (nx + 1), 0.9 * B / (ny + 1), 0.05)
+    log("band smooth lengths %s lx=%d ly=%d N=%d" % (prec, lx, ly, nb))
+    plan = pipe.GreenPlan(*shape, *h, A, B, kind=1, precision=prec, mx=2 * nx + 1, my=2 * ny + 3, band=nb,
+                          L=(lx, ly))
+    assert plan.info.lx == lx and (ly == 0 or plan.info.ly == ly)
+    got = gpu_solve(plan, rho)
+    ref = fourterm.solve(oracle_input(rho, prec), *h, A, B, 2 * nx + 1, 2 * ny + 3, 1, band=nb)
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))

@@ -57,12 +57,30 @@ def test_batch_equals_single_solves_and_replays(torch_cuda, batch_setup):
         torch.cuda.synchronize()
         for f, o in zip(first, outs):
             assert np.array_equal(f, o.double().cpu().numpy())
-    # new output buffers: the graph is rebuilt with the new pointers
+    # new output buffers: the descriptors are copied again, the graph replayed
     outs2 = [torch.empty_like(r) for r in rhos]
     b.solve(rhos, outs2)
     torch.cuda.synchronize()
     for f, o in zip(first, outs2):
         assert np.array_equal(f, o.double().cpu().numpy())
+    # alternate between the two output sets, back to back with no host wait,
+    # then on a second stream: every call must write its own outputs
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        for o in outs + outs2:
+            o.zero_()
+        b.solve(rhos, outs)
+        b.solve(rhos, outs2)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            outs3 = [torch.empty_like(r) for r in rhos]
+            b.solve(rhos, outs3, stream=side)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        for f, o1, o2, o3 in zip(first, outs, outs2, outs3):
+            assert np.array_equal(f, o1.double().cpu().numpy())
+            assert np.array_equal(f, o2.double().cpu().numpy())
+            assert np.array_equal(f, o3.double().cpu().numpy())
     b.close()
 
 
@@ -120,3 +138,42 @@ def test_same_plan_many_charges(torch_cuda, prec):
     for r, o in zip(rhos, outs):
         ref = plan.solve(r)
         assert torch.equal(o, ref)
+
+
+def test_autotuned_batch_members_match_the_oracle(torch_cuda):
+    """The batch the benchmark times: 96 uneven FP32 plans whose padded lengths
+    the throughput-mode autotuner picked (e.g. 96x96x192 -> 256x192x384), one
+    replay of the graph.  One member per mesh shape against the mode-space
+    oracle (exact for these full-aperture meshes), every member against its
+    own single solve."""
+    torch = torch_cuda
+    from oracle import modespace
+    from paper_1111_4971_amd import pipe, workloads
+    man = workloads.batch_manifest()
+    members = [workloads.batch_member(d) for d in man]
+    log("autotuned batch: building %d plans" % len(members))
+    plans = [pipe.GreenPlan(w.nx, w.ny, w.nz, w.hx, w.hy, w.hz, w.a, w.b, kind=w.kind, precision="fp32",
+                            mx=w.mx, my=w.my, autotune="batch") for w in members]
+    rhos = [torch.from_numpy(w.rho).to("cuda", torch.float32) for w in members]
+    lengths = {w.shape: (p.info.lx, p.info.ly, p.info.lz) for w, p in zip(members, plans)}
+    log("autotuned batch: lengths %s" % lengths)
+    for w, p in zip(members, plans):
+        assert (p.info.lx, p.info.ly, p.info.lz) == lengths[w.shape]
+    b = pipe.Batch(plans)
+    outs = b.solve(rhos)
+    torch.cuda.synchronize()
+    seen = set()
+    for w, p, r, o in zip(members, plans, rhos, outs):
+        got = o.double().cpu().numpy()
+        single = p.solve(r).double().cpu().numpy()
+        assert rel_l2(got, single) <= 1e-6 and rel_max(got, single) <= 1e-6
+        if w.shape in seen:
+            continue
+        seen.add(w.shape)
+        log("autotuned batch: oracle check %s at %s" % (w.shape, lengths[w.shape]))
+        ref = modespace.solve(oracle_input(w.rho, "fp32"), **w.geometry())
+        assert rel_l2(got, ref) <= 1e-5 and rel_max(got, ref) <= 1e-5, (w.shape, rel_l2(got, ref))
+    assert len(seen) == 4
+    b.close()
+    for p in plans:
+        p.close()

@@ -29,6 +29,8 @@ def torch_cuda():
                                           ((16, 10, 24), (0.05, 0.07, 0.04), 25.0, None),
                                           ((20, 13, 40), (0.03, 0.03, 0.06), 40.0, (48, 32, 96)),
                                           ((5, 6, 7), (0.2, 0.2, 0.2), 3.0, (12, 12, 16)),
+                                          ((14, 5, 20), (0.04, 0.1, 0.05), 9.0, (27, 9, 54)),
+                                          ((40, 18, 60), (0.02, 0.05, 0.03), 11.0, (81, 36, 144)),
                                           ((1, 1, 1), (0.1, 0.1, 0.1), 4.0, None),
                                           ((3, 1, 2), (0.1, 0.2, 0.3), 4.0, None)])
 def test_free_matches_eq5_oracle(torch_cuda, prec, shape, h, g0, L):
@@ -146,7 +148,7 @@ def _numpy_mixed(a, dirs):
 
 
 @pytest.mark.parametrize("dirs", DIRS)
-@pytest.mark.parametrize("shape", [(8, 12, 16), (24, 8, 48), (64, 32, 128)])
+@pytest.mark.parametrize("shape", [(8, 12, 16), (24, 8, 48), (64, 32, 128), (384, 8, 768), (768, 8, 384), (27, 36, 81), (9, 144, 54)])
 def test_fft3d_matches_numpy(torch_cuda, dirs, shape):
     torch = torch_cuda
     from paper_1111_4971_amd import pipe

@@ -13,7 +13,16 @@ from helpers import log, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-LENGTHS = [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+# every transform length the library supports: each 2^p 3^q in [8, 1024]
+def _smooth23(n):
+    for p in (2, 3):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+LENGTHS = [n for n in range(8, 1025) if _smooth23(n)]
+assert len(LENGTHS) == 36
 
 
 @pytest.fixture(scope="module")

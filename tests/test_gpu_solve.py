@@ -82,6 +82,86 @@ def test_largest_transform_lengths_match_eq10_oracle(torch_cuda, shape, dim, L, 
     assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
 
 
+# the four-stage plans (384 = 3.8.8.2, 768 = 3.8.8.4) in every pass: the fused x
+# pass (lx), the strided y passes (ly) and the z passes (lz/2); the shapes are
+# those whose smallest power-of-two-times-three length is 384 or 768
+MID = [((150, 3, 5), "lx", 384), ((3, 150, 5), "ly", 384), ((4, 3, 300), "lz", 768),
+       ((300, 3, 5), "lx", 768), ((3, 300, 5), "ly", 768), ((4, 3, 600), "lz", 1536)]
+
+
+@pytest.mark.parametrize("shape,dim,L", MID)
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_four_stage_lengths_match_eq10_oracle(torch_cuda, shape, dim, L, kind, prec):
+    """Padded lengths 384 and 768 in each pass against the literal Eq. 10
+    algorithm (Appendix A.3/A.9 slots), element by element."""
+    from oracle import fourterm
+    from paper_1111_4971_amd import pipe
+    nx, ny, nz = shape
+    a, b = 1.0, 1.2
+    hx, hy = a / (nx + 1), 0.9 * b / (ny + 1)
+    mx, my = 2 * nx + 1, 2 * ny + 3
+    rho = np.random.default_rng(7 * sum(shape) + kind).standard_normal(shape)
+    log("four-stage %s %s kind=%d shape=%s" % (dim, prec, kind, shape))
+    Ls = tuple(L if d == dim else 0 for d in ("lx", "ly", "lz"))
+    plan = pipe.GreenPlan(nx, ny, nz, hx, hy, 0.06, a, b, kind=kind, precision=prec, mx=mx, my=my, L=Ls)
+    assert getattr(plan.info, dim) == L
+    got = gpu_solve(plan, rho)
+    ref = fourterm.solve(oracle_input(rho, prec), hx, hy, 0.06, a, b, mx, my, kind)
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
+
+
+# the lengths beyond 2^k and 3 2^k: radix-9 and several radix-3 stages, odd
+# lengths (x and y only; z takes lz = 2 L), up to five stages
+SMOOTH = [9, 18, 27, 36, 54, 72, 81, 108, 144, 162, 216, 243, 288, 324, 432, 486, 576, 648, 729, 864, 972]
+
+
+@pytest.mark.parametrize("L", SMOOTH)
+@pytest.mark.parametrize("dim", ["lx", "ly", "lz"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_23_smooth_length_matches_eq10_oracle(torch_cuda, L, dim, prec):
+    """Each 2^p 3^q length in each pass (lx, ly = L; lz = 2 L), with the mesh as
+    large as the length allows (2 n - 1 <= L), against the literal Eq. 10
+    algorithm, element by element.  IGF Green function."""
+    from oracle import fourterm
+    from paper_1111_4971_amd import pipe
+    n = (L + 1) // 2 if dim != "lz" else L
+    shape = {"lx": (n, 3, 5), "ly": (4, n, 5), "lz": (4, 3, n)}[dim]
+    nx, ny, nz = shape
+    a, b = 1.1, 0.9
+    hx, hy = a / (nx + 1), b / (ny + 1)
+    mx, my = 2 * nx + 1, 2 * ny + 1
+    rho = np.random.default_rng(L * 3 + len(dim)).standard_normal(shape)
+    Ls = tuple((2 * L if d == "lz" else L) if d == dim else 0 for d in ("lx", "ly", "lz"))
+    log("smooth length %s=%d %s shape=%s" % (dim, L, prec, shape))
+    plan = pipe.GreenPlan(nx, ny, nz, hx, hy, 0.05, a, b, kind=1, precision=prec, mx=mx, my=my, L=Ls)
+    assert getattr(plan.info, dim) == (2 * L if dim == "lz" else L)
+    got = gpu_solve(plan, rho)
+    ref = fourterm.solve(oracle_input(rho, prec), hx, hy, 0.05, a, b, mx, my, 1)
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_default_lengths_take_the_smallest_smooth_length(torch_cuda, kind, prec):
+    """Default plans pad to the smallest 2^p 3^q >= 2n (x, y; may be odd) and
+    lz/2 >= nz: a 70 x 40 x 75 mesh gets 144 x 81 x 162 (not 192 x 96 x 192),
+    several tiles and ragged tails in every pass, against the oracle."""
+    from oracle import fourterm
+    from paper_1111_4971_amd import pipe
+    shape = (70, 40, 75)
+    nx, ny, nz = shape
+    a, b = 1.0, 1.3
+    hx, hy = a / (nx + 1), b / (ny + 1)
+    rho = np.random.default_rng(70).standard_normal(shape)
+    log("default smooth lengths %s kind=%d" % (prec, kind))
+    plan = pipe.GreenPlan(nx, ny, nz, hx, hy, 0.04, a, b, kind=kind, precision=prec, mx=2 * nx, my=2 * ny)
+    assert (plan.info.lx, plan.info.ly, plan.info.lz) == (144, 81, 162)
+    got = gpu_solve(plan, rho)
+    ref = fourterm.solve(oracle_input(rho, prec), hx, hy, 0.04, a, b, 2 * nx, 2 * ny, kind)
+    assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_padded_length_does_not_change_the_result(torch_cuda, prec):
     from paper_1111_4971_amd import pipe
