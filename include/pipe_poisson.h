@@ -113,14 +113,17 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
 /*
  * pipe_green_plan_ex -- as pipe_green_plan with explicit mode counts
  * (mx, my >= 1) and padded lengths (0 = default).  Each padded length must be
- * even, at least 2n - 1 (Appendix: N >= M = J + K - 1), and of the form
- * 2^p 3^q with lx, ly in [8, 1024] and lz/2 in [8, 1024]; otherwise
- * UNSUPPORTED_SIZE.  The physical result does not depend on the padded
- * lengths.  hip_stream (a hipStream_t, may be NULL) orders the build's GPU
+ * at least 2n - 1 (Appendix: N >= M = J + K - 1, else INVALID_ARG); lx and ly
+ * must be of the form 2^p 3^q in [8, 1024] (odd ones included), and lz must be
+ * even with lz/2 of that form (z is transformed real-to-complex as lz/2 packed
+ * pairs), i.e. lz in [16, 2048]; otherwise UNSUPPORTED_SIZE.  The default is
+ * the smallest such length >= 2n (lz: lz/2 >= nz).  The physical result does
+ * not depend on the padded lengths.  hip_stream (a hipStream_t, may be NULL) orders the build's GPU
  * work; the call still returns only when the build has finished.
  * With PIPE_AUTOTUNE in kind and all lengths 0, the plan times the five
  * passes for each candidate factorisation per dimension (the smallest
- * supported length >= 2n, the smallest power of two, the smallest 3 * 2^k)
+ * supported length >= 2n, the smallest even one, the smallest power of two,
+ * the smallest 3 * 2^k)
  * on scratch buffers and keeps the fastest: one solve at a time (latency)
  * with PIPE_AUTOTUNE, one grouped launch of 16 concurrent solves (throughput,
  * the batched form) with PIPE_AUTOTUNE_BATCH.  The choice is cached for the
@@ -153,7 +156,11 @@ pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double h
  * of the sum (Eq. 18; N = 0 is the set of independent 2-D problems of Eq. 17),
  * for long bunches whose Green function falls off within a few planes (Sec. 4,
  * end).  The z transform disappears: each plane is transformed in x and y
- * only (padded lengths lx, ly as in pipe_green_plan_ex; lz is reported as 0),
+ * only (padded lengths lx, ly as in pipe_green_plan_ex, except that lx must be
+ * one of 8, 12, 16, 24, 32, 36, 48, 64, 72, 96, 108, 128, 144, 192, 216, 256,
+ * 288, 384, 432, 512, 576, 768, 864, 1024 -- the banded x pass splits each
+ * line's orbits evenly over its threads -- else UNSUPPORTED_SIZE; the default
+ * is the smallest of these >= 2 nx; lz is reported as 0),
  * each output plane sums 2N + 1 transverse spectral products, and the plan
  * holds N + 1 two-dimensional Green spectra.  Solving is otherwise the same
  * call (pipe_poisson_solve / pipe_poisson_adjoint with info.workspace_bytes
@@ -330,7 +337,7 @@ pipe_status_t pipe_fft_lines(int real_bytes, int len, int n_in, int howmany, int
  * overlap it (ALIASING).  dirs: three characters, one per dimension in order,
  * 'f' = sum_n a_n W^{nk}, 'b' = sum_n a_n W^{-nk}, W = e^{-2 pi i/N}
  * (Eq. A.4's conventions; e.g. "fbf" is F^{fbf} of Eq. 6).  Each n must be a
- * supported length (2^p 3^q in [8, 1024]).  Asynchronous on hip_stream.
+ * supported length (2^p 3^q in [8, 1024], odd ones included).  Asynchronous on hip_stream.
  * Errors: INVALID_ARG, UNSUPPORTED_SIZE, ALIASING, NO_DEVICE, HIP.
  */
 pipe_status_t pipe_fft3d(int real_bytes, int n0, int n1, int n2, const char* dirs, const void* in_device,

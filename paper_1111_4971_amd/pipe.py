@@ -149,8 +149,8 @@ class GreenPlan:
     """Cached Green spectra for one mesh (pipe_green_plan_ex).
 
     kind: POINT or IGF_Z; precision: 'fp64' or 'fp32'.  mx, my default to
-    2 nx, 2 ny; L = (lx, ly, lz) defaults to the smallest supported even
-    lengths >= 2n.  autotune: False, True (time single solves) or "batch"
+    2 nx, 2 ny; L = (lx, ly, lz) defaults to the smallest supported lengths
+    >= 2n (lx, ly: any 2^p 3^q in [8, 1024]; lz: even, lz/2 of that form).  autotune: False, True (time single solves) or "batch"
     (time 16 concurrent solves) to pick the padded lengths.  offset = (x0, y0)
     places the mesh on a sub-region of the cross-section (node i at
     x0 + (i+1) hx).  band = N keeps only plane distances |k - k'| <= N
