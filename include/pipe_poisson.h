@@ -220,6 +220,25 @@ pipe_status_t pipe_poisson_adjoint(pipe_plan_t plan, const void* dphi, void* drh
                                    void* workspace, void* hip_stream);
 
 /*
+ * pipe_poisson_solve_noalloc -- pipe_poisson_solve without a workspace
+ * argument, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * workspace is a fixed scratch array of 256 MiB inside the library, one per
+ * device, held from the first plan built on that device until the process
+ * ends; the call itself allocates nothing and creates no HIP objects.  Every
+ * call on one device shares that device's scratch, so calls that overlap in
+ * time on one device (concurrent streams, or host threads) race and give
+ * wrong results: order them.  Nothing in the scratch needs to start at zero
+ * (each pass writes what the next reads), and it keeps the last call's
+ * contents.  pipe_plan_destroy does not wait for solves made through this
+ * entry point: finish them before destroying the plan.  A plan whose
+ * info.workspace_bytes exceeds 256 MiB (e.g. 128 x 128 x 512 in FP64) gets
+ * UNSUPPORTED_SIZE.  Otherwise arguments, results and errors as
+ * pipe_poisson_solve.
+ */
+pipe_status_t pipe_poisson_solve_noalloc(pipe_plan_t plan, const void* rho, void* phi, void* hip_stream);
+
+/*
  * pipe_batch_create -- group count >= 1 plans (any sizes, one precision) for
  * repeated batched solves: the per-plan pass launches are captured once into
  * a HIP graph and replayed by pipe_batch_solve.  The plans must outlive the

@@ -66,9 +66,17 @@ hipError_t dev_alloc(void** p, size_t bytes) {
 
 // ---------------------------------------------------------------- device context
 
+// Fixed device scratch of pipe_poisson_solve_noalloc: the solve's workspace
+// for callers that cannot allocate.  One copy per device, alive until the
+// process ends.  In host code the name is only a stand-in for the symbol: its
+// device address comes from hipGetSymbolAddress (DeviceCtx::scratch).
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct DeviceCtx {
     bool ready = false;
     TwiddleBank tw;
+    void* scratch = nullptr;   // this device's address of `scratch`
 };
 std::mutex g_ctx_mu;
 DeviceCtx g_ctx[64];
@@ -125,6 +133,9 @@ pipe_status_t device_ctx(int dev, DeviceCtx** out) {
         }
         HIP_TRY(hipMemcpy(c.tw.d64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice), "twiddle upload");
         HIP_TRY(hipMemcpy(c.tw.d32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice), "twiddle upload");
+        // device address of the fixed scratch (this device is current here)
+        HIP_TRY(hipGetSymbolAddress(&c.scratch, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (!c.scratch) return fail(PIPE_ERR_HIP, "scratch symbol address: null");
         c.ready = true;
     }
     *out = &c;
@@ -574,8 +585,10 @@ pipe_status_t run_band_passes(pipe_plan_s* p, const void* rho, void* phi, void* 
     return PIPE_OK;
 }
 
+// record_use: note the stream for pipe_plan_destroy (creates one event the
+// first time a stream is seen; the allocation-free entry point skips it).
 pipe_status_t solve_impl(pipe_plan_t plan, const void* rho, void* phi, void* ws, void* stream, bool adjoint,
-                         hipEvent_t* ev) {
+                         hipEvent_t* ev, bool record_use = true) {
     pipe_status_t s = check_solve_args(plan, rho, phi, ws);
     if (s != PIPE_OK) return s;
     int cur = -1;
@@ -589,7 +602,7 @@ pipe_status_t solve_impl(pipe_plan_t plan, const void* rho, void* phi, void* ws,
     else
         s = plan->rb == 8 ? run_passes<double>(plan, rho, phi, ws, st, adjoint, ev)
                           : run_passes<float>(plan, rho, phi, ws, st, adjoint, ev);
-    if (s == PIPE_OK) {
+    if (s == PIPE_OK && record_use) {
         const hipError_t e = note_use(plan, st);
         if (e != hipSuccess) s = hip_fail(e, "solve completion event");
     }
@@ -1018,6 +1031,18 @@ pipe_status_t pipe_poisson_solve(pipe_plan_t plan, const void* rho, void* phi, v
 
 pipe_status_t pipe_poisson_adjoint(pipe_plan_t plan, const void* dphi, void* drho, void* ws, void* stream) {
     return solve_impl(plan, dphi, drho, ws, stream, true, nullptr);
+}
+
+pipe_status_t pipe_poisson_solve_noalloc(pipe_plan_t plan, const void* rho, void* phi, void* stream) {
+    if (!reg_has(plan)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
+    if (plan->ws_bytes > kScratchBytes)
+        return fail(PIPE_ERR_UNSUPPORTED_SIZE,
+                    "the plan needs %zu bytes of workspace; the fixed scratch holds %zu (use pipe_poisson_solve "
+                    "with a workspace of info.workspace_bytes)",
+                    plan->ws_bytes, kScratchBytes);
+    void* ws = plan->ctx->scratch;   // the plan's device's copy, set up with the device context
+    if (!ws) return fail(PIPE_ERR_HIP, "fixed scratch not set up on device %d", plan->device);
+    return solve_impl(plan, rho, phi, ws, stream, false, nullptr, false);
 }
 
 pipe_status_t pipe_poisson_solve_timed(pipe_plan_t plan, const void* rho, void* phi, void* ws, void* stream,

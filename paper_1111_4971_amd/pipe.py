@@ -81,6 +81,7 @@ def lib():
         "pipe_plan_info": ([_P, ctypes.POINTER(PlanInfo)], _I),
         "pipe_poisson_solve": ([_P, _P, _P, _P, _P], _I),
         "pipe_poisson_adjoint": ([_P, _P, _P, _P, _P], _I),
+        "pipe_poisson_solve_noalloc": ([_P, _P, _P, _P], _I),
         "pipe_poisson_solve_timed": ([_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_float)], _I),
         "pipe_batch_create": ([ctypes.POINTER(_P), _I, ctypes.POINTER(_P)], _I),
         "pipe_batch_workspace": ([_P, ctypes.POINTER(ctypes.c_size_t)], _I),
@@ -267,6 +268,15 @@ class GreenPlan:
 
     def solve(self, rho, out=None, workspace=None, stream=None):
         return self._run(lib().pipe_poisson_solve, rho, out, workspace, stream)
+
+    def solve_noalloc(self, rho, out, stream=None):
+        """pipe_poisson_solve_noalloc: phi = A rho using the library's fixed
+        device scratch instead of a workspace (out must be given)."""
+        x = self._prep(rho)
+        self._check_out(out, x)
+        check(lib().pipe_poisson_solve_noalloc(self.handle, _P(x.data_ptr()), _P(out.data_ptr()),
+                                                _stream_ptr(stream)))
+        return out
 
     def adjoint(self, dphi, out=None, workspace=None, stream=None):
         return self._run(lib().pipe_poisson_adjoint, dphi, out, workspace, stream)
