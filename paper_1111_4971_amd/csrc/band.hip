@@ -43,7 +43,7 @@ void strided_pair_kernel(const void* in, void* out, int n_in, int n_out, long r_
     constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -55,7 +55,7 @@ void strided_pair_kernel(const void* in, void* out, int n_in, int n_out, long r_
     const long roff = active ? slab * r_ss + 2 * col : 0;
     const long coff = active ? slab * c_ss + col : 0;
     LdsCol<C, T> view{lds + s * N * T + c};
-    fft_line<N, INV, false>(
+    fft_line<Plan<N>, INV, false>(
         t, tw,
         [&](int e) -> C {
             if (!(active && e < n_in)) return cmake<C>(0, 0);
@@ -144,7 +144,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
     __shared__ C lds[2 * N * TS];
     __shared__ C s_tw[N];
     __shared__ real sK[10 * NKX];   // K0..K9 of one plane distance, this block's ky
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const unsigned ntile = gridDim.x;
     const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
@@ -185,7 +185,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
         const int pc = pbase + ch * T + c;
         const bool act = ch * T + c < ncolp && pc >= 0 && pc < nzp;
         const C* line = in + (act ? (long)kyl * nx * nzp + pc : 0);
-        fft_line<N, false, false>(
+        fft_line<Plan<N>, false, false>(
             t, tw, [&](int e) -> C { return (act && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
             [&](int e, C v) { view.set(e, v); }, view);
         __syncthreads();
@@ -300,7 +300,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
     const int pco = to * tile + c;
     const bool oact = c < to && pco < nzp && !(l == 1 && self);
     C* oline = out + (oact ? (long)kyl * nx * nzp + pco : 0);
-    fft_line<N, true, true>(
+    fft_line<Plan<N>, true, true>(
         t, tw, [&](int e) -> C { return view.get(e); },
         [&](int e, C v) {
             if (oact && e < nx) oline[e * xs] = v;
@@ -329,7 +329,7 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NKX = N / 2 + 1;
     __shared__ C lds[2 * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const unsigned ntile = gridDim.x;
     const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
@@ -345,7 +345,7 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     C* oline = out + (active ? (long)kyl * nx * nzp + pc : 0);
     LdsCol<C, T> view{lds + l * N * T + c};
 
-    fft_line<N, false, false>(
+    fft_line<Plan<N>, false, false>(
         t, tw, [&](int e) -> C { return (active && e < nx) ? iline[e * xs] : cmake<C>(0, 0); },
         [&](int e, C v) { view.set(e, v); }, view);
     __syncthreads();
@@ -383,7 +383,7 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     }
     __syncthreads();
 
-    fft_line<N, true, true>(
+    fft_line<Plan<N>, true, true>(
         t, tw, [&](int e) -> C { return view.get(e); },
         [&](int e, C v) {
             if (active && e < nx && !(l == 1 && self)) oline[e * xs] = v;
@@ -408,7 +408,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     constexpr int IM = (NH * T + NT - 1) / NT;   // (orbit < N/2, output column) items per thread, at most
     __shared__ C lds[2 * N * TS];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const unsigned ntile = gridDim.x;
     const unsigned lid = xcd_remap(blockIdx.x + ntile * blockIdx.y, ntile * gridDim.y);
@@ -429,7 +429,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
         const int pc = pbase + c;
         const bool act = c < ncolp && pc >= 0 && pc < nzp;
         const C* line = in + (act ? (long)kyl * nx * nzp + pc : 0);
-        fft_line<N, false, false>(
+        fft_line<Plan<N>, false, false>(
             t, tw, [&](int e) -> C { return (act && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
             [&](int e, C v) { view.set(e, v); }, view);
     }
@@ -514,7 +514,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     const int pco = to * tile + c;
     const bool oact = c < to && pco < nzp && !(l == 1 && self);
     C* oline = out + (oact ? (long)kyl * nx * nzp + pco : 0);
-    fft_line<N, true, true>(
+    fft_line<Plan<N>, true, true>(
         t, tw, [&](int e) -> C { return view.get(e); },
         [&](int e, C v) {
             if (oact && e < nx) oline[e * xs] = v;
@@ -532,7 +532,7 @@ void strided_real_kernel(const void* in, void* out, int n_in, int n_out, long in
     constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -540,7 +540,7 @@ void strided_real_kernel(const void* in, void* out, int n_in, int n_out, long in
     const long ioff = active ? slab * in_ss + col : 0;
     const long ooff = active ? slab * out_ss + col : 0;
     LdsCol<C, T> view{lds + s * N * T + c};
-    fft_line<N, INV, false>(
+    fft_line<Plan<N>, INV, false>(
         t, tw,
         [&](int e) -> C {
             if (!(active && e < n_in)) return cmake<C>(0, 0);

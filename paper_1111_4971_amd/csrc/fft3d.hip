@@ -19,7 +19,7 @@ void lines_kernel(const cplx<real>* in, cplx<real>* out, long nlines, const cplx
     constexpr int P = N / Plan<N>::E, LPB = lines_per_block<real, N>(), LS = N + N / 16 + 1;
     __shared__ C lds[LPB * LS];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int t = threadIdx.x % P, li = threadIdx.x / P;
     const long line = (long)blockIdx.x * LPB + li;
     const bool active = line < nlines;
@@ -27,7 +27,7 @@ void lines_kernel(const cplx<real>* in, cplx<real>* out, long nlines, const cplx
     C* dst = out + (active ? line * N : 0);
     LdsLine<C> view{lds + li * LS};
     // single-stage plans (P = 1) keep a line in one thread, so in == out is safe
-    fft_line<N, INV, false>(
+    fft_line<Plan<N>, INV, false>(
         t, tw, [&](int e) -> C { return active ? src[e] : cmake<C>(0, 0); },
         [&](int e, C v) {
             if (active) dst[e] = v;

@@ -180,14 +180,17 @@ template <int R, bool INV, typename C> __device__ __forceinline__ void dft(C* v)
 // worth of FP64 values (current and prefetched); single-stage plans have
 // P = 1, so a line is never shared by threads of one stage (in-place safe).
 
-template <int N> struct Plan;
-#define PIPE_PLAN(N_, E_, ...)                                                         \
-    template <> struct Plan<N_> {                                                      \
-        static constexpr int E = E_;                                                   \
+// Plan<N> is a length's default plan; Plan<N, V> with V >= 1 are variants a
+// kernel may choose instead (another E, so another thread count per line).
+template <int N, int V = 0> struct Plan;
+#define PIPE_PLAN_V(N_, V_, E_, ...)                                                   \
+    template <> struct Plan<N_, V_> {                                                  \
+        static constexpr int LEN = N_, VAR = V_, E = E_;                               \
         static constexpr int rad[] = {__VA_ARGS__};                                    \
         static constexpr int S = (int)(sizeof(rad) / sizeof(int));                     \
         static constexpr int radix(int s) { return rad[s]; }                           \
     };
+#define PIPE_PLAN(N_, E_, ...) PIPE_PLAN_V(N_, 0, E_, __VA_ARGS__)
 PIPE_PLAN(8, 8, 8)
 PIPE_PLAN(9, 9, 9)
 PIPE_PLAN(12, 12, 3, 4)
@@ -224,44 +227,66 @@ PIPE_PLAN(768, 24, 3, 8, 8, 4)
 PIPE_PLAN(864, 24, 3, 3, 3, 8, 4)
 PIPE_PLAN(972, 18, 9, 9, 3, 2, 2)
 PIPE_PLAN(1024, 16, 16, 16, 4)
+// variants: twice the threads per line (half the values per thread)
+PIPE_PLAN_V(256, 1, 8, 8, 8, 4)
 #undef PIPE_PLAN
+#undef PIPE_PLAN_V
 
-template <int N> __host__ __device__ constexpr int plan_ns(int s) {
+// The (length, variant) pairs that exist beyond the defaults; the twiddle bank
+// holds a stage table for each.
+#define PIPE_FOR_EACH_VARIANT(X) X(256, 1)
+
+template <class PL> __host__ __device__ constexpr int plan_ns(int s) {
     int ns = 1;
-    for (int i = 0; i < s; ++i) ns *= Plan<N>::radix(i);
+    for (int i = 0; i < s; ++i) ns *= PL::radix(i);
     return ns;
 }
 
-template <int N> constexpr bool plan_ok() {
-    constexpr int E = Plan<N>::E, S = Plan<N>::S;
-    if (N % E != 0 || plan_ns<N>(S) != N) return false;
+template <class PL> constexpr bool plan_ok() {
+    constexpr int N = PL::LEN, E = PL::E, S = PL::S;
+    if (N % E != 0 || plan_ns<PL>(S) != N) return false;
     for (int s = 0; s < S; ++s)
-        if (E % Plan<N>::radix(s) != 0) return false;
+        if (E % PL::radix(s) != 0) return false;
     return S > 1 || E == N;
 }
 
-// Stage twiddle table of length N: stage s >= 1 (radix R, span NS) owns R - 1
-// runs of NS values starting at stage_tw_offset<N>(NS); run r - 1 holds
-// W_{NS R}^{r k} = W_N^{r k N / (NS R)} for k < NS.  The lanes of a stage
+// Stage twiddle table of plan PL (length N): stage s >= 1 (radix R, span NS)
+// owns R - 1 runs of NS values starting at stage_tw_offset<PL>(NS); run r - 1
+// holds W_{NS R}^{r k} = W_N^{r k N / (NS R)} for k < NS.  The lanes of a stage
 // differ in k, so they read consecutive entries (no LDS bank conflicts), where
 // a natural-order table would be read at stride r N / (NS R).
-template <int N> __host__ __device__ constexpr int stage_tw_offset(int ns) {
+template <class PL> __host__ __device__ constexpr int stage_tw_offset(int ns) {
     int off = 0;
-    for (int s = 1; s < Plan<N>::S; ++s) {
-        if (plan_ns<N>(s) == ns) return off;
-        off += (Plan<N>::radix(s) - 1) * plan_ns<N>(s);
+    for (int s = 1; s < PL::S; ++s) {
+        if (plan_ns<PL>(s) == ns) return off;
+        off += (PL::radix(s) - 1) * plan_ns<PL>(s);
     }
     return off;
 }
-template <int N> __host__ __device__ constexpr int stage_tw_size() { return stage_tw_offset<N>(0); }
+template <class PL> __host__ __device__ constexpr int stage_tw_size() { return stage_tw_offset<PL>(0); }
+
+// Exchange ordering between the stages of a transform.  BLOCK: a block barrier
+// (the threads of a line may sit in several waves).  WAVE: every line lies
+// inside one wavefront (P divides 64), so ordering the wave's own LDS accesses
+// suffices and the waves of a block run independently.
+enum class Sync { BLOCK, WAVE };
+template <Sync SY> __device__ __forceinline__ void line_sync() {
+    if constexpr (SY == Sync::BLOCK) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
 
 // ---------------------------------------------------------------- stage pieces
 // v[b*R + r] holds input r of the thread's b-th butterfly, j = t + b*P.
 
 // Load the inputs of a stage with radix R: element index e = j + r*N/R.
-template <int N, int R, typename C, typename Src>
+template <class PL, int R, typename C, typename Src>
 __device__ __forceinline__ void stage_load(C* v, int t, Src src) {
-    constexpr int E = Plan<N>::E, P = N / E, NB = E / R;
+    constexpr int N = PL::LEN, E = PL::E, P = N / E, NB = E / R;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -269,14 +294,14 @@ __device__ __forceinline__ void stage_load(C* v, int t, Src src) {
 }
 
 // Twiddle (for Ns > 1) and butterfly in registers.
-template <int N, int R, int NS, bool INV, typename C>
+template <class PL, int R, int NS, bool INV, typename C>
 __device__ __forceinline__ void stage_compute(C* v, int t, const C* __restrict__ tw) {
-    constexpr int E = Plan<N>::E, P = N / E, NB = E / R;
+    constexpr int N = PL::LEN, E = PL::E, P = N / E, NB = E / R;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if constexpr (NS > 1) {
             const int k = (t + b * P) % NS;
-            constexpr int off = stage_tw_offset<N>(NS);
+            constexpr int off = stage_tw_offset<PL>(NS);
 #pragma unroll
             for (int r = 1; r < R; ++r) v[b * R + r] = ctw<INV>(v[b * R + r], tw[off + (r - 1) * NS + k]);
         }
@@ -285,9 +310,9 @@ __device__ __forceinline__ void stage_compute(C* v, int t, const C* __restrict__
 }
 
 // Store the outputs of a stage: element (j div NS) NS R + (j mod NS) + r NS.
-template <int N, int R, int NS, typename C, typename Dst>
+template <class PL, int R, int NS, typename C, typename Dst>
 __device__ __forceinline__ void stage_store(const C* v, int t, Dst dst) {
-    constexpr int E = Plan<N>::E, P = N / E, NB = E / R;
+    constexpr int N = PL::LEN, E = PL::E, P = N / E, NB = E / R;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + b * P;
@@ -300,40 +325,41 @@ __device__ __forceinline__ void stage_store(const C* v, int t, Dst dst) {
 // Stage s of the transform from its inputs in registers: twiddle and
 // butterflies, then the last stage stores to dst, any other stage exchanges
 // through LDS and continues with stage s + 1.
-template <int N, int s, bool INV, typename C, typename Dst, typename Lds>
+template <class PL, int s, bool INV, Sync SY, typename C, typename Dst, typename Lds>
 __device__ __forceinline__ void fft_stages(C* v, int t, const C* __restrict__ tw, Dst dst, Lds lds) {
-    constexpr int R = Plan<N>::radix(s), NS = plan_ns<N>(s);
-    stage_compute<N, R, NS, INV>(v, t, tw);
-    if constexpr (s == Plan<N>::S - 1) {
-        stage_store<N, R, NS>(v, t, dst);
+    constexpr int R = PL::radix(s), NS = plan_ns<PL>(s);
+    stage_compute<PL, R, NS, INV>(v, t, tw);
+    if constexpr (s == PL::S - 1) {
+        stage_store<PL, R, NS>(v, t, dst);
     } else {
-        stage_store<N, R, NS>(v, t, [&](int e, C x) { lds.set(e, x); });
-        __syncthreads();
-        stage_load<N, Plan<N>::radix(s + 1)>(v, t, [&](int e) { return lds.get(e); });
-        __syncthreads();
-        fft_stages<N, s + 1, INV>(v, t, tw, dst, lds);
+        stage_store<PL, R, NS>(v, t, [&](int e, C x) { lds.set(e, x); });
+        line_sync<SY>();
+        stage_load<PL, PL::radix(s + 1)>(v, t, [&](int e) { return lds.get(e); });
+        line_sync<SY>();
+        fft_stages<PL, s + 1, INV, SY>(v, t, tw, dst, lds);
     }
 }
 
 // Whole transform from stage-0 inputs already in registers (v, loaded by
-// stage_load<N, radix(0)>).  dst is the element accessor of the last store;
+// stage_load<PL, radix(0)>).  dst is the element accessor of the last store;
 // lds.get(e) / lds.set(e, v) address this thread's line in LDS.  Every thread
-// of the block must call this (it contains barriers).
-template <int N, bool INV, typename C, typename Dst, typename Lds>
+// of the block (SY = BLOCK) or of the wave (SY = WAVE) must call this.
+template <class PL, bool INV, Sync SY = Sync::BLOCK, typename C, typename Dst, typename Lds>
 __device__ __forceinline__ void fft_line_regs(C* v, int t, const C* __restrict__ tw, Dst dst, Lds lds) {
-    static_assert(plan_ok<N>(), "inconsistent length plan");
-    fft_stages<N, 0, INV>(v, t, tw, dst, lds);
+    static_assert(plan_ok<PL>(), "inconsistent length plan");
+    fft_stages<PL, 0, INV, SY>(v, t, tw, dst, lds);
 }
 
 // Whole transform.  src/dst are element accessors for the first load and the
 // last store.  SRC_LDS: the first load reads the same LDS line that later
 // stages overwrite, so a barrier separates it from the first store.
-template <int N, bool INV, bool SRC_LDS, typename C, typename Src, typename Dst, typename Lds>
+template <class PL, bool INV, bool SRC_LDS, Sync SY = Sync::BLOCK, typename C, typename Src, typename Dst,
+          typename Lds>
 __device__ __forceinline__ void fft_line(int t, const C* __restrict__ tw, Src src, Dst dst, Lds lds) {
-    C v[Plan<N>::E];
-    stage_load<N, Plan<N>::radix(0)>(v, t, src);
-    if constexpr (SRC_LDS && Plan<N>::S > 1) __syncthreads();
-    fft_line_regs<N, INV>(v, t, tw, dst, lds);
+    C v[PL::E];
+    stage_load<PL, PL::radix(0)>(v, t, src);
+    if constexpr (SRC_LDS && PL::S > 1) line_sync<SY>();
+    fft_line_regs<PL, INV, SY>(v, t, tw, dst, lds);
 }
 
 }  // namespace pipe

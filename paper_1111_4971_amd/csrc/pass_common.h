@@ -99,6 +99,17 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned p, unsigned total) {
     return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
+// Exchange ordering of the z passes: with PIPE_Z_WAVE_SYNC, a length whose
+// lines each fit inside one wavefront (P divides 64) orders its LDS exchanges
+// per wave, so the waves of a block need not wait for each other.
+#ifndef PIPE_Z_WAVE_SYNC
+#define PIPE_Z_WAVE_SYNC 1
+#endif
+template <int NH> constexpr Sync z_sync() {
+    constexpr int P = NH / Plan<NH>::E;
+    return (PIPE_Z_WAVE_SYNC && P <= 64 && 64 % P == 0) ? Sync::WAVE : Sync::BLOCK;
+}
+
 template <typename real, int NH> constexpr int z_lines() {
     int l = ce_max(1, PIPE_Z_THREADS / (NH / Plan<NH>::E));
     while (l > 1 && l * (NH + NH / 16 + 1) * 2 * (int)sizeof(real) > PIPE_LDS_CAP) l /= 2;
@@ -118,6 +129,19 @@ template <typename real> struct Orbit {
 // Nine values of one orbit, `stride` apart (T in the tiled table, 1 for kz = lz/2).
 template <typename real>
 __device__ __forceinline__ Orbit<real> load_orbit(gptr<const real> e, int stride) {
+    using C = cplx<real>;
+    Orbit<real> o;
+    o.cc = e[0];
+    o.cr = cmake<C>(e[stride], e[2 * stride]);
+    o.rc = cmake<C>(e[3 * stride], e[4 * stride]);
+    o.rr = cmake<C>(e[5 * stride], e[6 * stride]);
+    o.rr2 = cmake<C>(e[7 * stride], e[8 * stride]);
+    return o;
+}
+
+// The same from LDS.
+template <typename real>
+__device__ __forceinline__ Orbit<real> load_orbit_lds(const real* e, int stride) {
     using C = cplx<real>;
     Orbit<real> o;
     o.cc = e[0];

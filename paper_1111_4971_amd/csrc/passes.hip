@@ -47,33 +47,46 @@ template <typename C> const C* TwiddleBank::get(int n) const {
     }
     return nullptr;
 }
-template <typename C> const C* TwiddleBank::stage(int n) const {
-    for (int i = 0; i < kNumFft; ++i)
-        if (kFftLengths[i] == n) return bank_base<C>(*this) + soffset[i];
+template <typename C> const C* TwiddleBank::stage(int n, int variant) const {
+    if (variant == 0) {
+        for (int i = 0; i < kNumFft; ++i)
+            if (kFftLengths[i] == n) return bank_base<C>(*this) + soffset[i];
+        return nullptr;
+    }
+    for (int i = 0; i < kNumVariants; ++i)
+        if (kPlanVariants[i].n == n && kPlanVariants[i].v == variant) return bank_base<C>(*this) + voffset[i];
     return nullptr;
 }
 template const float2* TwiddleBank::get<float2>(int) const;
 template const double2* TwiddleBank::get<double2>(int) const;
-template const float2* TwiddleBank::stage<float2>(int) const;
-template const double2* TwiddleBank::stage<double2>(int) const;
+template const float2* TwiddleBank::stage<float2>(int, int) const;
+template const double2* TwiddleBank::stage<double2>(int, int) const;
 
-template <int N> static int stage_exponents(int* m) {
+template <class PL> static int stage_exponents(int* m) {
+    constexpr int N = PL::LEN;
     int i = 0;
-    for (int s = 1; s < Plan<N>::S; ++s) {
-        const int R = Plan<N>::radix(s), NS = plan_ns<N>(s);
+    for (int s = 1; s < PL::S; ++s) {
+        const int R = PL::radix(s), NS = plan_ns<PL>(s);
         for (int r = 1; r < R; ++r)
             for (int k = 0; k < NS; ++k) m[i++] = r * k * (N / (NS * R));
     }
     return i;
 }
 
-int fft_stage_exponents(int n, int* m_out) {
-    switch (n) {
+int fft_stage_exponents(int n, int variant, int* m_out) {
+    if (variant == 0) {
+        switch (n) {
 #define X(N_) \
-    case N_: return stage_exponents<N_>(m_out);
-        PIPE_FOR_EACH_N(X)
+    case N_: return stage_exponents<Plan<N_>>(m_out);
+            PIPE_FOR_EACH_N(X)
 #undef X
+        }
+        return -1;
     }
+#define X(N_, V_) \
+    if (n == N_ && variant == V_) return stage_exponents<Plan<N_, V_>>(m_out);
+    PIPE_FOR_EACH_VARIANT(X)
+#undef X
     return -1;
 }
 #endif
@@ -102,10 +115,12 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     constexpr int E = Plan<NH>::E, P = NH / E, LPW = z_lines<real, NH>();
     constexpr int R0 = Plan<NH>::radix(0);
     constexpr int PADN = NH + NH / 16 + 1;
+    constexpr Sync ZS = z_sync<NH>();
     __shared__ C lds[LPW * PADN];
     __shared__ C s_tw[NH], s_tw2[NH];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<NH>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<NH>>());
     tw2 = stage_twiddles(s_tw2, tw2, NH);
+    if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
     const int t = threadIdx.x % P, l = threadIdx.x / P;
     LdsLine<C> view{lds + l * PADN};
     const long ngroups = (nlines + LPW - 1) / LPW;
@@ -115,7 +130,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     auto load = [&](C* v, long line) {
         const bool active = line < nlines;
         const gptr<const real> src = gin + (active ? line : 0) * in_pitch;
-        stage_load<NH, R0>(v, t, [&](int m) -> C {
+        stage_load<Plan<NH>, R0>(v, t, [&](int m) -> C {
             if (vec2) {
                 if (active && 2 * m < n_in) return reinterpret_cast<gptr<const C>>(src)[m];
                 return cmake<C>(0, 0);
@@ -134,8 +149,8 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     for (; g < ngroups; g += gridDim.x) {
         const long gn = g + gridDim.x;
         if (gn < ngroups) load(nxt, gn * LPW + l);
-        fft_line_regs<NH, false>(cur, t, tw, [&](int k, C v) { view.set(k, v); }, view);
-        __syncthreads();
+        fft_line_regs<Plan<NH>, false, ZS>(cur, t, tw, [&](int k, C v) { view.set(k, v); }, view);
+        line_sync<ZS>();
         const long line = g * LPW + l;
         if (line < nlines) {
             const gptr<C> dst = gout + line * out_pitch;
@@ -153,7 +168,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
                 }
             }
         }
-        __syncthreads();
+        line_sync<ZS>();
 #pragma unroll
         for (int q = 0; q < E; ++q) cur[q] = nxt[q];
     }
@@ -176,10 +191,12 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
     }
     constexpr int E = Plan<NH>::E, P = NH / E, LPW = z_lines<real, NH>();
     constexpr int PADN = NH + NH / 16 + 1;
+    constexpr Sync ZS = z_sync<NH>();
     __shared__ C lds[LPW * PADN];
     __shared__ C s_tw[NH], s_tw2[NH];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<NH>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<NH>>());
     tw2 = stage_twiddles(s_tw2, tw2, NH);
+    if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
     const int t = threadIdx.x % P, l = threadIdx.x / P;
     LdsLine<C> view{lds + l * PADN};
     const long ngroups = (nlines + LPW - 1) / LPW;
@@ -202,12 +219,12 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
         const long gn = g + gridDim.x;
 #pragma unroll
         for (int q = 0; q < E; ++q) view.set(t + q * P, cur[q]);
-        __syncthreads();
+        line_sync<ZS>();
         if (gn < ngroups) load(nxt, gn * LPW + l);
         const long line = g * LPW + l;
         const bool active = line < nlines;
         const gptr<real> dst = gout + (active ? line : 0) * out_pitch;
-        fft_line<NH, true, true>(
+        fft_line<Plan<NH>, true, true, ZS>(
             t, tw,
             [&](int k) -> C {
                 const C xk = view.get(k);
@@ -227,7 +244,7 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
                 if (2 * m + 1 < n_out) dst[2 * m + 1] = v.y * scale;
             },
             view);
-        __syncthreads();
+        line_sync<ZS>();
 #pragma unroll
         for (int q = 0; q < E; ++q) cur[q] = nxt[q];
     }
@@ -248,7 +265,7 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
     constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -256,7 +273,7 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
     const gptr<const C> src = to_global(in) + (active ? slab * in_ss + col : 0);
     const gptr<C> dst = to_global(out) + (active ? slab * out_ss + col : 0);
     LdsCol<C, T> view{lds + s * N * T + c};
-    fft_line<N, INV, false>(
+    fft_line<Plan<N>, INV, false>(
         t, tw,
         [&](int e) -> C {
             if (active && e < n_in) return src[e * in_es];
@@ -274,13 +291,16 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
 // data is the ky-major (ly, nx, lz/2) array, so a line's rows are lz/2 apart.  The
 // spectra are stored tile-blocked (see xprod_tile); the kz = lz/2 values sit in
 // `nyq`.  NV = 9: the four terms; NV = 1: T_cc alone (free space), where the
-// product is a real scaling and its own adjoint.
-template <typename real, int N, int T, bool ADJ, int NV>
-__global__ __launch_bounds__(2 * (N / Plan<N>::E) * T)
+// product is a real scaling and its own adjoint.  V selects the length plan
+// (Plan<N, V>: the variant with fewer values per thread gives FP64 more
+// threads for the same LDS tile).
+template <typename real, int N, int V, int T, bool ADJ, int NV>
+__global__ __launch_bounds__(2 * (N / Plan<N, V>::E) * T)
 void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restrict__ table,
                   const real* __restrict__ nyq, const cplx<real>* __restrict__ tw,
                   const GroupArgs* __restrict__ group, int shared_table) {
     using C = cplx<real>;
+    using PL = Plan<N, V>;
     // Logical order of the (kz tile, ky) items: neighbouring kz tiles share
     // 128-byte lines when T complex values are narrower, so consecutive items
     // run back to back on one XCD.  When the members of a grouped launch share
@@ -302,10 +322,19 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
         table = (const real*)group[member].table;
         nyq = (const real*)group[member].nyq;
     }
-    constexpr int P = N / Plan<N>::E, NT = 2 * P * T;
+    constexpr int P = N / PL::E, NT = 2 * P * T;
+    // Orbits kx = 0 .. NKX - 1 (NKX = N/2 + 1 table entries).  For even N the
+    // Nyquist orbit kx = N/2 would add a whole register set of spectra per
+    // thread for T items; when the block has at least NV T threads its values
+    // are loaded one per thread and staged through LDS instead (NYQ_LDS), and
+    // the register loop covers the NO = N/2 other orbits.
+    constexpr int NKX = N / 2 + 1;
+    constexpr bool NYQ_LDS = (N % 2 == 0) && NT >= NV * T;
+    constexpr int NO = NYQ_LDS ? N / 2 : NKX;
     __shared__ C lds[2 * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<N>());
+    __shared__ real s_nyo[NYQ_LDS ? NV * T : 1];
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const int tile = (int)(item % ntile);
     const int ky = (int)(item / ntile);
@@ -318,7 +347,6 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     LdsCol<C, T> view{lds + l * N * T + c};
 
     const int kyo = ky;
-    constexpr int NKX = N / 2 + 1;
     const int ntiles = (nh + T - 1) / T;
     const gptr<const real> tblock = to_global(table) + ((long)kyo * ntiles + tile) * NKX * NV * T;
     auto load = [](gptr<const real> e, int stride) -> Orbit<real> {
@@ -339,18 +367,22 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     // together with the block's rows, before the forward transform, so all of
     // the block's global reads are in flight at once.  Issue order (measured):
     // rows first in single precision, spectra first in double.
-    constexpr int IT = (NKX * T + NT - 1) / NT;
+    constexpr int IT = (NO * T + NT - 1) / NT;
     Orbit<real> obs[IT];
+    real nyo = 0;
     auto load_spectra = [&] {
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             const int w = threadIdx.x + it * NT;
-            if (w < NKX * T) obs[it] = load(tblock + (long)(w / T) * NV * T + w % T, T);
+            if (w < NO * T) obs[it] = load(tblock + (long)(w / T) * NV * T + w % T, T);
+        }
+        if constexpr (NYQ_LDS) {
+            if (threadIdx.x < NV * T) nyo = tblock[(long)(N / 2) * NV * T + threadIdx.x];
         }
     };
-    C v0[Plan<N>::E];
+    C v0[PL::E];
     auto load_rows = [&] {
-        stage_load<N, Plan<N>::radix(0)>(v0, t, [&](int e) -> C {
+        stage_load<PL, PL::radix(0)>(v0, t, [&](int e) -> C {
             if (active && e < nx) return line[e * xs];
             return cmake<C>(0, 0);
         });
@@ -362,22 +394,21 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
         load_rows();
         load_spectra();
     }
-    fft_line_regs<N, false>(v0, t, tw, [&](int e, C v) { view.set(e, v); }, view);
+    fft_line_regs<PL, false>(v0, t, tw, [&](int e, C v) { view.set(e, v); }, view);
+    if constexpr (NYQ_LDS) {
+        if (threadIdx.x < NV * T) s_nyo[threadIdx.x] = nyo;
+    }
     __syncthreads();
 
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int w = threadIdx.x + it * NT;
-        if (w >= NKX * T) break;
-        const int cc = w % T, o = w / T;
+    // the product of orbit o, kz column cc (in place in the two LDS lines)
+    auto orbit_item = [&](int o, int cc, const Orbit<real>& ob) {
         const long kzz = (long)tile * T + cc;
-        if (kzz >= nh) continue;
+        if (kzz >= nh) return;
         const int on = (N - o) % N;
         C* L0 = lds + cc;
         C* L1 = lds + N * T + cc;
         C r[4] = {L0[o * T], L0[on * T], L1[o * T], L1[on * T]};
         C p[4];
-        const Orbit<real>& ob = obs[it];
         if (kzz != 0) {
             product(ob, r, p);
         } else {
@@ -387,8 +418,8 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const C pm = cconj(r[3 - q]);
-                const C s = cadd(r[q], pm), d = csub(r[q], pm);
-                ra[q] = cscale(s, (real)0.5);
+                const C sm = cadd(r[q], pm), d = csub(r[q], pm);
+                ra[q] = cscale(sm, (real)0.5);
                 rb[q] = cscale(cmake<C>(d.y, -d.x), (real)0.5);
             }
             const Orbit<real> obn = load(to_global(nyq) + ((long)kyo * NKX + o) * NV, 1);
@@ -401,10 +432,29 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
         L0[on * T] = p[1];
         L1[o * T] = p[2];
         L1[on * T] = p[3];
+    };
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int w = threadIdx.x + it * NT;
+        if (w >= NO * T) break;
+        orbit_item(w / T, w % T, obs[it]);
+    }
+    if constexpr (NYQ_LDS) {
+        // the Nyquist orbit: T items, one per thread of the first T
+        if (threadIdx.x < T) {
+            Orbit<real> ob;
+            if constexpr (NV == 9) {
+                ob = load_orbit_lds(s_nyo + threadIdx.x, T);
+            } else {
+                ob = Orbit<real>{};
+                ob.cc = s_nyo[threadIdx.x];
+            }
+            orbit_item(N / 2, threadIdx.x, ob);
+        }
     }
     __syncthreads();
 
-    fft_line<N, true, true>(
+    fft_line<PL, true, true>(
         t, tw, [&](int e) -> C { return view.get(e); },
         [&](int e, C v) {
             if (active && e < nx && !(l == 1 && self)) line[e * xs] = v;
@@ -506,10 +556,21 @@ hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_
     return hipErrorInvalidValue;
 }
 
+// Length plan of the fused x pass: the variant with fewer values per thread
+// where one exists for FP64 (twice the threads on the same LDS tile, and
+// fewer registers per thread), else the default.
+#ifndef PIPE_XPROD_F64_VARIANT
+#define PIPE_XPROD_F64_VARIANT 1
+#endif
+template <typename real, int N> constexpr int xprod_V() {
+    if constexpr (sizeof(real) == 8 && PIPE_XPROD_F64_VARIANT && N == 256) return 1;
+    return 0;
+}
+
 // kz tile of the fused x pass: 2 lines x lx x T complex values in LDS.
 template <typename real, int N> constexpr int xprod_T() {
     constexpr int bytes = sizeof(real) * 2;
-    constexpr int P = N / Plan<N>::E;
+    constexpr int P = N / Plan<N, xprod_V<real, N>()>::E;
     int t = PIPE_XPROD_TMAX;
     while (t > 1 && (2 * N * t * bytes > PIPE_LDS_CAP || 2 * P * t > 1024)) t /= 2;
     return t;
@@ -532,24 +593,25 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
                         const real* nyq, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
                         int ngroup, bool shared_table, int nval) {
     using C = cplx<real>;
-    const C* tw = twb.stage<C>(lx);
-    if (!tw || (nval != 9 && nval != 1)) return hipErrorInvalidValue;
+    if (nval != 9 && nval != 1) return hipErrorInvalidValue;
     switch (lx) {
-#define X(N_)                                                                                     \
-    case N_: {                                                                                    \
-        constexpr int T = xprod_T<real, N_>();                                                    \
-        constexpr int P = N_ / Plan<N_>::E;                                                       \
-        dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1), (unsigned)ngroup);        \
-        if (nval == 1)                                                                            \
-            hipLaunchKernelGGL((xprod_kernel<real, N_, T, false, 1>), grid, dim3(2 * P * T), 0,   \
-                               s, (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table); \
-        else if (adjoint)                                                                         \
-            hipLaunchKernelGGL((xprod_kernel<real, N_, T, true, 9>), grid, dim3(2 * P * T), 0, s, \
-                               (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);   \
-        else                                                                                      \
-            hipLaunchKernelGGL((xprod_kernel<real, N_, T, false, 9>), grid, dim3(2 * P * T), 0,   \
-                               s, (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table); \
-        return hipGetLastError();                                                                 \
+#define X(N_)                                                                                        \
+    case N_: {                                                                                       \
+        constexpr int V = xprod_V<real, N_>(), T = xprod_T<real, N_>();                              \
+        constexpr int P = N_ / Plan<N_, V>::E;                                                       \
+        const C* tw = twb.stage<C>(N_, V);                                                           \
+        if (!tw) return hipErrorInvalidValue;                                                        \
+        dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1), (unsigned)ngroup);           \
+        if (nval == 1)                                                                               \
+            hipLaunchKernelGGL((xprod_kernel<real, N_, V, T, false, 1>), grid, dim3(2 * P * T), 0,   \
+                               s, (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);    \
+        else if (adjoint)                                                                            \
+            hipLaunchKernelGGL((xprod_kernel<real, N_, V, T, true, 9>), grid, dim3(2 * P * T), 0, s, \
+                               (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);      \
+        else                                                                                         \
+            hipLaunchKernelGGL((xprod_kernel<real, N_, V, T, false, 9>), grid, dim3(2 * P * T), 0,   \
+                               s, (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);    \
+        return hipGetLastError();                                                                    \
     }
         PIPE_FOR_EACH_N(X)
 #undef X

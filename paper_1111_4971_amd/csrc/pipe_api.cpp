@@ -101,10 +101,12 @@ pipe_status_t device_ctx(int dev, DeviceCtx** out) {
             }
         }
         std::vector<int> ms(4096);
-        for (int i = 0; i < kNumFft; ++i) {
-            const int n = kFftLengths[i];
-            c.tw.soffset[i] = m_of.size();
-            const int cnt = fft_stage_exponents(n, ms.data());
+        for (int i = 0; i < kNumFft + kNumVariants; ++i) {
+            const int n = i < kNumFft ? kFftLengths[i] : kPlanVariants[i - kNumFft].n;
+            const int v = i < kNumFft ? 0 : kPlanVariants[i - kNumFft].v;
+            (i < kNumFft ? c.tw.soffset[i] : c.tw.voffset[i - kNumFft]) = m_of.size();
+            const int cnt = fft_stage_exponents(n, v, ms.data());
+            if (cnt < 0) return fail(PIPE_ERR_HIP, "no stage table for plan (%d, %d)", n, v);
             for (int q = 0; q < cnt; ++q) {
                 m_of.push_back(ms[q]);
                 n_of.push_back(n);

@@ -26,25 +26,34 @@ inline bool band_length_ok(int n) {
     return false;
 }
 
+// Plan variants beyond each length's default plan (fft_engine.h, Plan<N, V>);
+// must list the same pairs as PIPE_FOR_EACH_VARIANT.
+struct PlanVariant {
+    int n, v;
+};
+constexpr PlanVariant kPlanVariants[] = {{256, 1}};
+constexpr int kNumVariants = sizeof(kPlanVariants) / sizeof(PlanVariant);
+
 // Per-device twiddle bank: for every FFT length N the natural tables
 // tw[m] = exp(-2 pi i m / L), m < L, for L = N and L = 2N (get), and the stage
-// table of the transform engine (stage; see stage_tw_offset), all in one
-// allocation per precision.
+// table of every plan of the transform engine (stage; see stage_tw_offset),
+// all in one allocation per precision.
 struct TwiddleBank {
     void* d64 = nullptr;   // double2
     void* d32 = nullptr;   // float2
-    size_t offset[kNumFft] = {};    // natural table of length N
-    size_t offset2[kNumFft] = {};   // natural table of length 2N
-    size_t soffset[kNumFft] = {};   // stage table of length N
+    size_t offset[kNumFft] = {};        // natural table of length N
+    size_t offset2[kNumFft] = {};       // natural table of length 2N
+    size_t soffset[kNumFft] = {};       // stage table of the default plan of length N
+    size_t voffset[kNumVariants] = {};  // stage tables of the variant plans
     size_t total = 0;
     template <typename C> const C* get(int n) const;
-    template <typename C> const C* stage(int n) const;
+    template <typename C> const C* stage(int n, int variant = 0) const;
 };
 
-// Stage table of FFT length n: writes the exponent m of each entry (the entry
-// is W_n^m) to m_out (at least n slots) and returns the entry count, or -1 if
-// n is not an FFT length.
-int fft_stage_exponents(int n, int* m_out);
+// Stage table of the plan (n, variant): writes the exponent m of each entry
+// (the entry is W_n^m) to m_out (at least n slots) and returns the entry
+// count, or -1 if there is no such plan.
+int fft_stage_exponents(int n, int variant, int* m_out);
 
 // Per-member pointers of a grouped launch: blockIdx.z selects the member and its
 // entry replaces the launch's own data pointers (in/out; table/nyq for the x
