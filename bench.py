@@ -112,6 +112,7 @@ def time_leg(pipe, torch, wl, precision, steps, warmup):
         "ms_per_step_with_events": ms_events,
         "events_recorded": n,
         "plan_build_ms": info.build_ms,
+        "schedule": {"x_tile": info.xtile, "a2_row_pad": info.apad, "z_block_cap": info.zblocks},
         "model_bytes_per_solve": info.model_bytes,
         "model_GBps_whole_solve": info.model_bytes / (ms_step * 1e-3) / 1e9,
         "hbm_frac_whole_solve": info.model_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -92,6 +92,9 @@ typedef struct pipe_plan_info {
                              /* (0 = taken from the cache; -1 = not tuned)                */
     int band;                /* pipe_green_plan_banded: planes kept each side (N of Eq. 18);*/
                              /* -1 for the full 3-D plans                                 */
+    int xtile;               /* launch schedule (3-D plans; 0 for banded plans): kz tile of */
+    int apad;                /* the x pass, unused slots per row of the y-transformed array,*/
+    int zblocks;             /* block cap of the z passes; none of them changes a result   */
 } pipe_plan_info_t;
 
 /*
@@ -120,6 +123,16 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
  * the smallest such length >= 2n (lz: lz/2 >= nz).  The physical result does
  * not depend on the padded lengths.  hip_stream (a hipStream_t, may be NULL) orders the build's GPU
  * work; the call still returns only when the build has finished.
+ * Every 3-D plan (here, pipe_green_plan_region, pipe_free_plan) also picks a
+ * launch schedule by timing the solve on scratch buffers during the build:
+ * the kz tile of the x pass (its widest or half of it), the row pitch of the
+ * y-transformed array (lz/2 plus 0, 16 or 32) and the block cap of the z
+ * passes (1024 or 2048).  None of these changes any result; the choice is
+ * cached for the process (and in PIPE_TUNE_CACHE, "pipe-sched-v1" lines) and
+ * reported in pipe_plan_info (xtile, apad, zblocks).  The environment variable
+ * PIPE_SCHEDULE=fixed skips the timing (widest tile, no pad, 2048 blocks);
+ * PIPE_SCHEDULE=T,pad,cap forces a schedule (INVALID_ARG if T is neither the
+ * widest tile nor half of it, or pad is outside [0, 256]).
  * With PIPE_AUTOTUNE in kind and all lengths 0, the plan times the five
  * passes for each candidate factorisation per dimension (the smallest
  * supported length >= 2n, the smallest even one, the smallest power of two,

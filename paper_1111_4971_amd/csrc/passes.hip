@@ -35,6 +35,8 @@ namespace pipe {
 #define PIPE_TU_FP64 1
 #endif
 
+template <typename real> using C_of = cplx<real>;
+
 #if PIPE_TU_FP32
 template <typename C> static const C* bank_base(const TwiddleBank& b);
 template <> const float2* bank_base<float2>(const TwiddleBank& b) { return reinterpret_cast<const float2*>(b.d32); }
@@ -296,7 +298,7 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
 // threads for the same LDS tile).
 template <typename real, int N, int V, int T, bool ADJ, int NV>
 __global__ __launch_bounds__(2 * (N / Plan<N, V>::E) * T)
-void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restrict__ table,
+void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, long xs, const real* __restrict__ table,
                   const real* __restrict__ nyq, const cplx<real>* __restrict__ tw,
                   const GroupArgs* __restrict__ group, int shared_table) {
     using C = cplx<real>;
@@ -342,8 +344,8 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
     const bool self = (ky == 0) || (2 * ky == ly);
     const long kz = (long)tile * T + c;
     const bool active = kz < nh;
-    const long xs = nh;   // row (x) stride of the ky-major array
-    const gptr<C> line = to_global(data) + (active ? (long)kyl * nx * nh + kz : 0);
+    // xs: row (x) stride of the ky-major array
+    const gptr<C> line = to_global(data) + (active ? (long)kyl * nx * xs + kz : 0);
     LdsCol<C, T> view{lds + l * N * T + c};
 
     const int kyo = ky;
@@ -464,13 +466,11 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, const real* __restri
 
 // ---------------------------------------------------------------- launchers
 
-// Persistent grid of the z passes: at most PIPE_Z_BLOCKS blocks in total (over
-// all members of a grouped launch), each looping over its share of line groups.
-#ifndef PIPE_Z_BLOCKS
-#define PIPE_Z_BLOCKS 2048
-#endif
-static unsigned z_grid(long ngroups, int nmembers) {
-    long cap = PIPE_Z_BLOCKS / (nmembers > 0 ? nmembers : 1);
+// Persistent grid of the z passes: at most zcap blocks in total (over all
+// members of a grouped launch; a plan's schedule sets zcap), each looping over
+// its share of line groups.
+static unsigned z_grid(long ngroups, int nmembers, int zcap) {
+    long cap = (zcap > 0 ? zcap : 2048) / (nmembers > 0 ? nmembers : 1);
     if (cap < 1) cap = 1;
     return (unsigned)(ngroups < cap ? ngroups : cap);
 }
@@ -479,7 +479,7 @@ static unsigned z_grid(long ngroups, int nmembers) {
 template <typename real>
 hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* out, long out_pitch,
                         long nlines, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group, int ngroup,
-                        bool aligned) {
+                        bool aligned, int zcap) {
     using C = cplx<real>;
     const C* tw = twb.stage<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
@@ -490,7 +490,7 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
         constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
-        dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup), 1, (unsigned)ngroup);               \
+        dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup, zcap), 1, (unsigned)ngroup);               \
         hipLaunchKernelGGL((z_r2c_kernel<real, N_>), grid, dim3(LPW * P), 0, s, in, in_pitch,   \
                            n_in, (C*)out, out_pitch, nlines, tw, tw2, vec2, group);             \
         return hipGetLastError();                                                               \
@@ -504,7 +504,7 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
 template <typename real>
 hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long out_pitch, int n_out,
                         long nlines, real scale, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
-                        int ngroup, bool aligned) {
+                        int ngroup, bool aligned, int zcap) {
     using C = cplx<real>;
     const C* tw = twb.stage<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
@@ -515,7 +515,7 @@ hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long o
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
         constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
-        dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup), 1, (unsigned)ngroup);               \
+        dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup, zcap), 1, (unsigned)ngroup);               \
         hipLaunchKernelGGL((z_c2r_kernel<real, N_>), grid, dim3(LPW * P), 0, s, (const C*)in,   \
                            in_pitch, out, out_pitch, n_out, nlines, scale, tw, tw2, vec2, group); \
         return hipGetLastError();                                                               \
@@ -588,30 +588,48 @@ int xprod_tile(int lx, int real_bytes) {
 }
 #endif
 
+// The fused pass is compiled for two kz tiles per length: the widest T (above)
+// and T/2 (when T > 1); a plan's schedule picks one.
+template <typename real, int N, int T, int V>
+static hipError_t launch_xprod_t(bool adjoint, C_of<real>* data, int nx, int ly, int nh, long pitch,
+                                 const real* table, const real* nyq, const C_of<real>* tw, hipStream_t s,
+                                 const GroupArgs* group, int ngroup, bool shared_table, int nval) {
+    constexpr int P = N / Plan<N, V>::E;
+    dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1), (unsigned)ngroup);
+    if (nval == 1)
+        hipLaunchKernelGGL((xprod_kernel<real, N, V, T, false, 1>), grid, dim3(2 * P * T), 0, s, data, nx, ly, nh,
+                           pitch, table, nyq, tw, group, (int)shared_table);
+    else if (adjoint)
+        hipLaunchKernelGGL((xprod_kernel<real, N, V, T, true, 9>), grid, dim3(2 * P * T), 0, s, data, nx, ly, nh,
+                           pitch, table, nyq, tw, group, (int)shared_table);
+    else
+        hipLaunchKernelGGL((xprod_kernel<real, N, V, T, false, 9>), grid, dim3(2 * P * T), 0, s, data, nx, ly, nh,
+                           pitch, table, nyq, tw, group, (int)shared_table);
+    return hipGetLastError();
+}
+
 template <typename real>
-hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh, const real* table,
-                        const real* nyq, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
-                        int ngroup, bool shared_table, int nval) {
+hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh, long pitch, int tile,
+                        const real* table, const real* nyq, const TwiddleBank& twb, hipStream_t s,
+                        const GroupArgs* group, int ngroup, bool shared_table, int nval) {
     using C = cplx<real>;
-    if (nval != 9 && nval != 1) return hipErrorInvalidValue;
+    if ((nval != 9 && nval != 1) || pitch < nh) return hipErrorInvalidValue;
     switch (lx) {
-#define X(N_)                                                                                        \
-    case N_: {                                                                                       \
-        constexpr int V = xprod_V<real, N_>(), T = xprod_T<real, N_>();                              \
-        constexpr int P = N_ / Plan<N_, V>::E;                                                       \
-        const C* tw = twb.stage<C>(N_, V);                                                           \
-        if (!tw) return hipErrorInvalidValue;                                                        \
-        dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1), (unsigned)ngroup);           \
-        if (nval == 1)                                                                               \
-            hipLaunchKernelGGL((xprod_kernel<real, N_, V, T, false, 1>), grid, dim3(2 * P * T), 0,   \
-                               s, (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);    \
-        else if (adjoint)                                                                            \
-            hipLaunchKernelGGL((xprod_kernel<real, N_, V, T, true, 9>), grid, dim3(2 * P * T), 0, s, \
-                               (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);      \
-        else                                                                                         \
-            hipLaunchKernelGGL((xprod_kernel<real, N_, V, T, false, 9>), grid, dim3(2 * P * T), 0,   \
-                               s, (C*)data, nx, ly, nh, table, nyq, tw, group, (int)shared_table);    \
-        return hipGetLastError();                                                                    \
+#define X(N_)                                                                                          \
+    case N_: {                                                                                         \
+        constexpr int V = xprod_V<real, N_>(), T = xprod_T<real, N_>();                                \
+        const C* tw = twb.stage<C>(N_, V);                                                             \
+        if (!tw) return hipErrorInvalidValue;                                                          \
+        if (tile == T)                                                                                 \
+            return launch_xprod_t<real, N_, T, V>(adjoint, (C*)data, nx, ly, nh, pitch, table, nyq, tw, s, \
+                                                  group, ngroup, shared_table, nval);                  \
+        if constexpr (T > 1) {                                                                         \
+            if (tile == T / 2)                                                                         \
+                return launch_xprod_t<real, N_, (T > 1 ? T / 2 : 1), V>(adjoint, (C*)data, nx, ly, nh, pitch, \
+                                                                        table, nyq, tw, s, group, ngroup, \
+                                                                        shared_table, nval);           \
+        }                                                                                              \
+        return hipErrorInvalidValue;                                                                   \
     }
         PIPE_FOR_EACH_N(X)
 #undef X
@@ -621,13 +639,13 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
 
 #define PIPE_INST(real)                                                                               \
     template hipError_t launch_z_r2c<real>(int, const real*, long, int, void*, long, long,             \
-                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool); \
+                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool, int); \
     template hipError_t launch_z_c2r<real>(int, const void*, long, real*, long, int, long, real,       \
-                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool); \
+                                           const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool, int); \
     template hipError_t launch_strided<real>(int, bool, const void*, void*, int, int, long, long, long, \
                                              long, long, long, const TwiddleBank&, hipStream_t,         \
                                              const GroupArgs*, int);                                    \
-    template hipError_t launch_xprod<real>(int, bool, void*, int, int, int, const real*, const real*,  \
+    template hipError_t launch_xprod<real>(int, bool, void*, int, int, int, long, int, const real*, const real*,  \
                                            const TwiddleBank&, hipStream_t, const GroupArgs*, int, bool, int);
 #if PIPE_TU_FP32
 PIPE_INST(float)

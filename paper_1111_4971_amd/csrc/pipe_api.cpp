@@ -185,7 +185,9 @@ struct pipe_plan_s {
     void* table = nullptr;   // tile-blocked spectra, nval values per orbit (see xprod_tile)
     void* nyq = nullptr;     // kz = lz/2 values, nval per orbit (inside the table allocation)
     size_t table_elems = 0, nyq_elems = 0;
-    int tile = 0;            // kz tile of the table layout
+    int tile = 0;            // kz tile of the table layout (and of the fused x pass)
+    int apad = 0;            // schedule: unused slots per row of the y-transformed array
+    int zcap = 2048;         // schedule: block cap of the persistent z passes
     int nval = 9;            // values per orbit: 9 (four terms), 1 (free space: T_cc only)
     int band = -1;           // banded plan: planes kept each side of the z sum (Eq. 18); -1 = 3-D plan
     double g0 = 0;           // free-space plans: G at zero separation
@@ -210,7 +212,7 @@ size_t plan_ws_bytes(const pipe_plan_s* p) {
     const size_t cb = 2 * (size_t)p->rb;
     if (p->band >= 0) return 2 * align256((size_t)p->nx * p->ly * ((p->nz + 1) / 2) * cb);   // A, B: packed pairs
     const size_t a1 = (size_t)p->nx * p->ny * p->nh * cb;
-    const size_t a2 = (size_t)p->nx * p->ly * p->nh * cb;
+    const size_t a2 = (size_t)p->nx * p->ly * a2_pitch(p->nh, p->apad) * cb;
     return align256(a1) + align256(a2);
 }
 
@@ -495,21 +497,26 @@ pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, h
     const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly, nh = p->nh;
     const TwiddleBank& tw = p->ctx->tw;
     if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event");
-    HIP_TRY(launch_z_r2c<real>(nh, (const real*)rho, nz, nz, A1, nh, (long)nx * ny, tw, st), "z forward pass");
+    HIP_TRY(launch_z_r2c<real>(nh, (const real*)rho, nz, nz, A1, nh, (long)nx * ny, tw, st, nullptr, 1, true,
+                               p->zcap),
+            "z forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
     // A2 is (ly, nx, lz/2): ky-major, see passes.hip
-    HIP_TRY(launch_strided<real>(ly, false, A1, A2, ny, ly, nh, (long)nx * nh, nh, (long)ny * nh, nh, nx, tw, st),
+    const long pa = a2_pitch(nh, p->apad);
+    HIP_TRY(launch_strided<real>(ly, false, A1, A2, ny, ly, nh, (long)nx * pa, nh, (long)ny * nh, pa, nx, tw, st),
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
-    HIP_TRY(launch_xprod<real>(p->lx, adjoint, A2, nx, ly, nh, (const real*)p->table, (const real*)p->nyq, tw, st,
-                               nullptr, 1, false, p->nval),
+    HIP_TRY(launch_xprod<real>(p->lx, adjoint, A2, nx, ly, nh, pa, p->tile, (const real*)p->table,
+                               (const real*)p->nyq, tw, st, nullptr, 1, false, p->nval),
             "x pass with spectral product");
     if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event");
-    HIP_TRY(launch_strided<real>(ly, true, A2, A1, ly, ny, (long)nx * nh, nh, nh, nh, (long)ny * nh, nx, tw, st),
+    HIP_TRY(launch_strided<real>(ly, true, A2, A1, ly, ny, (long)nx * pa, nh, nh, pa, (long)ny * nh, nx, tw, st),
             "y inverse pass");
     if (ev) HIP_TRY(hipEventRecord(ev[4], st), "event");
     const real scale = (real)(p->hx * p->hy * p->hz / ((double)p->lx * p->ly * p->lz));
-    HIP_TRY(launch_z_c2r<real>(nh, A1, nh, (real*)phi, nz, nz, (long)nx * ny, scale, tw, st), "z inverse pass");
+    HIP_TRY(launch_z_c2r<real>(nh, A1, nh, (real*)phi, nz, nz, (long)nx * ny, scale, tw, st, nullptr, 1, true,
+                               p->zcap),
+            "z inverse pass");
     if (ev) HIP_TRY(hipEventRecord(ev[5], st), "event");
     return PIPE_OK;
 }
@@ -712,8 +719,95 @@ template <typename real>
 pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al_in, bool al_out, hipStream_t st,
                            bool shared_table = false);
 
-// members = 1: time one solve at a time (latency); members > 1: time one grouped
-// launch of that many concurrent solves (throughput, as in a batch).
+// Times candidate configurations of one mesh (lengths and schedule differ,
+// everything else equal) on scratch buffers with a zero table: pass timing
+// does not depend on the values.  members = 1: one solve at a time
+// (latency); members > 1: one grouped launch of that many solves
+// (throughput, as in a batch).  ms_out[i] = ms per solve of candidate i.
+pipe_status_t time_candidates(std::vector<pipe_plan_s>& cands, int members, hipStream_t st, std::vector<double>& ms_out) {
+    size_t ws_max = 0, tab_max = 0;
+    for (pipe_plan_s& q : cands) {
+        q.nh = q.lz / 2;
+        const size_t orbits = (size_t)(q.lx / 2 + 1) * (q.ly / 2 + 1);
+        q.table_elems = q.nval * orbits * ((q.nh + q.tile - 1) / q.tile) * q.tile;
+        q.nyq_elems = q.nval * orbits;
+        q.ws_bytes = plan_ws_bytes(&q);
+        ws_max = std::max(ws_max, q.ws_bytes);
+        tab_max = std::max(tab_max, (q.table_elems + q.nyq_elems) * q.rb);
+    }
+    const pipe_plan_s& t0 = cands[0];
+    const size_t field = align256((size_t)t0.nx * t0.ny * t0.nz * t0.rb);
+    ws_max = align256(ws_max);
+    Scratch s;
+    void *ws, *tab, *rho, *phi;
+    GroupArgs* dargs = nullptr;
+    HIP_TRY(s.get(&ws, ws_max * members), "tuning allocation");
+    HIP_TRY(s.get(&tab, tab_max), "tuning allocation");
+    HIP_TRY(s.get(&rho, field), "tuning allocation");
+    HIP_TRY(s.get(&phi, field * members), "tuning allocation");
+    if (members > 1) HIP_TRY(s.get((void**)&dargs, sizeof(GroupArgs) * 5 * members), "tuning allocation");
+    HIP_TRY(hipMemsetAsync(tab, 0, tab_max, st), "tuning fill");
+    HIP_TRY(hipMemsetAsync(rho, 0, field, st), "tuning fill");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    ms_out.assign(cands.size(), 1e30);
+    pipe_status_t rs = PIPE_OK;
+    for (size_t i = 0; i < cands.size() && rs == PIPE_OK; ++i) {
+        pipe_plan_s& q = cands[i];
+        q.table = tab;
+        q.nyq = (char*)tab + q.table_elems * q.rb;
+        q.tev.clear(); q.tmax = 0; q.tn = 0;
+        if (members > 1) {
+            std::vector<GroupArgs> a(5 * members);
+            for (int k = 0; k < members; ++k) {
+                char* A1 = (char*)ws + ws_max * k;
+                char* A2 = A1 + align256((size_t)q.nx * q.ny * q.nh * 2 * q.rb);
+                char* ph = (char*)phi + field * k;
+                a[0 * members + k] = {rho, A1, nullptr, nullptr, 0.0};
+                a[1 * members + k] = {A1, A2, nullptr, nullptr, 0.0};
+                a[2 * members + k] = {A2, A2, q.table, q.nyq, 0.0};
+                a[3 * members + k] = {A2, A1, nullptr, nullptr, 0.0};
+                a[4 * members + k] = {A1, ph, nullptr, nullptr, 1.0};
+            }
+            he = hipMemcpyAsync(dargs, a.data(), a.size() * sizeof(GroupArgs), hipMemcpyHostToDevice, st);
+            if (he == hipSuccess) he = hipStreamSynchronize(st);
+            if (he != hipSuccess) {
+                rs = hip_fail(he, "tuning descriptors");
+                break;
+            }
+        }
+        const int reps = 5;
+        for (int r = 0; r < 2 + reps && rs == PIPE_OK; ++r) {
+            if (r == 2) {
+                he = hipEventRecord(e0, st);
+                if (he != hipSuccess) rs = hip_fail(he, "tuning timing");
+            }
+            if (rs != PIPE_OK) break;
+            if (members > 1)
+                rs = q.rb == 8 ? launch_group<double>(&q, dargs, members, true, true, st)
+                               : launch_group<float>(&q, dargs, members, true, true, st);
+            else
+                rs = q.rb == 8 ? run_passes<double>(&q, rho, phi, ws, st, false, nullptr)
+                               : run_passes<float>(&q, rho, phi, ws, st, false, nullptr);
+        }
+        if (rs != PIPE_OK) break;
+        float ms = 0.f;
+        he = hipEventRecord(e1, st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) rs = hip_fail(he, "tuning timing");
+        else ms_out[i] = ms / (reps * members);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rs;
+}
+
 pipe_status_t autotune_lengths(pipe_plan_s* tmpl, int members, hipStream_t st, int* lx, int* ly, int* lz,
                                double* ms_out) {
     const TuneKey key{device_arch(tmpl->device), tmpl->nx, tmpl->ny, tmpl->nz, tmpl->rb, tmpl->nval, members};
@@ -735,108 +829,143 @@ pipe_status_t autotune_lengths(pipe_plan_s* tmpl, int members, hipStream_t st, i
     }
     const std::vector<int> cx = length_candidates(2 * tmpl->nx), cy = length_candidates(2 * tmpl->ny),
                            cz = length_candidates(tmpl->nz);
-    struct Cand { int lx, ly, lz; };
-    std::vector<Cand> cands;
+    std::vector<pipe_plan_s> cands;
     for (int a : cx)
         for (int b : cy)
-            for (int c : cz) cands.push_back({a, b, 2 * c});
+            for (int c : cz) {
+                pipe_plan_s q = *tmpl;
+                q.lx = a; q.ly = b; q.lz = 2 * c;
+                q.tile = xprod_tile(q.lx, q.rb);   // default schedule
+                q.apad = 0; q.zcap = 2048;
+                cands.push_back(q);
+            }
     if (cands.size() == 1) {
         *lx = cands[0].lx; *ly = cands[0].ly; *lz = cands[0].lz;
         *ms_out = 0.0;
         return PIPE_OK;
     }
-    // scratch sized for the largest candidate
-    size_t ws_max = 0, tab_max = 0;
-    std::vector<pipe_plan_s> plans(cands.size(), *tmpl);
-    for (size_t i = 0; i < cands.size(); ++i) {
-        pipe_plan_s& q = plans[i];
-        q.lx = cands[i].lx; q.ly = cands[i].ly; q.lz = cands[i].lz; q.nh = q.lz / 2;
-        q.tile = xprod_tile(q.lx, q.rb);
-        const size_t orbits = (size_t)(q.lx / 2 + 1) * (q.ly / 2 + 1);
-        q.table_elems = q.nval * orbits * ((q.nh + q.tile - 1) / q.tile) * q.tile;
-        q.nyq_elems = q.nval * orbits;
-        q.ws_bytes = plan_ws_bytes(&q);
-        ws_max = std::max(ws_max, q.ws_bytes);
-        tab_max = std::max(tab_max, (q.table_elems + q.nyq_elems) * q.rb);
-    }
-    const size_t field = align256((size_t)tmpl->nx * tmpl->ny * tmpl->nz * tmpl->rb);
-    ws_max = align256(ws_max);
-    Scratch s;
-    void *ws, *tab, *rho, *phi;
-    GroupArgs* dargs = nullptr;
-    HIP_TRY(s.get(&ws, ws_max * members), "autotune allocation");
-    HIP_TRY(s.get(&tab, tab_max), "autotune allocation");
-    HIP_TRY(s.get(&rho, field), "autotune allocation");
-    HIP_TRY(s.get(&phi, field * members), "autotune allocation");
-    if (members > 1) HIP_TRY(s.get((void**)&dargs, sizeof(GroupArgs) * 5 * members), "autotune allocation");
-    HIP_TRY(hipMemsetAsync(tab, 0, tab_max, st), "autotune fill");
-    HIP_TRY(hipMemsetAsync(rho, 0, field, st), "autotune fill");
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
-    hipError_t he = hipEventCreate(&e1);
-    if (he != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return hip_fail(he, "hipEventCreate");
-    }
-    double best = 1e30;
-    size_t bi = 0;
-    pipe_status_t rs = PIPE_OK;
-    for (size_t i = 0; i < cands.size() && rs == PIPE_OK; ++i) {
-        pipe_plan_s& q = plans[i];
-        q.table = tab;
-        q.nyq = (char*)tab + q.table_elems * q.rb;
-        q.tev.clear(); q.tmax = 0; q.tn = 0;
-        if (members > 1) {
-            std::vector<GroupArgs> a(5 * members);
-            for (int k = 0; k < members; ++k) {
-                char* A1 = (char*)ws + ws_max * k;
-                char* A2 = A1 + align256((size_t)q.nx * q.ny * q.nh * 2 * q.rb);
-                char* ph = (char*)phi + field * k;
-                a[0 * members + k] = {rho, A1, nullptr, nullptr, 0.0};
-                a[1 * members + k] = {A1, A2, nullptr, nullptr, 0.0};
-                a[2 * members + k] = {A2, A2, q.table, q.nyq, 0.0};
-                a[3 * members + k] = {A2, A1, nullptr, nullptr, 0.0};
-                a[4 * members + k] = {A1, ph, nullptr, nullptr, 1.0};
-            }
-            he = hipMemcpyAsync(dargs, a.data(), a.size() * sizeof(GroupArgs), hipMemcpyHostToDevice, st);
-            if (he == hipSuccess) he = hipStreamSynchronize(st);
-            if (he != hipSuccess) {
-                rs = hip_fail(he, "autotune descriptors");
-                break;
-            }
-        }
-        const int reps = 5;
-        for (int r = 0; r < 2 + reps && rs == PIPE_OK; ++r) {
-            if (r == 2) he = hipEventRecord(e0, st);
-            if (members > 1)
-                rs = q.rb == 8 ? launch_group<double>(&q, dargs, members, true, true, st)
-                               : launch_group<float>(&q, dargs, members, true, true, st);
-            else
-                rs = q.rb == 8 ? run_passes<double>(&q, rho, phi, ws, st, false, nullptr)
-                               : run_passes<float>(&q, rho, phi, ws, st, false, nullptr);
-        }
-        if (rs != PIPE_OK) break;
-        float ms = 0.f;
-        he = hipEventRecord(e1, st);
-        if (he == hipSuccess) he = hipEventSynchronize(e1);
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he != hipSuccess) rs = hip_fail(he, "autotune timing");
-        else if (ms / (reps * members) < best) {
-            best = ms / (reps * members);
-            bi = i;
-        }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    std::vector<double> ms;
+    pipe_status_t rs = time_candidates(cands, members, st, ms);
     if (rs != PIPE_OK) return rs;
+    const size_t bi = std::min_element(ms.begin(), ms.end()) - ms.begin();
     *lx = cands[bi].lx; *ly = cands[bi].ly; *lz = cands[bi].lz;
-    *ms_out = best;
+    *ms_out = ms[bi];
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const std::array<int, 3> v{*lx, *ly, *lz};
         g_tune[key] = v;
         tune_cache_store(key, v);
     }
+    return PIPE_OK;
+}
+
+// ---------------------------------------------------------------- schedule
+//
+// With the padded lengths fixed, three launch parameters change no result
+// (each output value is computed by the same arithmetic) but move the time a
+// lot depending on the mesh, the precision and the chip's memory interleave:
+// the kz tile of the fused x pass (its widest T or T/2), the row pitch of the
+// y-transformed array (lz/2 plus 0, 16 or 32 unused slots: its rows are read
+// and written at a stride of pitch values by the fused and y passes), and the
+// block cap of the persistent z passes (1024 or 2048).  Each plan times
+// the (tile, pitch) pairs, then the two caps, on scratch buffers, and keeps the
+// fastest; the choice is cached like the lengths.  PIPE_SCHEDULE=fixed uses
+// (widest T, no pad, 2048); PIPE_SCHEDULE=T,pad,cap forces one.
+
+struct SchedKey {
+    std::string arch;
+    int nx, ny, nz, lx, ly, lz, rb, nval, members;
+    bool operator<(const SchedKey& o) const {
+        return std::tie(arch, nx, ny, nz, lx, ly, lz, rb, nval, members) <
+               std::tie(o.arch, o.nx, o.ny, o.nz, o.lx, o.ly, o.lz, o.rb, o.nval, o.members);
+    }
+};
+std::map<SchedKey, std::array<int, 3>> g_sched;
+std::string g_sched_loaded;
+
+bool schedule_ok(int lx, int rb, const std::array<int, 3>& v) {
+    const int T = xprod_tile(lx, rb);
+    return (v[0] == T || (T > 1 && v[0] == T / 2)) && v[1] >= 0 && v[1] <= 256 && v[2] >= 1 && v[2] <= 65536;
+}
+
+void sched_cache_load() {
+    const char* path = getenv("PIPE_TUNE_CACHE");
+    if (!path || g_sched_loaded == path) return;
+    g_sched_loaded = path;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[512], arch[128];
+    while (fgets(line, sizeof line, f)) {
+        SchedKey k;
+        std::array<int, 3> v;
+        if (sscanf(line, "pipe-sched-v1 %127s %d %d %d %d %d %d %d %d %d %d %d %d", arch, &k.nx, &k.ny, &k.nz, &k.lx,
+                   &k.ly, &k.lz, &k.rb, &k.nval, &k.members, &v[0], &v[1], &v[2]) != 13)
+            continue;
+        k.arch = arch;
+        if (schedule_ok(k.lx, k.rb, v)) g_sched[k] = v;
+    }
+    fclose(f);
+}
+
+void sched_cache_store(const SchedKey& k, const std::array<int, 3>& v) {
+    const char* path = getenv("PIPE_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "pipe-sched-v1 %s %d %d %d %d %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.nx, k.ny, k.nz, k.lx, k.ly,
+            k.lz, k.rb, k.nval, k.members, v[0], v[1], v[2]);
+    fclose(f);
+}
+
+// Sets p->tile, p->apad, p->zcap (p's lengths and sizes already set).
+pipe_status_t tune_schedule(pipe_plan_s* p, int members, hipStream_t st) {
+    const int T = xprod_tile(p->lx, p->rb);
+    std::array<int, 3> v{T, 0, 2048};
+    if (const char* f = getenv("PIPE_SCHEDULE")) {
+        if (!strcmp(f, "fixed")) {
+            p->tile = v[0]; p->apad = v[1]; p->zcap = v[2];
+            return PIPE_OK;
+        }
+        if (sscanf(f, "%d,%d,%d", &v[0], &v[1], &v[2]) != 3 || !schedule_ok(p->lx, p->rb, v))
+            return fail(PIPE_ERR_INVALID_ARG, "PIPE_SCHEDULE must be 'fixed' or 'T,pad,cap' with T %d or %d, "
+                        "0 <= pad <= 256, cap >= 1 (got '%s')", T, T / 2, f);
+        p->tile = v[0]; p->apad = v[1]; p->zcap = v[2];
+        return PIPE_OK;
+    }
+    const SchedKey key{device_arch(p->device), p->nx, p->ny, p->nz, p->lx, p->ly, p->lz, p->rb, p->nval, members};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        sched_cache_load();
+        auto it = g_sched.find(key);
+        if (it != g_sched.end()) {
+            p->tile = it->second[0]; p->apad = it->second[1]; p->zcap = it->second[2];
+            return PIPE_OK;
+        }
+    }
+    // (tile, pad) pairs first, then the z cap with the best pair
+    std::vector<pipe_plan_s> cands;
+    for (int t : {T, T / 2}) {
+        if (t < 1 || (t == T / 2 && T == 1)) continue;
+        for (int pad : {0, 16, 32}) {
+            pipe_plan_s q = *p;
+            q.tile = t; q.apad = pad; q.zcap = 2048;
+            cands.push_back(q);
+        }
+    }
+    std::vector<double> ms;
+    pipe_status_t rs = time_candidates(cands, members, st, ms);
+    if (rs != PIPE_OK) return rs;
+    size_t bi = std::min_element(ms.begin(), ms.end()) - ms.begin();
+    v = {cands[bi].tile, cands[bi].apad, 2048};
+    std::vector<pipe_plan_s> caps(1, cands[bi]);
+    caps[0].zcap = 1024;
+    std::vector<double> ms2;
+    if ((rs = time_candidates(caps, members, st, ms2)) != PIPE_OK) return rs;
+    if (ms2[0] < ms[bi]) v[2] = 1024;
+    p->tile = v[0]; p->apad = v[1]; p->zcap = v[2];
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_sched[key] = v;
+    sched_cache_store(key, v);
     return PIPE_OK;
 }
 
@@ -900,7 +1029,12 @@ pipe_status_t create_plan(int nx, int ny, int nz, double hx, double hy, double h
     p->device = dev; p->ctx = ctx;
     p->nval = free_space ? 1 : 9;
     const size_t orbits = (size_t)(lx / 2 + 1) * (ly / 2 + 1);
-    p->tile = xprod_tile(lx, p->rb);
+    // launch schedule (kz tile, row pitch, z block cap); the table layout follows the tile
+    s = tune_schedule(p, tune_members, (hipStream_t)hip_stream);
+    if (s != PIPE_OK) {
+        plan_free(p);
+        return s;
+    }
     const size_t ntiles = (p->nh + p->tile - 1) / p->tile;
     p->table_elems = p->nval * orbits * ntiles * p->tile;
     p->nyq_elems = p->nval * orbits;
@@ -1024,6 +1158,9 @@ pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     out->build_ms = p->build_ms;
     out->tune_ms = p->tune_ms;
     out->band = p->band;
+    out->xtile = p->band >= 0 ? 0 : p->tile;
+    out->apad = p->band >= 0 ? 0 : p->apad;
+    out->zblocks = p->band >= 0 ? 0 : p->zcap;
     return PIPE_OK;
 }
 
@@ -1264,19 +1401,20 @@ pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al
     const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly, nh = p->nh;
     const TwiddleBank& tw = p->ctx->tw;
     const real scale = (real)0;  // taken from each member's GroupArgs
-    HIP_TRY(launch_z_r2c<real>(nh, nullptr, nz, nz, nullptr, nh, (long)nx * ny, tw, st, args, n, al_in),
+    HIP_TRY(launch_z_r2c<real>(nh, nullptr, nz, nz, nullptr, nh, (long)nx * ny, tw, st, args, n, al_in, p->zcap),
             "grouped z forward pass");
-    HIP_TRY(launch_strided<real>(ly, false, nullptr, nullptr, ny, ly, nh, (long)nx * nh, nh, (long)ny * nh, nh, nx,
+    const long pa = a2_pitch(nh, p->apad);
+    HIP_TRY(launch_strided<real>(ly, false, nullptr, nullptr, ny, ly, nh, (long)nx * pa, nh, (long)ny * nh, pa, nx,
                                  tw, st, args + n, n),
             "grouped y forward pass");
-    HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, nullptr, nullptr, tw, st, args + 2 * n, n,
-                               shared_table, p->nval),
+    HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, pa, p->tile, nullptr, nullptr, tw, st,
+                               args + 2 * n, n, shared_table, p->nval),
             "grouped x pass with spectral product");
-    HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, (long)nx * nh, nh, nh, nh, (long)ny * nh, nx,
+    HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, (long)nx * pa, nh, nh, pa, (long)ny * nh, nx,
                                  tw, st, args + 3 * n, n),
             "grouped y inverse pass");
     HIP_TRY(launch_z_c2r<real>(nh, nullptr, nh, nullptr, nz, nz, (long)nx * ny, scale, tw, st, args + 4 * n, n,
-                               al_out),
+                               al_out, p->zcap),
             "grouped z inverse pass");
     return PIPE_OK;
 }
@@ -1303,7 +1441,8 @@ pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_
         for (size_t k = 0; p->band < 0 && k < b->groups.size(); ++k) {
             pipe_plan_s* r = b->groups[k].rep;
             if (!b->groups[k].banded && r->nx == p->nx && r->ny == p->ny && r->nz == p->nz && r->lx == p->lx &&
-                r->ly == p->ly && r->lz == p->lz && r->nval == p->nval)
+                r->ly == p->ly && r->lz == p->lz && r->nval == p->nval && r->tile == p->tile &&
+                r->apad == p->apad && r->zcap == p->zcap)
                 g = (int)k;
         }
         if (g < 0) {

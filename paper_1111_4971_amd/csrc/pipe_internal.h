@@ -69,13 +69,14 @@ struct GroupArgs {
 // Kernel launchers (passes.hip).  All return hipSuccess or the launch error.
 // group (device array of ngroup entries) may be null for a single solve.
 template <typename real>
+// zcap: at most this many blocks in the persistent grid (over all members).
 hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* out, long out_pitch,
                         long nlines, const TwiddleBank& tw, hipStream_t s,
-                        const GroupArgs* group = nullptr, int ngroup = 1, bool aligned = true);
+                        const GroupArgs* group = nullptr, int ngroup = 1, bool aligned = true, int zcap = 2048);
 template <typename real>
 hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long out_pitch, int n_out,
                         long nlines, real scale, const TwiddleBank& tw, hipStream_t s,
-                        const GroupArgs* group = nullptr, int ngroup = 1, bool aligned = true);
+                        const GroupArgs* group = nullptr, int ngroup = 1, bool aligned = true, int zcap = 2048);
 template <typename real>
 hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_in, int n_out,
                           long in_es, long out_es, long ncols, long in_ss, long out_ss, long nslabs,
@@ -85,10 +86,16 @@ template <typename real>
 // shared_table (grouped launches whose members all use one plan's spectra):
 // members of one (kz tile, ky) item run back to back, so the tile is read once.
 // nval: values per orbit in the table, 9 (four terms) or 1 (T_cc only: free space).
-hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh,
+// pitch: row stride of the (ly, nx, pitch) array, >= nh; tile: the kz tile,
+// xprod_tile(lx, .) or half of it (the table must be laid out for that tile).
+hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh, long pitch, int tile,
                         const real* table, const real* nyq, const TwiddleBank& tw, hipStream_t s,
                         const GroupArgs* group = nullptr, int ngroup = 1, bool shared_table = false,
                         int nval = 9);
+
+// Row pitch (complex values) of the y-transformed array A2 = (ly, nx, pitch):
+// lz/2 plus pad unused slots per row (a plan's schedule sets pad).
+inline long a2_pitch(int nh, int pad) { return (long)nh + pad; }
 
 // kz tile width of the fused x pass for padded length lx (0 if unsupported).
 // The Green spectra are stored tile-blocked to match: for orbit row kyo, kz tile

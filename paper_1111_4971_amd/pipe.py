@@ -46,7 +46,8 @@ class PlanInfo(ctypes.Structure):
                 ("norm", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("spectra_bytes", ctypes.c_size_t),
                 ("model_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double * 5),
-                ("build_ms", ctypes.c_double), ("tune_ms", ctypes.c_double), ("band", ctypes.c_int)]
+                ("build_ms", ctypes.c_double), ("tune_ms", ctypes.c_double), ("band", ctypes.c_int),
+                ("xtile", ctypes.c_int), ("apad", ctypes.c_int), ("zblocks", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
