@@ -283,9 +283,20 @@ def band_leg(pipe, torch, steps=50, tol=1e-6):
                 e = r.setdefault("N_auto" if nb == "auto" else "N%d" % nb, {})
                 e["N"] = plan.band
                 e[prec] = {"ms_per_solve": ms, "kernel_ms": pm[:3], "speedup_over_full": ms_full / ms,
+                           "build_time_ratio_3d_over_banded": plan.info.band_speedup,
                            "x_pass_GBps": pb[1] / (pm[1] * 1e-3) / 1e9,
                            "rel_max_vs_full_fp64": float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))}
                 plan.close()
+                if nb == "auto":
+                    # the same request with band_fastest: the faster of the banded and 3-D plans
+                    plan = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind,
+                                          precision=prec, mx=wl.mx, my=wl.my, band=nb, band_tol=tol,
+                                          band_fastest=True)
+                    ms_f, _, _ = timed(plan, x)
+                    f = r.setdefault("N_auto_fastest", {})
+                    f[prec] = {"returned": "banded N=%d" % plan.band if plan.band is not None else "3-D",
+                               "ms_per_solve": ms_f, "speedup_over_full": ms_full / ms_f}
+                    plan.close()
         res[key] = r
     return res
 
@@ -483,7 +494,7 @@ def main():
             if not isinstance(v, dict):
                 continue
             for nm, e in v.items():
-                if nm.startswith("N"):
+                if nm.startswith("N") and "N" in e:
                     log("[bench] banded %s %s (N=%d): %.2fx (FP32) / %.2fx (FP64) the full solve's speed, "
                         "max rel deviation %.1e" % (k, nm, e["N"], e["fp32"]["speedup_over_full"],
                                                     e["fp64"]["speedup_over_full"], e["fp64"]["rel_max_vs_full_fp64"]))

@@ -70,7 +70,8 @@ enum {
     PIPE_PREC_FP32 = 0x10,  /* transforms, products, rho and phi in float                 */
     PIPE_KEEP_GREEN = 0x100,/* keep the on-mesh Green table for pipe_plan_green_table     */
     PIPE_AUTOTUNE = 0x200,  /* time the candidate padded lengths, keep the fastest        */
-    PIPE_AUTOTUNE_BATCH = 0x400 /* as PIPE_AUTOTUNE, timing 16 concurrent solves (batches) */
+    PIPE_AUTOTUNE_BATCH = 0x400, /* as PIPE_AUTOTUNE, timing 16 concurrent solves (batches) */
+    PIPE_BAND_FASTEST = 0x800    /* pipe_green_plan_banded: return the 3-D plan if it is faster */
 };
 
 typedef struct pipe_plan_info {
@@ -92,6 +93,9 @@ typedef struct pipe_plan_info {
                              /* (0 = taken from the cache; -1 = not tuned)                */
     int band;                /* pipe_green_plan_banded: planes kept each side (N of Eq. 18);*/
                              /* -1 for the full 3-D plans                                 */
+    double band_speedup;     /* pipe_green_plan_banded: measured time of the mesh's 3-D     */
+                             /* solve over the banded solve's (> 1: banded is faster);      */
+                             /* also on a 3-D plan returned for PIPE_BAND_FASTEST; else 0  */
     int xtile;               /* launch schedule (3-D plans; 0 for banded plans): kz tile of */
     int apad;                /* the x pass, unused slots per row of the y-transformed array,*/
     int zblocks;             /* block cap of the z passes; none of them changes a result   */
@@ -183,7 +187,13 @@ pipe_status_t pipe_green_plan_region(int nx, int ny, int nz, double hx, double h
  *   B(d) <= tol * B(0) for every plane distance N < d < nz,
  * B(d) = sum over the kept modes (m, n) of |the mode's z factor at d hz|
  * times the Eq. 9 prefactor, an upper bound on |R| over the cross-section at
- * that distance.  tol must then be in (0, 1).  Other arguments, ownership and
+ * that distance.  tol must then be in (0, 1).  The build times one banded
+ * solve against one solve of the 3-D plan the mesh would get from
+ * pipe_green_plan_region (on scratch buffers) and reports the ratio in
+ * info.band_speedup (below 1: the banded plan is the slower one, which happens
+ * once 2N + 1 plane products cost more than the z transforms they replace).
+ * With PIPE_BAND_FASTEST in kind, the call then returns the 3-D plan (exact,
+ * info.band = -1) whenever it is the faster.  Other arguments, ownership and
  * errors as pipe_green_plan_region; PIPE_AUTOTUNE flags are ignored.  In a
  * batch (pipe_batch_create) a banded plan runs its own three passes inside the
  * captured graph rather than in grouped launches.

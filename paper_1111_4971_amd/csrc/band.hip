@@ -36,14 +36,16 @@ namespace pipe {
 // Forward: real in, complex out (all ly rows, zero-padded beyond n_in).
 // Inverse: complex in, real out (rows e < n_out), times scale.
 template <typename real, int N, int T, bool INV>
-__global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N>::E) * T)) * (N / Plan<N>::E) * T)
+__global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N, strided_V<real, N>()>::E) * T)) *
+                             (N / Plan<N, strided_V<real, N>()>::E) * T)
 void strided_pair_kernel(const void* in, void* out, int n_in, int n_out, long r_es, long c_es, long ncols,
                          long r_ss, long c_ss, long nslabs, int nz, real scale, const cplx<real>* __restrict__ tw) {
     using C = cplx<real>;
-    constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
+    using PL = Plan<N, strided_V<real, N>()>;
+    constexpr int P = N / PL::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -55,7 +57,7 @@ void strided_pair_kernel(const void* in, void* out, int n_in, int n_out, long r_
     const long roff = active ? slab * r_ss + 2 * col : 0;
     const long coff = active ? slab * c_ss + col : 0;
     LdsCol<C, T> view{lds + s * N * T + c};
-    fft_line<Plan<N>, INV, false>(
+    fft_line<PL, INV, false>(
         t, tw,
         [&](int e) -> C {
             if (!(active && e < n_in)) return cmake<C>(0, 0);
@@ -525,14 +527,16 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
 // y pass with real input (forward: rho -> complex) or real output (inverse:
 // complex -> scaled real part), one plane per column (the Green arrangements).
 template <typename real, int N, int T, bool INV>
-__global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N>::E) * T)) * (N / Plan<N>::E) * T)
+__global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N, strided_V<real, N>()>::E) * T)) *
+                             (N / Plan<N, strided_V<real, N>()>::E) * T)
 void strided_real_kernel(const void* in, void* out, int n_in, int n_out, long in_es, long out_es, long ncols,
                          long in_ss, long out_ss, long nslabs, real scale, const cplx<real>* __restrict__ tw) {
     using C = cplx<real>;
-    constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
+    using PL = Plan<N, strided_V<real, N>()>;
+    constexpr int P = N / PL::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -540,7 +544,7 @@ void strided_real_kernel(const void* in, void* out, int n_in, int n_out, long in
     const long ioff = active ? slab * in_ss + col : 0;
     const long ooff = active ? slab * out_ss + col : 0;
     LdsCol<C, T> view{lds + s * N * T + c};
-    fft_line<Plan<N>, INV, false>(
+    fft_line<PL, INV, false>(
         t, tw,
         [&](int e) -> C {
             if (!(active && e < n_in)) return cmake<C>(0, 0);
@@ -611,14 +615,15 @@ hipError_t launch_strided_pair(int n, bool inverse, const void* in, void* out, i
                                long c_es, long r_ss, long c_ss, long nslabs, int nz, real scale,
                                const TwiddleBank& twb, hipStream_t s) {
     using C = cplx<real>;
-    const C* tw = twb.stage<C>(n);
     const long ncols = (nz + 1) / 2;
-    if (!tw || nz < 1 || nslabs <= 0) return hipErrorInvalidValue;
+    if (nz < 1 || nslabs <= 0) return hipErrorInvalidValue;
     switch (n) {
 #define X(N_)                                                                                        \
     case N_: {                                                                                       \
-        constexpr int T = strided_T<real, N_>();                                                     \
-        constexpr int P = N_ / Plan<N_>::E, SPW = ce_max(1, 256 / (P * T));                          \
+        constexpr int T = strided_T<real, N_>(), V = strided_V<real, N_>();                          \
+        constexpr int P = N_ / Plan<N_, V>::E, SPW = ce_max(1, 256 / (P * T));                       \
+        const C* tw = twb.stage<C>(N_, V);                                                           \
+        if (!tw) return hipErrorInvalidValue;                                                        \
         dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW));            \
         if (inverse)                                                                                 \
             hipLaunchKernelGGL((strided_pair_kernel<real, N_, T, true>), grid, dim3(SPW * P * T), 0, \
@@ -641,13 +646,14 @@ hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, i
                                long out_es, long ncols, long in_ss, long out_ss, long nslabs, real scale,
                                const TwiddleBank& twb, hipStream_t s) {
     using C = cplx<real>;
-    const C* tw = twb.stage<C>(n);
-    if (!tw || ncols <= 0 || nslabs <= 0) return hipErrorInvalidValue;
+    if (ncols <= 0 || nslabs <= 0) return hipErrorInvalidValue;
     switch (n) {
 #define X(N_)                                                                                        \
     case N_: {                                                                                       \
-        constexpr int T = strided_T<real, N_>();                                                     \
-        constexpr int P = N_ / Plan<N_>::E, SPW = ce_max(1, 256 / (P * T));                          \
+        constexpr int T = strided_T<real, N_>(), V = strided_V<real, N_>();                          \
+        constexpr int P = N_ / Plan<N_, V>::E, SPW = ce_max(1, 256 / (P * T));                       \
+        const C* tw = twb.stage<C>(N_, V);                                                           \
+        if (!tw) return hipErrorInvalidValue;                                                        \
         dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW));            \
         if (inverse)                                                                                 \
             hipLaunchKernelGGL((strided_real_kernel<real, N_, T, true>), grid, dim3(SPW * P * T), 0, \

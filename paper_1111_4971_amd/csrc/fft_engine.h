@@ -227,14 +227,53 @@ PIPE_PLAN(768, 24, 3, 8, 8, 4)
 PIPE_PLAN(864, 24, 3, 3, 3, 8, 4)
 PIPE_PLAN(972, 18, 9, 9, 3, 2, 2)
 PIPE_PLAN(1024, 16, 16, 16, 4)
-// variants: twice the threads per line (half the values per thread)
-PIPE_PLAN_V(256, 1, 8, 8, 8, 4)
+// Variant 2: at most 12 values per thread (8 for powers of two), for kernels
+// whose registers or LDS would otherwise limit them to one or two waves per
+// SIMD (z passes holding two line groups, FP64 passes); more threads per line
+// and usually one more stage.
+PIPE_PLAN_V(16, 2, 8, 4, 4)
+PIPE_PLAN_V(24, 2, 12, 3, 4, 2)
+PIPE_PLAN_V(54, 2, 6, 3, 3, 3, 2)
+PIPE_PLAN_V(72, 2, 12, 3, 3, 4, 2)
+PIPE_PLAN_V(96, 2, 12, 3, 4, 4, 2)
+PIPE_PLAN_V(128, 2, 8, 8, 4, 4)
+PIPE_PLAN_V(162, 2, 6, 3, 3, 3, 3, 2)
+PIPE_PLAN_V(192, 2, 12, 3, 4, 4, 4)
+PIPE_PLAN_V(216, 2, 12, 3, 3, 3, 4, 2)
+PIPE_PLAN_V(256, 2, 8, 8, 8, 4)
+PIPE_PLAN_V(288, 2, 12, 3, 3, 4, 4, 2)
+PIPE_PLAN_V(324, 2, 12, 3, 3, 3, 3, 4)
+PIPE_PLAN_V(384, 2, 12, 3, 4, 4, 4, 2)
+PIPE_PLAN_V(432, 2, 12, 3, 3, 3, 4, 4)
+PIPE_PLAN_V(486, 2, 6, 3, 3, 3, 3, 3, 2)
+PIPE_PLAN_V(576, 2, 12, 3, 3, 4, 4, 4)
+PIPE_PLAN_V(648, 2, 12, 3, 3, 3, 3, 4, 2)
+PIPE_PLAN_V(768, 2, 12, 3, 4, 4, 4, 4)
+PIPE_PLAN_V(864, 2, 12, 3, 3, 3, 4, 4, 2)
+PIPE_PLAN_V(972, 2, 12, 3, 3, 3, 3, 3, 4)
+PIPE_PLAN_V(1024, 2, 8, 8, 8, 4, 4)
 #undef PIPE_PLAN
 #undef PIPE_PLAN_V
 
 // The (length, variant) pairs that exist beyond the defaults; the twiddle bank
 // holds a stage table for each.
-#define PIPE_FOR_EACH_VARIANT(X) X(256, 1)
+#define PIPE_FOR_EACH_VARIANT(X)                                                                     \
+    X(16, 2) X(24, 2) X(54, 2) X(72, 2) X(96, 2) X(128, 2) X(162, 2) X(192, 2) X(216, 2) X(256, 2)  \
+    X(288, 2) X(324, 2) X(384, 2) X(432, 2) X(486, 2) X(576, 2) X(648, 2) X(768, 2) X(864, 2)      \
+    X(972, 2) X(1024, 2)
+
+// Whether Plan<N, V> is defined.
+template <int N, int V, typename = void> struct plan_exists { static constexpr bool value = false; };
+template <int N, int V> struct plan_exists<N, V, decltype((void)Plan<N, V>::E)> {
+    static constexpr bool value = true;
+};
+
+// The plan a kernel uses for length N: variant 2 when the default plan holds
+// more than emax values per thread and the variant exists, else the default.
+template <int N> constexpr int narrow_variant(int emax) {
+    if constexpr (plan_exists<N, 2>::value) return Plan<N>::E > emax ? 2 : 0;
+    return 0;
+}
 
 template <class PL> __host__ __device__ constexpr int plan_ns(int s) {
     int ns = 1;

@@ -54,11 +54,18 @@ constexpr int ce_max(int a, int b) { return a > b ? a : b; }
     X(8) X(12) X(16) X(24) X(32) X(36) X(48) X(64) X(72) X(96) X(108) X(128) X(144) X(192) X(216)       \
     X(256) X(288) X(384) X(432) X(512) X(576) X(768) X(864) X(1024)
 
+// Plan of the y passes: FP64 takes the narrow variant where the default plan
+// holds more than 8 values per thread (a block of ~256 threads then needs
+// 256 E complex values of LDS).
+template <typename real, int N> constexpr int strided_V() {
+    return narrow_variant<N>(sizeof(real) == 8 ? 8 : 24);
+}
 // Column tile of the y passes: PIPE_STRIDED_TMAX columns per row segment,
-// halved until the block's LDS (N x T complex) fits in PIPE_LDS_CAP.
+// halved until the block's LDS (slabs x N x T complex) fits in PIPE_LDS_CAP.
 template <typename real, int N> constexpr int strided_T() {
+    constexpr int P = N / Plan<N, strided_V<real, N>()>::E;
     int t = PIPE_STRIDED_TMAX;
-    while (t > 1 && N * t * (int)sizeof(real) * 2 > PIPE_LDS_CAP) t /= 2;
+    while (t > 1 && ce_max(1, 256 / (P * t)) * N * t * (int)sizeof(real) * 2 > PIPE_LDS_CAP) t /= 2;
     return t;
 }
 
@@ -105,13 +112,18 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned p, unsigned total) {
 #ifndef PIPE_Z_WAVE_SYNC
 #define PIPE_Z_WAVE_SYNC 1
 #endif
-template <int NH> constexpr Sync z_sync() {
-    constexpr int P = NH / Plan<NH>::E;
+// Plan of the z passes: each thread holds two line groups (current and
+// prefetched), so plans with more than 12 values per thread (8 in FP64) take
+// the narrow variant.
+template <typename real, int NH> constexpr int z_V() { return narrow_variant<NH>(sizeof(real) == 8 ? 8 : 12); }
+
+template <typename real, int NH> constexpr Sync z_sync() {
+    constexpr int P = NH / Plan<NH, z_V<real, NH>()>::E;
     return (PIPE_Z_WAVE_SYNC && P <= 64 && 64 % P == 0) ? Sync::WAVE : Sync::BLOCK;
 }
 
 template <typename real, int NH> constexpr int z_lines() {
-    int l = ce_max(1, PIPE_Z_THREADS / (NH / Plan<NH>::E));
+    int l = ce_max(1, PIPE_Z_THREADS / (NH / Plan<NH, z_V<real, NH>()>::E));
     while (l > 1 && l * (NH + NH / 16 + 1) * 2 * (int)sizeof(real) > PIPE_LDS_CAP) l /= 2;
     return l;
 }

@@ -105,7 +105,7 @@ int fft_stage_exponents(int n, int variant, int* m_out) {
 //   X[0] = Re Z[0] + Im Z[0],  X[NH] = Re Z[0] - Im Z[0]  (stored as slot 0 = (X[0], X[NH])).
 // vec2: n_in and in_pitch even and `in` 2-element aligned, so x[2m], x[2m+1] load as one pair.
 template <typename real, int NH>
-__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH>::E)))
+__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH, z_V<real, NH>()>::E)))
 void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long out_pitch, long nlines,
                   const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2,
                   const GroupArgs* __restrict__ group) {
@@ -114,13 +114,14 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
         in = (const real*)group[blockIdx.z].in;
         out = (C*)group[blockIdx.z].out;
     }
-    constexpr int E = Plan<NH>::E, P = NH / E, LPW = z_lines<real, NH>();
-    constexpr int R0 = Plan<NH>::radix(0);
+    using PL = Plan<NH, z_V<real, NH>()>;
+    constexpr int E = PL::E, P = NH / E, LPW = z_lines<real, NH>();
+    constexpr int R0 = PL::radix(0);
     constexpr int PADN = NH + NH / 16 + 1;
-    constexpr Sync ZS = z_sync<NH>();
+    constexpr Sync ZS = z_sync<real, NH>();
     __shared__ C lds[LPW * PADN];
     __shared__ C s_tw[NH], s_tw2[NH];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<NH>>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
     const int t = threadIdx.x % P, l = threadIdx.x / P;
@@ -132,7 +133,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     auto load = [&](C* v, long line) {
         const bool active = line < nlines;
         const gptr<const real> src = gin + (active ? line : 0) * in_pitch;
-        stage_load<Plan<NH>, R0>(v, t, [&](int m) -> C {
+        stage_load<PL, R0>(v, t, [&](int m) -> C {
             if (vec2) {
                 if (active && 2 * m < n_in) return reinterpret_cast<gptr<const C>>(src)[m];
                 return cmake<C>(0, 0);
@@ -151,7 +152,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     for (; g < ngroups; g += gridDim.x) {
         const long gn = g + gridDim.x;
         if (gn < ngroups) load(nxt, gn * LPW + l);
-        fft_line_regs<Plan<NH>, false, ZS>(cur, t, tw, [&](int k, C v) { view.set(k, v); }, view);
+        fft_line_regs<PL, false, ZS>(cur, t, tw, [&](int k, C v) { view.set(k, v); }, view);
         line_sync<ZS>();
         const long line = g * LPW + l;
         if (line < nlines) {
@@ -181,7 +182,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
 // then x[2m] + i x[2m+1] = IDFT_NH(Z')[m].
 // vec2: n_out and out_pitch even and `out` 2-element aligned (pairs stored at once).
 template <typename real, int NH>
-__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH>::E)))
+__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH, z_V<real, NH>()>::E)))
 void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch, int n_out, long nlines,
                   real scale, const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2,
                   const GroupArgs* __restrict__ group) {
@@ -191,12 +192,13 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
         out = (real*)group[blockIdx.z].out;
         scale = (real)group[blockIdx.z].scale;
     }
-    constexpr int E = Plan<NH>::E, P = NH / E, LPW = z_lines<real, NH>();
+    using PL = Plan<NH, z_V<real, NH>()>;
+    constexpr int E = PL::E, P = NH / E, LPW = z_lines<real, NH>();
     constexpr int PADN = NH + NH / 16 + 1;
-    constexpr Sync ZS = z_sync<NH>();
+    constexpr Sync ZS = z_sync<real, NH>();
     __shared__ C lds[LPW * PADN];
     __shared__ C s_tw[NH], s_tw2[NH];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<NH>>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
     const int t = threadIdx.x % P, l = threadIdx.x / P;
@@ -226,7 +228,7 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
         const long line = g * LPW + l;
         const bool active = line < nlines;
         const gptr<real> dst = gout + (active ? line : 0) * out_pitch;
-        fft_line<Plan<NH>, true, true, ZS>(
+        fft_line<PL, true, true, ZS>(
             t, tw,
             [&](int k) -> C {
                 const C xk = view.get(k);
@@ -255,7 +257,8 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
 // P2 / P4 / spectra y and x passes: lines along a strided dimension.
 // Block = T contiguous columns x P threads per line x SPW slabs.
 template <typename real, int N, int T, bool INV>
-__global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N>::E) * T)) * (N / Plan<N>::E) * T)
+__global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N, strided_V<real, N>()>::E) * T)) *
+                             (N / Plan<N, strided_V<real, N>()>::E) * T)
 void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, long in_es, long out_es,
                     long ncols, long in_ss, long out_ss, long nslabs, const cplx<real>* __restrict__ tw,
                     const GroupArgs* __restrict__ group) {
@@ -264,10 +267,11 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
         in = (const C*)group[blockIdx.z].in;
         out = (C*)group[blockIdx.z].out;
     }
-    constexpr int P = N / Plan<N>::E, SPW = ce_max(1, 256 / (P * T));
+    using PL = Plan<N, strided_V<real, N>()>;
+    constexpr int P = N / PL::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
     __shared__ C s_tw[N];
-    tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
+    tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
     const long col = (long)blockIdx.x * T + c;
@@ -275,7 +279,7 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
     const gptr<const C> src = to_global(in) + (active ? slab * in_ss + col : 0);
     const gptr<C> dst = to_global(out) + (active ? slab * out_ss + col : 0);
     LdsCol<C, T> view{lds + s * N * T + c};
-    fft_line<Plan<N>, INV, false>(
+    fft_line<PL, INV, false>(
         t, tw,
         [&](int e) -> C {
             if (active && e < n_in) return src[e * in_es];
@@ -481,15 +485,16 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
                         long nlines, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group, int ngroup,
                         bool aligned, int zcap) {
     using C = cplx<real>;
-    const C* tw = twb.stage<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
-    if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
+    if (!tw2 || nlines <= 0) return hipErrorInvalidValue;
     const int vec2 = (n_in % 2 == 0) && (in_pitch % 2 == 0) && aligned &&
                      (group || (uintptr_t)in % (2 * sizeof(real)) == 0);
     switch (nh) {
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
-        constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
+        constexpr int V = z_V<real, N_>(), P = N_ / Plan<N_, V>::E, LPW = z_lines<real, N_>();       \
+        const C* tw = twb.stage<C>(N_, V);                                                      \
+        if (!tw) return hipErrorInvalidValue;                                                   \
         dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup, zcap), 1, (unsigned)ngroup);               \
         hipLaunchKernelGGL((z_r2c_kernel<real, N_>), grid, dim3(LPW * P), 0, s, in, in_pitch,   \
                            n_in, (C*)out, out_pitch, nlines, tw, tw2, vec2, group);             \
@@ -506,15 +511,16 @@ hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long o
                         long nlines, real scale, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
                         int ngroup, bool aligned, int zcap) {
     using C = cplx<real>;
-    const C* tw = twb.stage<C>(nh);
     const C* tw2 = twb.get<C>(2 * nh);
-    if (!tw || !tw2 || nlines <= 0) return hipErrorInvalidValue;
+    if (!tw2 || nlines <= 0) return hipErrorInvalidValue;
     const int vec2 = (n_out % 2 == 0) && (out_pitch % 2 == 0) && aligned &&
                      (group || (uintptr_t)out % (2 * sizeof(real)) == 0);
     switch (nh) {
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
-        constexpr int P = N_ / Plan<N_>::E, LPW = z_lines<real, N_>();                                \
+        constexpr int V = z_V<real, N_>(), P = N_ / Plan<N_, V>::E, LPW = z_lines<real, N_>();       \
+        const C* tw = twb.stage<C>(N_, V);                                                      \
+        if (!tw) return hipErrorInvalidValue;                                                   \
         dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup, zcap), 1, (unsigned)ngroup);               \
         hipLaunchKernelGGL((z_c2r_kernel<real, N_>), grid, dim3(LPW * P), 0, s, (const C*)in,   \
                            in_pitch, out, out_pitch, n_out, nlines, scale, tw, tw2, vec2, group); \
@@ -531,13 +537,14 @@ hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_
                           long out_es, long ncols, long in_ss, long out_ss, long nslabs,
                           const TwiddleBank& twb, hipStream_t s, const GroupArgs* group, int ngroup) {
     using C = cplx<real>;
-    const C* tw = twb.stage<C>(n);
-    if (!tw || ncols <= 0 || nslabs <= 0) return hipErrorInvalidValue;
+    if (ncols <= 0 || nslabs <= 0) return hipErrorInvalidValue;
     switch (n) {
 #define X(N_)                                                                                      \
     case N_: {                                                                                     \
-        constexpr int T = strided_T<real, N_>();                                                   \
-        constexpr int P = N_ / Plan<N_>::E, SPW = ce_max(1, 256 / (P * T));                        \
+        constexpr int T = strided_T<real, N_>(), V = strided_V<real, N_>();                        \
+        constexpr int P = N_ / Plan<N_, V>::E, SPW = ce_max(1, 256 / (P * T));                     \
+        const C* tw = twb.stage<C>(N_, V);                                                         \
+        if (!tw) return hipErrorInvalidValue;                                                      \
         dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW),           \
                   (unsigned)ngroup);                                                               \
         if (inverse)                                                                               \
@@ -556,16 +563,10 @@ hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_
     return hipErrorInvalidValue;
 }
 
-// Length plan of the fused x pass: the variant with fewer values per thread
-// where one exists for FP64 (twice the threads on the same LDS tile, and
-// fewer registers per thread), else the default.
-#ifndef PIPE_XPROD_F64_VARIANT
-#define PIPE_XPROD_F64_VARIANT 1
-#endif
-template <typename real, int N> constexpr int xprod_V() {
-    if constexpr (sizeof(real) == 8 && PIPE_XPROD_F64_VARIANT && N == 256) return 1;
-    return 0;
-}
+// Length plan of the fused x pass: the narrow variant where the default plan
+// holds more than 16 values per thread (8 in FP64): more threads on the same
+// LDS tile and fewer registers per thread.
+template <typename real, int N> constexpr int xprod_V() { return narrow_variant<N>(sizeof(real) == 8 ? 8 : 16); }
 
 // kz tile of the fused x pass: 2 lines x lx x T complex values in LDS.
 template <typename real, int N> constexpr int xprod_T() {

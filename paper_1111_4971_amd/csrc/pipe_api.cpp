@@ -192,6 +192,7 @@ struct pipe_plan_s {
     int band = -1;           // banded plan: planes kept each side of the z sum (Eq. 18); -1 = 3-D plan
     double g0 = 0;           // free-space plans: G at zero separation
     bool band_single = false; // banded x pass: single-window kernel (else chunked), chosen by timing
+    double band_speedup = 0;  // banded build: measured 3-D solve time / banded solve time
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
     double tune_ms = -1;     // autotuner: best candidate's time per solve, 0 if cached, -1 if not tuned
@@ -1079,12 +1080,72 @@ pipe_status_t pipe_green_plan_ex(int nx, int ny, int nz, double hx, double hy, d
     return pipe_green_plan_region(nx, ny, nz, hx, hy, hz, a, b, 0.0, 0.0, kind, mx, my, lx, ly, lz, hip_stream, out);
 }
 
+namespace {
+// ms per banded solve of p, on scratch buffers (timing does not depend on values).
+pipe_status_t time_banded(pipe_plan_s* p, hipStream_t st, double* ms_out) {
+    Scratch s;
+    void *ws, *rho, *phi;
+    const size_t field = align256((size_t)p->nx * p->ny * p->nz * p->rb);
+    HIP_TRY(s.get(&ws, p->ws_bytes), "band timing allocation");
+    HIP_TRY(s.get(&rho, field), "band timing allocation");
+    HIP_TRY(s.get(&phi, field), "band timing allocation");
+    HIP_TRY(hipMemsetAsync(rho, 0, field, st), "band timing fill");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    pipe_status_t rs = PIPE_OK;
+    const int reps = 5;
+    for (int r = 0; r < 2 + reps && rs == PIPE_OK; ++r) {
+        if (r == 2 && (he = hipEventRecord(e0, st)) != hipSuccess) rs = hip_fail(he, "band timing");
+        if (rs == PIPE_OK)
+            rs = p->rb == 8 ? run_band_passes<double>(p, rho, phi, ws, st, false, nullptr)
+                            : run_band_passes<float>(p, rho, phi, ws, st, false, nullptr);
+    }
+    float ms = 0.f;
+    if (rs == PIPE_OK) {
+        he = hipEventRecord(e1, st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) rs = hip_fail(he, "band timing");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_out = ms / reps;
+    return rs;
+}
+
+// ms per solve of the 3-D plan the same mesh would get by default (default
+// lengths and schedule), on scratch buffers.
+pipe_status_t time_full_for(const pipe_plan_s* b, hipStream_t st, double* ms_out) {
+    int lx = 0, ly = 0, lz = 0;
+    pipe_status_t s = validate(b->nx, b->ny, b->nz, b->hx, b->hy, b->hz, b->a, b->b, b->x0, b->y0, b->kind, b->mx,
+                               b->my, &lx, &ly, &lz);
+    if (s != PIPE_OK) return s;
+    std::vector<pipe_plan_s> c(1);
+    pipe_plan_s& q = c[0];
+    q.nx = b->nx; q.ny = b->ny; q.nz = b->nz; q.lx = lx; q.ly = ly; q.lz = lz; q.nh = lz / 2;
+    q.mx = b->mx; q.my = b->my; q.kind = b->kind; q.rb = b->rb;
+    q.hx = b->hx; q.hy = b->hy; q.hz = b->hz; q.a = b->a; q.b = b->b; q.x0 = b->x0; q.y0 = b->y0;
+    q.device = b->device; q.ctx = b->ctx; q.nval = 9;
+    q.tile = xprod_tile(lx, q.rb); q.apad = 0; q.zcap = 2048;
+    std::vector<double> ms;
+    if ((s = time_candidates(c, 1, st, ms)) != PIPE_OK) return s;
+    *ms_out = ms[0];
+    return PIPE_OK;
+}
+}  // namespace
+
 pipe_status_t pipe_green_plan_banded(int nx, int ny, int nz, double hx, double hy, double hz, double a, double b,
                                      double x0, double y0, int kind, int mx, int my, int lx, int ly, int nband,
                                      double tol, void* hip_stream, pipe_plan_t* out) {
     if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");
     *out = nullptr;
     const bool keep = (kind & PIPE_KEEP_GREEN) != 0;
+    const bool fastest = (kind & PIPE_BAND_FASTEST) != 0;
     kind &= 0xff;
     // the banded x pass takes a subset of the transform lengths
     if (lx == 0 && nx >= 1 && nx <= 512) {
@@ -1128,6 +1189,27 @@ pipe_status_t pipe_green_plan_banded(int nx, int ny, int nz, double hx, double h
             return s;
         }
     }
+    // time the banded solve against the 3-D solve of the same mesh
+    double t_band = 0, t_full = 0;
+    s = time_banded(p, (hipStream_t)hip_stream, &t_band);
+    if (s == PIPE_OK) s = time_full_for(p, (hipStream_t)hip_stream, &t_full);
+    if (s != PIPE_OK) {
+        plan_free(p);
+        return s;
+    }
+    p->band_speedup = t_band > 0 ? t_full / t_band : 0;
+    if (fastest && t_full < t_band) {
+        // the full z sum is exact and faster here: return the 3-D plan instead
+        pipe_plan_t full = nullptr;
+        s = create_plan(nx, ny, nz, hx, hy, hz, a, b, x0, y0, kind | (keep ? PIPE_KEEP_GREEN : 0), mx, my, 0, 0, 0,
+                        false, 0.0, hip_stream, &full);
+        const double sp = p->band_speedup;
+        plan_free(p);
+        if (s != PIPE_OK) return s;
+        full->band_speedup = sp;
+        *out = full;
+        return PIPE_OK;
+    }
     p->tune_ms = -1.0;
     p->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     reg_add(p);
@@ -1158,6 +1240,7 @@ pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     out->build_ms = p->build_ms;
     out->tune_ms = p->tune_ms;
     out->band = p->band;
+    out->band_speedup = p->band_speedup;
     out->xtile = p->band >= 0 ? 0 : p->tile;
     out->apad = p->band >= 0 ? 0 : p->apad;
     out->zblocks = p->band >= 0 ? 0 : p->zcap;

@@ -31,7 +31,9 @@ inline bool band_length_ok(int n) {
 struct PlanVariant {
     int n, v;
 };
-constexpr PlanVariant kPlanVariants[] = {{256, 1}};
+constexpr PlanVariant kPlanVariants[] = {{16, 2},  {24, 2},  {54, 2},  {72, 2},  {96, 2},  {128, 2}, {162, 2},
+                                         {192, 2}, {216, 2}, {256, 2}, {288, 2}, {324, 2}, {384, 2}, {432, 2},
+                                         {486, 2}, {576, 2}, {648, 2}, {768, 2}, {864, 2}, {972, 2}, {1024, 2}};
 constexpr int kNumVariants = sizeof(kPlanVariants) / sizeof(PlanVariant);
 
 // Per-device twiddle bank: for every FFT length N the natural tables

@@ -24,6 +24,7 @@ PREC_FP64, PREC_FP32 = 0x00, 0x10
 KEEP_GREEN = 0x100
 AUTOTUNE = 0x200
 AUTOTUNE_BATCH = 0x400
+BAND_FASTEST = 0x800
 
 STATUS = {0: "PIPE_OK", 1: "PIPE_ERR_INVALID_ARG", 2: "PIPE_ERR_UNSUPPORTED_SIZE", 3: "PIPE_ERR_OUT_OF_MEMORY",
           4: "PIPE_ERR_NO_DEVICE", 5: "PIPE_ERR_HIP", 6: "PIPE_ERR_ALIASING"}
@@ -47,6 +48,7 @@ class PlanInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("spectra_bytes", ctypes.c_size_t),
                 ("model_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double * 5),
                 ("build_ms", ctypes.c_double), ("tune_ms", ctypes.c_double), ("band", ctypes.c_int),
+                ("band_speedup", ctypes.c_double),
                 ("xtile", ctypes.c_int), ("apad", ctypes.c_int), ("zblocks", ctypes.c_int)]
 
     def as_dict(self):
@@ -158,12 +160,16 @@ class GreenPlan:
     x0 + (i+1) hx).  band = N keeps only plane distances |k - k'| <= N
     (pipe_green_plan_banded, Eq. 18); band = "auto" picks N from the decay
     of the mode sum with tolerance band_tol.  L is then (lx, ly).
+    band_fastest=True returns the 3-D plan instead when it solves faster
+    (info.band_speedup holds the measured ratio either way).
     """
 
     def __init__(self, nx, ny, nz, hx, hy, hz, a, b, kind=IGF_Z, precision="fp64", mx=None, my=None,
                  L=None, keep_green=False, autotune=False, stream=None, offset=(0.0, 0.0), band=None,
-                 band_tol=1e-6):
+                 band_tol=1e-6, band_fastest=False):
         flags = int(kind) | (PREC_FP32 if precision == "fp32" else PREC_FP64) | (KEEP_GREEN if keep_green else 0)
+        if band_fastest:
+            flags |= BAND_FASTEST
         h = _P()
         st = _stream_ptr(stream) if stream is not None else None
         if band is not None:

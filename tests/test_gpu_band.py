@@ -341,3 +341,28 @@ def test_band_at_smooth_lengths(torch_cuda, prec, lx, ly, nb):
     got = gpu_solve(plan, rho)
     ref = fourterm.solve(oracle_input(rho, prec), *h, A, B, 2 * nx + 1, 2 * ny + 3, 1, band=nb)
     assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
+
+
+def test_banded_build_times_itself_against_the_3d_plan(torch_cuda):
+    """Every banded plan reports the measured 3-D/banded solve-time ratio; with
+    band_fastest the call returns whichever plan is faster: here the 3-D plan
+    for the full z sum (N = nz - 1 plane products cost more than the z
+    transforms), the banded plan for N = 0 on a long mesh (Eq. 17)."""
+    from oracle import fourterm
+    from paper_1111_4971_amd import pipe
+    shape = (16, 14, 64)
+    nx, ny, nz = shape
+    rho = np.random.default_rng(64).standard_normal(shape)
+    log("band vs 3-D timing: full z sum")
+    p = _plan(shape, "fp64", 1, nz - 1, band_fastest=True)
+    assert p.band is None and 0 < p.info.band_speedup < 1
+    got = gpu_solve(p, rho)
+    ref = fourterm.solve(rho, *H, A, B, 2 * nx + 3, 2 * ny + 1, 1)
+    assert rel_l2(got, ref) <= 1e-12 and rel_max(got, ref) <= 1e-12
+    q = _plan(shape, "fp64", 1, 3)
+    assert q.band == 3 and q.info.band_speedup > 0
+    log("band vs 3-D timing: N = 0 on 128x128x256")
+    wl, _ = __import__("paper_1111_4971_amd.workloads", fromlist=["x"]).accuracy_study_bunch(128, 256, 120.0)
+    r = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind, precision="fp32",
+                       mx=wl.mx, my=wl.my, band=0, band_fastest=True)
+    assert r.band == 0 and r.info.band_speedup > 1
