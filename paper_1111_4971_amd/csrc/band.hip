@@ -39,12 +39,12 @@ template <typename real, int N, int T, bool INV>
 __global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N, strided_V<real, N>()>::E) * T)) *
                              (N / Plan<N, strided_V<real, N>()>::E) * T)
 void strided_pair_kernel(const void* in, void* out, int n_in, int n_out, long r_es, long c_es, long ncols,
-                         long r_ss, long c_ss, long nslabs, int nz, real scale, const cplx<real>* __restrict__ tw) {
+                         long r_ss, long c_ss, long nslabs, int nz, real scale, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
     using PL = Plan<N, strided_V<real, N>()>;
     constexpr int P = N / PL::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
-    __shared__ C s_tw[N];
+    __shared__ twid<real> s_tw[N];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
@@ -134,7 +134,7 @@ __device__ __forceinline__ int floor_half(int x) { return x >= 0 ? x / 2 : -((1 
 template <typename real, int N>
 __global__ __launch_bounds__((2 * (N / Plan<N>::E) * band_T<real, N>()))
 void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz, int nb,
-                  int to, const real* __restrict__ table, const cplx<real>* __restrict__ tw) {
+                  int to, const real* __restrict__ table, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
     constexpr int T = band_T<real, N>(), TS = T + 1;
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NH = N / 2, NKX = NH + 1;
@@ -144,7 +144,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
     static_assert(IM * NT == NH * T, "the E/4 items per thread must tile the orbits");
     constexpr int KPT = (10 * NKX + NT - 1) / NT;   // coefficients each thread stages per distance
     __shared__ C lds[2 * N * TS];
-    __shared__ C s_tw[N];
+    __shared__ twid<real> s_tw[N];
     __shared__ real sK[10 * NKX];   // K0..K9 of one plane distance, this block's ky
     tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
@@ -325,12 +325,12 @@ template <typename real, int N> constexpr int band0_T() {
 template <typename real, int N>
 __global__ __launch_bounds__((2 * (N / Plan<N>::E) * band0_T<real, N>()))
 void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz,
-                   const real* __restrict__ table, const cplx<real>* __restrict__ tw) {
+                   const real* __restrict__ table, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
     constexpr int T = band0_T<real, N>();
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NKX = N / 2 + 1;
     __shared__ C lds[2 * N * T];
-    __shared__ C s_tw[N];
+    __shared__ twid<real> s_tw[N];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const unsigned ntile = gridDim.x;
@@ -403,13 +403,13 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
 template <typename real, int N>
 __global__ __launch_bounds__((2 * (N / Plan<N>::E) * band0_T<real, N>()))
 void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz,
-                   int nb, int to, const real* __restrict__ table, const cplx<real>* __restrict__ tw) {
+                   int nb, int to, const real* __restrict__ table, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
     constexpr int T = band0_T<real, N>(), TS = T + 1;
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NH = N / 2, NKX = NH + 1;
     constexpr int IM = (NH * T + NT - 1) / NT;   // (orbit < N/2, output column) items per thread, at most
     __shared__ C lds[2 * N * TS];
-    __shared__ C s_tw[N];
+    __shared__ twid<real> s_tw[N];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const unsigned ntile = gridDim.x;
@@ -530,12 +530,12 @@ template <typename real, int N, int T, bool INV>
 __global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N, strided_V<real, N>()>::E) * T)) *
                              (N / Plan<N, strided_V<real, N>()>::E) * T)
 void strided_real_kernel(const void* in, void* out, int n_in, int n_out, long in_es, long out_es, long ncols,
-                         long in_ss, long out_ss, long nslabs, real scale, const cplx<real>* __restrict__ tw) {
+                         long in_ss, long out_ss, long nslabs, real scale, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
     using PL = Plan<N, strided_V<real, N>()>;
     constexpr int P = N / PL::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
-    __shared__ C s_tw[N];
+    __shared__ twid<real> s_tw[N];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
@@ -622,7 +622,7 @@ hipError_t launch_strided_pair(int n, bool inverse, const void* in, void* out, i
     case N_: {                                                                                       \
         constexpr int T = strided_T<real, N_>(), V = strided_V<real, N_>();                          \
         constexpr int P = N_ / Plan<N_, V>::E, SPW = ce_max(1, 256 / (P * T));                       \
-        const C* tw = twb.stage<C>(N_, V);                                                           \
+        const twid<real>* tw = twb.stage<twid<real>>(N_, V);                                                           \
         if (!tw) return hipErrorInvalidValue;                                                        \
         dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW));            \
         if (inverse)                                                                                 \
@@ -652,7 +652,7 @@ hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, i
     case N_: {                                                                                       \
         constexpr int T = strided_T<real, N_>(), V = strided_V<real, N_>();                          \
         constexpr int P = N_ / Plan<N_, V>::E, SPW = ce_max(1, 256 / (P * T));                       \
-        const C* tw = twb.stage<C>(N_, V);                                                           \
+        const twid<real>* tw = twb.stage<twid<real>>(N_, V);                                                           \
         if (!tw) return hipErrorInvalidValue;                                                        \
         dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW));            \
         if (inverse)                                                                                 \
@@ -714,7 +714,7 @@ template <typename real>
 hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
                         const TwiddleBank& twb, hipStream_t s, bool single_window) {
     using C = cplx<real>;
-    const C* tw = twb.stage<C>(lx);
+    const twid<real>* tw = twb.stage<twid<real>>(lx);
     if (!tw || nb < 0 || nx > lx || nz < 1) return hipErrorInvalidValue;
     const int nzp = (nz + 1) / 2;
     switch (lx) {

@@ -14,11 +14,11 @@ template <typename real, int N> constexpr int lines_per_block() {
 
 template <typename real, int N, bool INV>
 __global__ __launch_bounds__((lines_per_block<real, N>() * (N / Plan<N>::E)))
-void lines_kernel(const cplx<real>* in, cplx<real>* out, long nlines, const cplx<real>* __restrict__ tw) {
+void lines_kernel(const cplx<real>* in, cplx<real>* out, long nlines, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
     constexpr int P = N / Plan<N>::E, LPB = lines_per_block<real, N>(), LS = N + N / 16 + 1;
     __shared__ C lds[LPB * LS];
-    __shared__ C s_tw[N];
+    __shared__ twid<real> s_tw[N];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int t = threadIdx.x % P, li = threadIdx.x / P;
     const long line = (long)blockIdx.x * LPB + li;
@@ -39,7 +39,7 @@ template <typename real>
 hipError_t launch_lines(int n, bool inverse, const void* in, void* out, long nlines, const TwiddleBank& twb,
                         hipStream_t s) {
     using C = cplx<real>;
-    const C* tw = twb.stage<C>(n);
+    const twid<real>* tw = twb.stage<twid<real>>(n);
     if (!tw || nlines <= 0) return hipErrorInvalidValue;
     switch (n) {
 #define X(N_)                                                                                        \

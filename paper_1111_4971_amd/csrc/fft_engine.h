@@ -17,12 +17,32 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace pipe {
 
 template <typename R> struct cplx_t;
 template <> struct cplx_t<float> { using type = float2; };
 template <> struct cplx_t<double> { using type = double2; };
 template <typename R> using cplx = typename cplx_t<R>::type;
+
+// Twiddles.  FP64 passes take W as one double2.  FP32 passes take W either
+// rounded once to float2, or (PIPE_TW_COMPENSATED) as an unevaluated sum
+// hi + lo of two float2 (lo = the FP32 rounding of W - hi), applied as
+// a hi + a lo, which removes the twiddles' own rounding from the transform.
+#ifndef PIPE_TW_COMPENSATED
+#define PIPE_TW_COMPENSATED 0
+#endif
+struct TwPair32 {
+    float2 hi, lo;
+};
+template <typename real> struct twid_t { using type = cplx<real>; };
+template <> struct twid_t<float> { using type = std::conditional_t<PIPE_TW_COMPENSATED != 0, TwPair32, float2>; };
+template <typename real> using twid = typename twid_t<real>::type;
+// the complex type a twiddle type multiplies
+template <typename TW> struct tw_complex { using type = TW; };
+template <> struct tw_complex<TwPair32> { using type = float2; };
+
 
 template <typename C> __device__ __forceinline__ C cmake(decltype(C::x) x, decltype(C::x) y) { C c; c.x = x; c.y = y; return c; }
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return cmake<C>(a.x + b.x, a.y + b.y); }
@@ -43,6 +63,16 @@ template <bool INV, typename C> __device__ __forceinline__ C cmul_mi(C a) {
 // twiddle multiply: a * w (forward) or a * conj(w) (inverse)
 template <bool INV, typename C> __device__ __forceinline__ C ctw(C a, C w) {
     return INV ? cmulc(a, w) : cmul(a, w);
+}
+template <bool INV> __device__ __forceinline__ float2 ctw(float2 a, TwPair32 w) {
+    // the lo products first, then the hi products fused onto them
+    const float sy = INV ? -1.f : 1.f;
+    const float lr = a.x * w.lo.x - sy * (a.y * w.lo.y);
+    const float li = sy * (a.x * w.lo.y) + a.y * w.lo.x;
+    float2 r;
+    r.x = fmaf(a.x, w.hi.x, fmaf(-sy * a.y, w.hi.y, lr));
+    r.y = fmaf(sy * a.x, w.hi.y, fmaf(a.y, w.hi.x, li));
+    return r;
 }
 
 // ---------------------------------------------------------------- butterflies
@@ -333,8 +363,8 @@ __device__ __forceinline__ void stage_load(C* v, int t, Src src) {
 }
 
 // Twiddle (for Ns > 1) and butterfly in registers.
-template <class PL, int R, int NS, bool INV, typename C>
-__device__ __forceinline__ void stage_compute(C* v, int t, const C* __restrict__ tw) {
+template <class PL, int R, int NS, bool INV, typename C, typename TW>
+__device__ __forceinline__ void stage_compute(C* v, int t, const TW* __restrict__ tw) {
     constexpr int N = PL::LEN, E = PL::E, P = N / E, NB = E / R;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -364,8 +394,8 @@ __device__ __forceinline__ void stage_store(const C* v, int t, Dst dst) {
 // Stage s of the transform from its inputs in registers: twiddle and
 // butterflies, then the last stage stores to dst, any other stage exchanges
 // through LDS and continues with stage s + 1.
-template <class PL, int s, bool INV, Sync SY, typename C, typename Dst, typename Lds>
-__device__ __forceinline__ void fft_stages(C* v, int t, const C* __restrict__ tw, Dst dst, Lds lds) {
+template <class PL, int s, bool INV, Sync SY, typename C, typename TW, typename Dst, typename Lds>
+__device__ __forceinline__ void fft_stages(C* v, int t, const TW* __restrict__ tw, Dst dst, Lds lds) {
     constexpr int R = PL::radix(s), NS = plan_ns<PL>(s);
     stage_compute<PL, R, NS, INV>(v, t, tw);
     if constexpr (s == PL::S - 1) {
@@ -383,8 +413,8 @@ __device__ __forceinline__ void fft_stages(C* v, int t, const C* __restrict__ tw
 // stage_load<PL, radix(0)>).  dst is the element accessor of the last store;
 // lds.get(e) / lds.set(e, v) address this thread's line in LDS.  Every thread
 // of the block (SY = BLOCK) or of the wave (SY = WAVE) must call this.
-template <class PL, bool INV, Sync SY = Sync::BLOCK, typename C, typename Dst, typename Lds>
-__device__ __forceinline__ void fft_line_regs(C* v, int t, const C* __restrict__ tw, Dst dst, Lds lds) {
+template <class PL, bool INV, Sync SY = Sync::BLOCK, typename C, typename TW, typename Dst, typename Lds>
+__device__ __forceinline__ void fft_line_regs(C* v, int t, const TW* __restrict__ tw, Dst dst, Lds lds) {
     static_assert(plan_ok<PL>(), "inconsistent length plan");
     fft_stages<PL, 0, INV, SY>(v, t, tw, dst, lds);
 }
@@ -392,9 +422,10 @@ __device__ __forceinline__ void fft_line_regs(C* v, int t, const C* __restrict__
 // Whole transform.  src/dst are element accessors for the first load and the
 // last store.  SRC_LDS: the first load reads the same LDS line that later
 // stages overwrite, so a barrier separates it from the first store.
-template <class PL, bool INV, bool SRC_LDS, Sync SY = Sync::BLOCK, typename C, typename Src, typename Dst,
+template <class PL, bool INV, bool SRC_LDS, Sync SY = Sync::BLOCK, typename TW, typename Src, typename Dst,
           typename Lds>
-__device__ __forceinline__ void fft_line(int t, const C* __restrict__ tw, Src src, Dst dst, Lds lds) {
+__device__ __forceinline__ void fft_line(int t, const TW* __restrict__ tw, Src src, Dst dst, Lds lds) {
+    using C = typename tw_complex<TW>::type;
     C v[PL::E];
     stage_load<PL, PL::radix(0)>(v, t, src);
     if constexpr (SRC_LDS && PL::S > 1) line_sync<SY>();

@@ -41,6 +41,9 @@ template <typename real> using C_of = cplx<real>;
 template <typename C> static const C* bank_base(const TwiddleBank& b);
 template <> const float2* bank_base<float2>(const TwiddleBank& b) { return reinterpret_cast<const float2*>(b.d32); }
 template <> const double2* bank_base<double2>(const TwiddleBank& b) { return reinterpret_cast<const double2*>(b.d64); }
+template <> const TwPair32* bank_base<TwPair32>(const TwiddleBank& b) {
+    return reinterpret_cast<const TwPair32*>(b.d32c);
+}
 
 template <typename C> const C* TwiddleBank::get(int n) const {
     for (int i = 0; i < kNumFft; ++i) {
@@ -63,6 +66,8 @@ template const float2* TwiddleBank::get<float2>(int) const;
 template const double2* TwiddleBank::get<double2>(int) const;
 template const float2* TwiddleBank::stage<float2>(int, int) const;
 template const double2* TwiddleBank::stage<double2>(int, int) const;
+template const TwPair32* TwiddleBank::get<TwPair32>(int) const;
+template const TwPair32* TwiddleBank::stage<TwPair32>(int, int) const;
 
 template <class PL> static int stage_exponents(int* m) {
     constexpr int N = PL::LEN;
@@ -107,7 +112,7 @@ int fft_stage_exponents(int n, int variant, int* m_out) {
 template <typename real, int NH>
 __global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH, z_V<real, NH>()>::E)))
 void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long out_pitch, long nlines,
-                  const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2,
+                  const twid<real>* __restrict__ tw, const twid<real>* __restrict__ tw2, int vec2,
                   const GroupArgs* __restrict__ group) {
     using C = cplx<real>;
     if (group) {
@@ -120,7 +125,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     constexpr int PADN = NH + NH / 16 + 1;
     constexpr Sync ZS = z_sync<real, NH>();
     __shared__ C lds[LPW * PADN];
-    __shared__ C s_tw[NH], s_tw2[NH];
+    __shared__ twid<real> s_tw[NH], s_tw2[NH];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
@@ -166,7 +171,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
                 } else {
                     const C zn = cconj(view.get(NH - k));
                     const C A = cadd(zk, zn), B = csub(zk, zn);
-                    const C wb = cmul(B, tw2[k]);  // W^k B;  X = (A - i W^k B) / 2
+                    const C wb = ctw<false>(B, tw2[k]);  // W^k B;  X = (A - i W^k B) / 2
                     dst[k] = cscale(cmake<C>(A.x + wb.y, A.y - wb.x), (real)0.5);
                 }
             }
@@ -184,7 +189,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
 template <typename real, int NH>
 __global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH, z_V<real, NH>()>::E)))
 void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch, int n_out, long nlines,
-                  real scale, const cplx<real>* __restrict__ tw, const cplx<real>* __restrict__ tw2, int vec2,
+                  real scale, const twid<real>* __restrict__ tw, const twid<real>* __restrict__ tw2, int vec2,
                   const GroupArgs* __restrict__ group) {
     using C = cplx<real>;
     if (group) {
@@ -197,7 +202,7 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
     constexpr int PADN = NH + NH / 16 + 1;
     constexpr Sync ZS = z_sync<real, NH>();
     __shared__ C lds[LPW * PADN];
-    __shared__ C s_tw[NH], s_tw2[NH];
+    __shared__ twid<real> s_tw[NH], s_tw2[NH];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
@@ -235,7 +240,7 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
                 if (k == 0) return cmake<C>(xk.x + xk.y, xk.x - xk.y);
                 const C xn = cconj(view.get(NH - k));
                 const C A = cadd(xk, xn), B = csub(xk, xn);
-                const C wb = cmulc(B, tw2[k]);  // W^{-k} B
+                const C wb = ctw<true>(B, tw2[k]);  // W^{-k} B
                 return cmake<C>(A.x - wb.y, A.y + wb.x);  // A + i W^{-k} B
             },
             [&](int m, C v) {
@@ -260,7 +265,7 @@ template <typename real, int N, int T, bool INV>
 __global__ __launch_bounds__(ce_max(1, 256 / ((N / Plan<N, strided_V<real, N>()>::E) * T)) *
                              (N / Plan<N, strided_V<real, N>()>::E) * T)
 void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, long in_es, long out_es,
-                    long ncols, long in_ss, long out_ss, long nslabs, const cplx<real>* __restrict__ tw,
+                    long ncols, long in_ss, long out_ss, long nslabs, const twid<real>* __restrict__ tw,
                     const GroupArgs* __restrict__ group) {
     using C = cplx<real>;
     if (group) {
@@ -270,7 +275,7 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
     using PL = Plan<N, strided_V<real, N>()>;
     constexpr int P = N / PL::E, SPW = ce_max(1, 256 / (P * T));
     __shared__ C lds[SPW * N * T];
-    __shared__ C s_tw[N];
+    __shared__ twid<real> s_tw[N];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, s = threadIdx.x / (T * P);
     const long slab = (long)blockIdx.y * SPW + s;
@@ -303,7 +308,7 @@ void strided_kernel(const cplx<real>* in, cplx<real>* out, int n_in, int n_out, 
 template <typename real, int N, int V, int T, bool ADJ, int NV>
 __global__ __launch_bounds__(2 * (N / Plan<N, V>::E) * T)
 void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, long xs, const real* __restrict__ table,
-                  const real* __restrict__ nyq, const cplx<real>* __restrict__ tw,
+                  const real* __restrict__ nyq, const twid<real>* __restrict__ tw,
                   const GroupArgs* __restrict__ group, int shared_table) {
     using C = cplx<real>;
     using PL = Plan<N, V>;
@@ -338,7 +343,7 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, long xs, const real*
     constexpr bool NYQ_LDS = (N % 2 == 0) && NT >= NV * T;
     constexpr int NO = NYQ_LDS ? N / 2 : NKX;
     __shared__ C lds[2 * N * T];
-    __shared__ C s_tw[N];
+    __shared__ twid<real> s_tw[N];
     __shared__ real s_nyo[NYQ_LDS ? NV * T : 1];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
@@ -485,7 +490,7 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
                         long nlines, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group, int ngroup,
                         bool aligned, int zcap) {
     using C = cplx<real>;
-    const C* tw2 = twb.get<C>(2 * nh);
+    const twid<real>* tw2 = twb.get<twid<real>>(2 * nh);
     if (!tw2 || nlines <= 0) return hipErrorInvalidValue;
     const int vec2 = (n_in % 2 == 0) && (in_pitch % 2 == 0) && aligned &&
                      (group || (uintptr_t)in % (2 * sizeof(real)) == 0);
@@ -493,7 +498,7 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
         constexpr int V = z_V<real, N_>(), P = N_ / Plan<N_, V>::E, LPW = z_lines<real, N_>();       \
-        const C* tw = twb.stage<C>(N_, V);                                                      \
+        const twid<real>* tw = twb.stage<twid<real>>(N_, V);                                                      \
         if (!tw) return hipErrorInvalidValue;                                                   \
         dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup, zcap), 1, (unsigned)ngroup);               \
         hipLaunchKernelGGL((z_r2c_kernel<real, N_>), grid, dim3(LPW * P), 0, s, in, in_pitch,   \
@@ -511,7 +516,7 @@ hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long o
                         long nlines, real scale, const TwiddleBank& twb, hipStream_t s, const GroupArgs* group,
                         int ngroup, bool aligned, int zcap) {
     using C = cplx<real>;
-    const C* tw2 = twb.get<C>(2 * nh);
+    const twid<real>* tw2 = twb.get<twid<real>>(2 * nh);
     if (!tw2 || nlines <= 0) return hipErrorInvalidValue;
     const int vec2 = (n_out % 2 == 0) && (out_pitch % 2 == 0) && aligned &&
                      (group || (uintptr_t)out % (2 * sizeof(real)) == 0);
@@ -519,7 +524,7 @@ hipError_t launch_z_c2r(int nh, const void* in, long in_pitch, real* out, long o
 #define X(N_)                                                                                   \
     case N_: {                                                                                  \
         constexpr int V = z_V<real, N_>(), P = N_ / Plan<N_, V>::E, LPW = z_lines<real, N_>();       \
-        const C* tw = twb.stage<C>(N_, V);                                                      \
+        const twid<real>* tw = twb.stage<twid<real>>(N_, V);                                                      \
         if (!tw) return hipErrorInvalidValue;                                                   \
         dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup, zcap), 1, (unsigned)ngroup);               \
         hipLaunchKernelGGL((z_c2r_kernel<real, N_>), grid, dim3(LPW * P), 0, s, (const C*)in,   \
@@ -543,7 +548,7 @@ hipError_t launch_strided(int n, bool inverse, const void* in, void* out, int n_
     case N_: {                                                                                     \
         constexpr int T = strided_T<real, N_>(), V = strided_V<real, N_>();                        \
         constexpr int P = N_ / Plan<N_, V>::E, SPW = ce_max(1, 256 / (P * T));                     \
-        const C* tw = twb.stage<C>(N_, V);                                                         \
+        const twid<real>* tw = twb.stage<twid<real>>(N_, V);                                                         \
         if (!tw) return hipErrorInvalidValue;                                                      \
         dim3 grid((unsigned)((ncols + T - 1) / T), (unsigned)((nslabs + SPW - 1) / SPW),           \
                   (unsigned)ngroup);                                                               \
@@ -593,7 +598,7 @@ int xprod_tile(int lx, int real_bytes) {
 // and T/2 (when T > 1); a plan's schedule picks one.
 template <typename real, int N, int T, int V>
 static hipError_t launch_xprod_t(bool adjoint, C_of<real>* data, int nx, int ly, int nh, long pitch,
-                                 const real* table, const real* nyq, const C_of<real>* tw, hipStream_t s,
+                                 const real* table, const real* nyq, const twid<real>* tw, hipStream_t s,
                                  const GroupArgs* group, int ngroup, bool shared_table, int nval) {
     constexpr int P = N / Plan<N, V>::E;
     dim3 grid((unsigned)((nh + T - 1) / T), (unsigned)(ly / 2 + 1), (unsigned)ngroup);
@@ -619,7 +624,7 @@ hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh
 #define X(N_)                                                                                          \
     case N_: {                                                                                         \
         constexpr int V = xprod_V<real, N_>(), T = xprod_T<real, N_>();                                \
-        const C* tw = twb.stage<C>(N_, V);                                                             \
+        const twid<real>* tw = twb.stage<twid<real>>(N_, V);                                                             \
         if (!tw) return hipErrorInvalidValue;                                                          \
         if (tile == T)                                                                                 \
             return launch_xprod_t<real, N_, T, V>(adjoint, (C*)data, nx, ly, nh, pitch, table, nyq, tw, s, \

@@ -115,9 +115,10 @@ pipe_status_t device_ctx(int dev, DeviceCtx** out) {
         const size_t off = m_of.size();
         c.tw.total = off;
         std::vector<double> h64(2 * off);
-        std::vector<float> h32(2 * off);
+        std::vector<float> h32(2 * off), h32c(4 * off);
         for (size_t k = 0; k < off; ++k) {
-            // W_n^m = exp(-2 pi i m / n), evaluated in long double and rounded once
+            // W_n^m = exp(-2 pi i m / n), evaluated in long double and rounded once;
+            // the FP32 pair holds hi = the rounding and lo = the rounding of the rest
             const long double ang =
                 -2.0L * 3.141592653589793238462643383279503L * (long double)m_of[k] / (long double)n_of[k];
             const long double cr = cosl(ang), ci = sinl(ang);
@@ -125,16 +126,27 @@ pipe_status_t device_ctx(int dev, DeviceCtx** out) {
             h64[2 * k + 1] = (double)ci;
             h32[2 * k] = (float)cr;
             h32[2 * k + 1] = (float)ci;
+            h32c[4 * k] = h32[2 * k];
+            h32c[4 * k + 1] = h32[2 * k + 1];
+            h32c[4 * k + 2] = (float)(cr - (long double)h32[2 * k]);
+            h32c[4 * k + 3] = (float)(ci - (long double)h32[2 * k + 1]);
         }
-        HIP_TRY(dev_alloc(&c.tw.d64, h64.size() * sizeof(double)), "twiddle allocation");
-        hipError_t e = dev_alloc(&c.tw.d32, h32.size() * sizeof(float));
+        void* bufs[3] = {nullptr, nullptr, nullptr};
+        const std::vector<float>* srcf[2] = {&h32, &h32c};
+        hipError_t e = dev_alloc(&bufs[0], h64.size() * sizeof(double));
+        if (e == hipSuccess) e = dev_alloc(&bufs[1], h32.size() * sizeof(float));
+        if (e == hipSuccess) e = dev_alloc(&bufs[2], h32c.size() * sizeof(float));
+        if (e == hipSuccess) e = hipMemcpy(bufs[0], h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i)
+            e = hipMemcpy(bufs[1 + i], srcf[i]->data(), srcf[i]->size() * sizeof(float), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            (void)hipFree(c.tw.d64);
-            c.tw.d64 = nullptr;
-            return hip_fail(e, "twiddle allocation");
+            for (void* b : bufs)
+                if (b) (void)hipFree(b);
+            return hip_fail(e, "twiddle tables");
         }
-        HIP_TRY(hipMemcpy(c.tw.d64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice), "twiddle upload");
-        HIP_TRY(hipMemcpy(c.tw.d32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice), "twiddle upload");
+        c.tw.d64 = bufs[0];
+        c.tw.d32 = bufs[1];
+        c.tw.d32c = bufs[2];
         // device address of the fixed scratch (this device is current here)
         HIP_TRY(hipGetSymbolAddress(&c.scratch, HIP_SYMBOL(scratch)), "scratch symbol address");
         if (!c.scratch) return fail(PIPE_ERR_HIP, "scratch symbol address: null");

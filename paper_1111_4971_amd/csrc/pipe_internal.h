@@ -43,6 +43,7 @@ constexpr int kNumVariants = sizeof(kPlanVariants) / sizeof(PlanVariant);
 struct TwiddleBank {
     void* d64 = nullptr;   // double2
     void* d32 = nullptr;   // float2
+    void* d32c = nullptr;  // TwPair32: the same entries as FP32 (hi, lo) pairs
     size_t offset[kNumFft] = {};        // natural table of length N
     size_t offset2[kNumFft] = {};       // natural table of length 2N
     size_t soffset[kNumFft] = {};       // stage table of the default plan of length N
