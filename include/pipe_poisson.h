@@ -96,9 +96,10 @@ typedef struct pipe_plan_info {
     double band_speedup;     /* pipe_green_plan_banded: measured time of the mesh's 3-D     */
                              /* solve over the banded solve's (> 1: banded is faster);      */
                              /* also on a 3-D plan returned for PIPE_BAND_FASTEST; else 0  */
-    int xtile;               /* launch schedule (3-D plans; 0 for banded plans): kz tile of */
-    int apad;                /* the x pass, unused slots per row of the y-transformed array,*/
-    int zblocks;             /* block cap of the z passes; none of them changes a result   */
+    int xtile;               /* launch schedule (3-D plans; banded plans report only xtile, */
+    int apad;                /* for N = 0): kz (packed-column) tile of the x pass, unused   */
+    int zblocks;             /* slots per row of the y-transformed array, block cap of the  */
+                             /* z passes; none of them changes a result                    */
 } pipe_plan_info_t;
 
 /*

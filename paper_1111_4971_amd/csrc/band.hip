@@ -322,15 +322,21 @@ template <typename real, int N> constexpr int band0_T() {
     return t;
 }
 
-template <typename real, int N>
-__global__ __launch_bounds__((2 * (N / Plan<N>::E) * band0_T<real, N>()))
+// T: the widest tile (band0_T) or half of it; the plan picks by timing.  The
+// ten coefficients of each of a thread's orbits are loaded with the rows,
+// before the forward transform (they depend on ky and kx only); the Nyquist
+// orbit kx = N/2, whose T items go to the first T threads, is staged in LDS.
+template <typename real, int N, int T>
+__global__ __launch_bounds__((2 * (N / Plan<N>::E) * T))
 void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz,
                    const real* __restrict__ table, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
-    constexpr int T = band0_T<real, N>();
-    constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NKX = N / 2 + 1;
+    constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NKX = N / 2 + 1, NO = N / 2;
+    constexpr int IT = (NO * T + NT - 1) / NT, KN = (10 + NT - 1) / NT;
+    static_assert(N % 2 == 0, "banded lengths are even");
     __shared__ C lds[2 * N * T];
     __shared__ twid<real> s_tw[N];
+    __shared__ real s_kn[10];   // the Nyquist orbit's coefficients
     tw = stage_twiddles(s_tw, tw, stage_tw_size<Plan<N>>());
     const int c = threadIdx.x % T, t = (threadIdx.x / T) % P, l = threadIdx.x / (T * P);
     const unsigned ntile = gridDim.x;
@@ -347,20 +353,37 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     C* oline = out + (active ? (long)kyl * nx * nzp + pc : 0);
     LdsCol<C, T> view{lds + l * N * T + c};
 
+    const real* trow = table + (long)ky * 10 * NKX;
+    real qs[IT][10];
+    real kn[KN];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int w = threadIdx.x + it * NT;
+        if (w < NO * T) {
+#pragma unroll
+            for (int m = 0; m < 10; ++m) qs[it][m] = trow[m * NKX + w / T];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+        const int m = threadIdx.x + k * NT;
+        if (m < 10) kn[k] = trow[m * NKX + NO];
+    }
+
     fft_line<Plan<N>, false, false>(
         t, tw, [&](int e) -> C { return (active && e < nx) ? iline[e * xs] : cmake<C>(0, 0); },
         [&](int e, C v) { view.set(e, v); }, view);
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+        const int m = threadIdx.x + k * NT;
+        if (m < 10) s_kn[m] = kn[k];
+    }
     __syncthreads();
 
-    const real* trow = table + (long)ky * 10 * NKX;
-    for (int w = threadIdx.x; w < NKX * T; w += NT) {
-        const int j = w % T, o = w / T;
+    auto orbit_item = [&](int o, int j, const real* q) {
         const int on = (N - o) % N;
         const C f0 = lds[o * T + j], f1 = lds[on * T + j];
         const C g0 = lds[(N + o) * T + j], g1 = lds[(N + on) * T + j];
-        real q[10];
-#pragma unroll
-        for (int m = 0; m < 10; ++m) q[m] = trow[m * NKX + o];
         // 2 R of the even and the odd plane at (kx,ky), (-kx,ky)
         const C u0 = csub(f0, cconj(g1)), u1 = csub(f1, cconj(g0));
         const C xe0 = cadd(f0, cconj(g1)), xe1 = cadd(f1, cconj(g0));
@@ -382,6 +405,17 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
             lds[on * T + j] = pack(e1, d1);
             lds[(N + on) * T + j] = pack(cconj(e0), cconj(d0));
         }
+    };
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int w = threadIdx.x + it * NT;
+        if (w < NO * T) orbit_item(w / T, w % T, qs[it]);
+    }
+    if (threadIdx.x < T) {
+        real q[10];
+#pragma unroll
+        for (int m = 0; m < 10; ++m) q[m] = s_kn[m];
+        orbit_item(NO, threadIdx.x, q);
     }
     __syncthreads();
 
@@ -699,6 +733,16 @@ static int band_small_columns(int T, int nb) {
 }
 
 #if PIPE_TU_FP32
+int band0_tile(int lx, int real_bytes) {
+    switch (lx) {
+#define X(N_) \
+    case N_: return real_bytes == 8 ? band0_T<double, N_>() : band0_T<float, N_>();
+        PIPE_FOR_EACH_BAND_N(X)
+#undef X
+    }
+    return 0;
+}
+
 int band_small_columns_for(int lx, int real_bytes, int nb) {
     switch (lx) {
 #define X(N_) \
@@ -712,7 +756,7 @@ int band_small_columns_for(int lx, int real_bytes, int nb) {
 
 template <typename real>
 hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
-                        const TwiddleBank& twb, hipStream_t s, bool single_window) {
+                        const TwiddleBank& twb, hipStream_t s, bool single_window, int tile0) {
     using C = cplx<real>;
     const twid<real>* tw = twb.stage<twid<real>>(lx);
     if (!tw || nb < 0 || nx > lx || nz < 1) return hipErrorInvalidValue;
@@ -722,10 +766,16 @@ hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int n
     case N_: {                                                                                       \
         constexpr int P = N_ / Plan<N_>::E;                                                          \
         if (nb == 0) {                                                                               \
-            constexpr int T = band0_T<real, N_>();                                                   \
-            dim3 grid((unsigned)((nzp + T - 1) / T), (unsigned)(ly / 2 + 1));                        \
-            hipLaunchKernelGGL((xband0_kernel<real, N_>), grid, dim3(2 * P * T), 0, s,               \
-                               (const C*)in, (C*)out, nx, ly, nz, table, tw);                        \
+            constexpr int T = band0_T<real, N_>(), T2 = T > 1 ? T / 2 : 1;                           \
+            if (tile0 == T2 && T > 1) {                                                              \
+                dim3 grid((unsigned)((nzp + T2 - 1) / T2), (unsigned)(ly / 2 + 1));                  \
+                hipLaunchKernelGGL((xband0_kernel<real, N_, T2>), grid, dim3(2 * P * T2), 0, s,      \
+                                   (const C*)in, (C*)out, nx, ly, nz, table, tw);                    \
+            } else {                                                                                 \
+                dim3 grid((unsigned)((nzp + T - 1) / T), (unsigned)(ly / 2 + 1));                    \
+                hipLaunchKernelGGL((xband0_kernel<real, N_, T>), grid, dim3(2 * P * T), 0, s,        \
+                                   (const C*)in, (C*)out, nx, ly, nz, table, tw);                    \
+            }                                                                                        \
         } else if (single_window && band_small_columns(band0_T<real, N_>(), nb) > 0) {               \
             constexpr int T = band0_T<real, N_>();                                                   \
             const int to = band_small_columns(T, nb);                                                \
@@ -780,7 +830,7 @@ hipError_t launch_band_coefficients(const double* tmp, void* table, int real_byt
     template hipError_t launch_strided_real<real>(int, bool, const void*, void*, int, int, long, long, long, \
                                                   long, long, long, real, const TwiddleBank&, hipStream_t);  \
     template hipError_t launch_xband<real>(int, const void*, void*, int, int, int, int, const real*,         \
-                                           const TwiddleBank&, hipStream_t, bool);
+                                           const TwiddleBank&, hipStream_t, bool, int);
 
 #if PIPE_TU_FP32
 PIPE_INST(float)

@@ -204,6 +204,7 @@ struct pipe_plan_s {
     int band = -1;           // banded plan: planes kept each side of the z sum (Eq. 18); -1 = 3-D plan
     double g0 = 0;           // free-space plans: G at zero separation
     bool band_single = false; // banded x pass: single-window kernel (else chunked), chosen by timing
+    int band_tile0 = 0;       // banded N = 0 x pass: packed-column tile, chosen by timing
     double band_speedup = 0;  // banded build: measured 3-D solve time / banded solve time
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
@@ -534,15 +535,47 @@ pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, h
     return PIPE_OK;
 }
 
-// Times the two banded x-pass kernels (on zeroed scratch of the workspace's
-// size: timing does not depend on the values) and keeps the faster.
-// PIPE_BAND_KERNEL=single or =chunked forces one (tests exercise both).
+// Chooses the banded x pass by timing (on zeroed scratch of the workspace's
+// size: timing does not depend on the values): for N >= 1 the single-window
+// or the chunked kernel (PIPE_BAND_KERNEL=single or =chunked forces one), for
+// N = 0 the packed-column tile, the widest or half of it (PIPE_BAND_TILE0=T
+// forces one).  Tests exercise every choice.
 pipe_status_t choose_band_kernel(pipe_plan_s* p, hipStream_t st) {
-    if (const char* f = std::getenv("PIPE_BAND_KERNEL")) {
-        if (!strcmp(f, "single") || !strcmp(f, "chunked")) {
-            p->band_single = !strcmp(f, "single");
+    struct Cand {
+        bool single;
+        int tile0;
+    };
+    std::vector<Cand> cands;
+    const int T0 = band0_tile(p->lx, p->rb);
+    if (p->band == 0) {
+        if (const char* f = std::getenv("PIPE_BAND_TILE0")) {
+            const int t = atoi(f);
+            if (t != T0 && !(T0 > 1 && t == T0 / 2))
+                return fail(PIPE_ERR_INVALID_ARG, "PIPE_BAND_TILE0 must be %d or %d (got '%s')", T0, T0 / 2, f);
+            p->band_tile0 = t;
             return PIPE_OK;
         }
+        cands.push_back({false, T0});
+        if (T0 > 1) cands.push_back({false, T0 / 2});
+    } else {
+        p->band_tile0 = T0;
+        if (band_small_columns_for(p->lx, p->rb, p->band) <= 0) {
+            p->band_single = false;
+            return PIPE_OK;
+        }
+        if (const char* f = std::getenv("PIPE_BAND_KERNEL")) {
+            if (!strcmp(f, "single") || !strcmp(f, "chunked")) {
+                p->band_single = !strcmp(f, "single");
+                return PIPE_OK;
+            }
+        }
+        cands.push_back({false, T0});
+        cands.push_back({true, T0});
+    }
+    if (cands.size() == 1) {
+        p->band_single = cands[0].single;
+        p->band_tile0 = cands[0].tile0;
+        return PIPE_OK;
     }
     void* ws = nullptr;
     HIP_TRY(dev_alloc(&ws, p->ws_bytes), "allocation (band kernel timing)");
@@ -555,14 +588,16 @@ pipe_status_t choose_band_kernel(pipe_plan_s* p, hipStream_t st) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
-    float best[2] = {0, 0};
+    std::vector<float> best(cands.size(), 0.f);
     pipe_status_t s = PIPE_OK;
-    for (int v = 0; v < 2 && s == PIPE_OK; ++v) {
+    for (size_t v = 0; v < cands.size() && s == PIPE_OK; ++v) {
         auto launch = [&]() -> hipError_t {
             return p->rb == 8 ? launch_xband<double>(p->lx, ws, (char*)ws + half, p->nx, p->ly, p->nz, p->band,
-                                                     (const double*)p->table, p->ctx->tw, st, v == 1)
+                                                     (const double*)p->table, p->ctx->tw, st, cands[v].single,
+                                                     cands[v].tile0)
                               : launch_xband<float>(p->lx, ws, (char*)ws + half, p->nx, p->ly, p->nz, p->band,
-                                                    (const float*)p->table, p->ctx->tw, st, v == 1);
+                                                    (const float*)p->table, p->ctx->tw, st, cands[v].single,
+                                                    cands[v].tile0);
         };
         hipError_t e = launch();   // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, st);
@@ -574,7 +609,11 @@ pipe_status_t choose_band_kernel(pipe_plan_s* p, hipStream_t st) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (s == PIPE_OK) p->band_single = best[1] < best[0];
+    if (s == PIPE_OK) {
+        const size_t bi = std::min_element(best.begin(), best.end()) - best.begin();
+        p->band_single = cands[bi].single;
+        p->band_tile0 = cands[bi].tile0;
+    }
     return s;
 }
 
@@ -594,7 +633,8 @@ pipe_status_t run_band_passes(pipe_plan_s* p, const void* rho, void* phi, void* 
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
     (void)adjoint;   // the banded coefficient matrices are symmetric: same kernel both ways
-    HIP_TRY(launch_xband<real>(p->lx, A, B, nx, ly, nz, p->band, (const real*)p->table, tw, st, p->band_single),
+    HIP_TRY(launch_xband<real>(p->lx, A, B, nx, ly, nz, p->band, (const real*)p->table, tw, st, p->band_single,
+                               p->band_tile0),
             "x pass with banded product");
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
     // 1/2 undoes the factor 2 of the split in the x pass
@@ -1194,12 +1234,10 @@ pipe_status_t pipe_green_plan_banded(int nx, int ny, int nz, double hx, double h
         return s;
     }
     p->ws_bytes = plan_ws_bytes(p);
-    if (p->band >= 1 && band_small_columns_for(p->lx, p->rb, p->band) > 0) {
-        s = choose_band_kernel(p, (hipStream_t)hip_stream);
-        if (s != PIPE_OK) {
-            plan_free(p);
-            return s;
-        }
+    s = choose_band_kernel(p, (hipStream_t)hip_stream);
+    if (s != PIPE_OK) {
+        plan_free(p);
+        return s;
     }
     // time the banded solve against the 3-D solve of the same mesh
     double t_band = 0, t_full = 0;
@@ -1253,7 +1291,7 @@ pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     out->tune_ms = p->tune_ms;
     out->band = p->band;
     out->band_speedup = p->band_speedup;
-    out->xtile = p->band >= 0 ? 0 : p->tile;
+    out->xtile = p->band >= 0 ? (p->band == 0 ? p->band_tile0 : 0) : p->tile;
     out->apad = p->band >= 0 ? 0 : p->apad;
     out->zblocks = p->band >= 0 ? 0 : p->zcap;
     return PIPE_OK;

@@ -153,8 +153,11 @@ hipError_t launch_strided_real(int n, bool inverse, const void* in, void* out, i
 // a block is one transform chunk, available when band_small_columns_for > 0) and
 // the chunked one; the plan times both and keeps the faster.
 template <typename real>
+// tile0 (nb = 0 only): the N = 0 kernel's packed-column tile, band0_tile(lx, .) or half of it.
 hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
-                        const TwiddleBank& tw, hipStream_t s, bool single_window);
+                        const TwiddleBank& tw, hipStream_t s, bool single_window, int tile0 = 0);
+// Widest packed-column tile of the N = 0 banded x pass (0 if lx unsupported).
+int band0_tile(int lx, int real_bytes);
 // Output columns per block of the single-window banded x pass, 0 if not available.
 int band_small_columns_for(int lx, int real_bytes, int nb);
 // Packed columns per block of the banded x pass (0 if lx unsupported).

@@ -366,3 +366,34 @@ def test_banded_build_times_itself_against_the_3d_plan(torch_cuda):
     r = pipe.GreenPlan(wl.nx, wl.ny, wl.nz, wl.hx, wl.hy, wl.hz, wl.a, wl.b, kind=wl.kind, precision="fp32",
                        mx=wl.mx, my=wl.my, band=0, band_fastest=True)
     assert r.band == 0 and r.info.band_speedup > 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(256, 5, 19), (13, 10, 33), (40, 24, 7)])
+def test_both_n0_tiles(torch_cuda, monkeypatch, prec, shape):
+    """The N = 0 x pass at its widest packed-column tile and at half of it (the
+    plan picks one by timing) against the oracle's Eq. 17 (z distances 0)."""
+    from oracle import fourterm
+    from paper_1111_4971_amd import pipe
+    nx, ny, nz = shape
+    h = (A / (nx + 1), 0.9 * B / (ny + 1), 0.05)
+    rho = np.random.default_rng(nz + nx).standard_normal(shape)
+    ref = fourterm.solve(oracle_input(rho, prec), *h, A, B, 2 * nx + 1, 2 * ny + 3, 1, band=0)
+    mk = lambda: pipe.GreenPlan(nx, ny, nz, *h, A, B, kind=1, precision=prec, mx=2 * nx + 1, my=2 * ny + 3, band=0)
+    chosen = mk().info.xtile
+    accepted = []
+    for t in (16, 8, 4, 2, 1):
+        monkeypatch.setenv("PIPE_BAND_TILE0", str(t))
+        log("band N=0 tile %d %s %s" % (t, prec, shape))
+        try:
+            plan = mk()
+        except pipe.PipeError as e:
+            assert e.status == 1     # not one of this length's two tiles
+            continue
+        accepted.append(t)
+        assert plan.info.xtile == t
+        got = gpu_solve(plan, rho)
+        assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (t, rel_l2(got, ref))
+    # the widest tile and half of it (one tile where the widest is 1)
+    assert chosen in accepted and len(accepted) in (1, 2)
+    assert len(accepted) == 1 or accepted[0] == 2 * accepted[1]
