@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 PASS_NAMES = ["z_forward", "y_forward", "x_product", "y_inverse", "z_inverse"]
 KERNEL_NAMES = ["z_r2c_kernel", "strided_kernel<fwd>", "xprod_kernel", "strided_kernel<inv>", "z_c2r_kernel"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_three_bunch_cic.json")
-KERNEL_SOURCES = ["paper_1111_4971_amd/csrc/passes.hip", "paper_1111_4971_amd/csrc/pass_common.h",
-                  "paper_1111_4971_amd/csrc/fft_engine.h"]
+KERNEL_SOURCES = ["paper_1111_4971_amd/csrc/passes.hip", "paper_1111_4971_amd/csrc/xprod.hip",
+                  "paper_1111_4971_amd/csrc/pass_common.h", "paper_1111_4971_amd/csrc/fft_engine.h"]
 
 
 def log(*a):
@@ -112,7 +112,9 @@ def time_leg(pipe, torch, wl, precision, steps, warmup):
         "ms_per_step_with_events": ms_events,
         "events_recorded": n,
         "plan_build_ms": info.build_ms,
-        "schedule": {"x_tile": info.xtile, "a2_row_pad": info.apad, "z_block_cap": info.zblocks},
+        "schedule": {"x_tile": info.xtile, "a2_row_pad": info.apad, "z_block_cap": info.zblocks,
+                     "x_nontemporal_stores": info.xnt},
+        "padded_lengths": [info.lx, info.ly, info.lz],
         "model_bytes_per_solve": info.model_bytes,
         "model_GBps_whole_solve": info.model_bytes / (ms_step * 1e-3) / 1e9,
         "hbm_frac_whole_solve": info.model_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -415,6 +417,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--mesh", default=None,
+                    help="NXxNYxNZ: time a smooth bunch on this mesh instead of the benchmark charge "
+                         "(profiling other sizes; implies --no-batch and --no-cpu-baseline)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -432,10 +437,17 @@ def main():
 
     from paper_1111_4971_amd import pipe, workloads
     pipe.lib()
-    log("[bench] generating the 128x128x512 three-bunch CIC charge")
-    t = time.perf_counter()
-    wl = workloads.three_bunch_cic()
-    log("[bench] generated in %.1f s (%d macroparticles)" % (time.perf_counter() - t, wl.notes["n_particles"]))
+    if args.mesh:
+        nx, ny, nz = (int(v) for v in args.mesh.lower().split("x"))
+        wl = workloads.gaussian_bunch(nx, ny, nz)
+        wl.notes = {"n_particles": 0, "peak_rel_noise": 0.0}
+        args.no_batch = args.no_cpu_baseline = True
+        log("[bench] smooth bunch on %dx%dx%d" % (nx, ny, nz))
+    else:
+        log("[bench] generating the 128x128x512 three-bunch CIC charge")
+        t = time.perf_counter()
+        wl = workloads.three_bunch_cic()
+        log("[bench] generated in %.1f s (%d macroparticles)" % (time.perf_counter() - t, wl.notes["n_particles"]))
 
     legs = {}
     outs = {}
@@ -459,9 +471,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if primary == "fp32" else "f64",
         "data": "synthetic: three seeded Gaussian sub-bunches, 2^28 CIC macroparticles",
-        "config": {"workload": "three_bunch_cic 128x128x512 (padded 256x256x1024), pipe 1x1, IGF Green "
-                               "function, 256x256 modes, h=1/129, hz=20/511",
-                   "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "lx": 2 * wl.nx, "ly": 2 * wl.ny, "lz": 2 * wl.nz,
+        "config": {"workload": ("three_bunch_cic 128x128x512 (padded 256x256x1024), pipe 1x1, IGF Green "
+                                "function, 256x256 modes, h=1/129, hz=20/511") if not args.mesh else wl.name,
+                   "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "lx": legs[primary]["padded_lengths"][0],
+                   "ly": legs[primary]["padded_lengths"][1], "lz": legs[primary]["padded_lengths"][2],
                    "green": "IGF_Z", "modes": [wl.mx, wl.my], "n_particles": wl.notes["n_particles"],
                    "peak_node_rel_noise": wl.notes["peak_rel_noise"]},
         "roofline": legs[primary]["roofline"],

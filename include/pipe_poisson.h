@@ -100,6 +100,7 @@ typedef struct pipe_plan_info {
     int apad;                /* for N = 0): kz (packed-column) tile of the x pass, unused   */
     int zblocks;             /* slots per row of the y-transformed array, block cap of the  */
                              /* z passes; none of them changes a result                    */
+    int xnt;                 /* schedule: 1 if the x pass writes with non-temporal stores  */
 } pipe_plan_info_t;
 
 /*
@@ -131,13 +132,15 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
  * Every 3-D plan (here, pipe_green_plan_region, pipe_free_plan) also picks a
  * launch schedule by timing the solve on scratch buffers during the build:
  * the kz tile of the x pass (its widest or half of it), the row pitch of the
- * y-transformed array (lz/2 plus 0, 16 or 32) and the block cap of the z
- * passes (1024 or 2048).  None of these changes any result; the choice is
- * cached for the process (and in PIPE_TUNE_CACHE, "pipe-sched-v1" lines) and
- * reported in pipe_plan_info (xtile, apad, zblocks).  The environment variable
- * PIPE_SCHEDULE=fixed skips the timing (widest tile, no pad, 2048 blocks);
- * PIPE_SCHEDULE=T,pad,cap forces a schedule (INVALID_ARG if T is neither the
- * widest tile nor half of it, or pad is outside [0, 256]).
+ * y-transformed array (lz/2 plus 0, 16 or 32), the block cap of the z
+ * passes (1024, 2048 or 4096) and whether the x pass writes with non-temporal
+ * stores.  None of these changes any result; the choice is cached for the
+ * process (and in PIPE_TUNE_CACHE, "pipe-sched-v2" lines) and reported in
+ * pipe_plan_info (xtile, apad, zblocks, xnt).  The environment variable
+ * PIPE_SCHEDULE=fixed skips the timing (widest tile, no pad, 2048 blocks,
+ * plain stores); PIPE_SCHEDULE=T,pad,cap[,nt] forces a schedule (INVALID_ARG
+ * if T is neither the widest tile nor half of it, pad is outside [0, 256] or
+ * nt is not 0 or 1; non-temporal stores are an FP64 option only).
  * With PIPE_AUTOTUNE in kind and all lengths 0, the plan times the five
  * passes for each candidate factorisation per dimension (the smallest
  * supported length >= 2n, the smallest even one, the smallest power of two,

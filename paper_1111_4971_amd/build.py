@@ -17,8 +17,8 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpipe.so")
 # (source, unit): the kernel files are compiled as two units each, FP32 kernels
 # with the precision-independent code (PIPE_TU=1) and FP64 kernels (PIPE_TU=2)
-SOURCES = [("passes.hip", 1), ("passes.hip", 2), ("band.hip", 1), ("band.hip", 2), ("fft3d.hip", 1),
-           ("fft3d.hip", 2), ("green.hip", 0), ("pipe_api.cpp", 0)]
+SOURCES = [("xprod.hip", 1), ("xprod.hip", 2), ("passes.hip", 1), ("passes.hip", 2), ("band.hip", 1),
+           ("band.hip", 2), ("fft3d.hip", 1), ("fft3d.hip", 2), ("green.hip", 0), ("pipe_api.cpp", 0)]
 ARCH = os.environ.get("PIPE_OFFLOAD_ARCH", "gfx950")
 
 

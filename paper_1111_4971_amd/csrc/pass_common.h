@@ -82,6 +82,24 @@ template <typename T> using gptr = T*;
 #endif
 template <typename T> __device__ __forceinline__ gptr<T> to_global(T* p) { return (gptr<T>)p; }
 
+// Store of a pass's output element; NT: as a non-temporal store (the
+// fused x pass can take this as part of its plan's schedule: it keeps the
+// written rows from displacing the spectra and rows other blocks still read).
+template <bool NT = false, typename C> __device__ __forceinline__ void out_store(gptr<C> p, C v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (NT) {
+        using R = decltype(C::x);
+        typedef R V2 __attribute__((ext_vector_type(2)));
+        V2 w;
+        w.x = v.x;
+        w.y = v.y;
+        __builtin_nontemporal_store(w, reinterpret_cast<__attribute__((address_space(1))) V2*>(p));
+        return;
+    }
+#endif
+    *p = v;
+}
+
 // Copy n twiddles into LDS (no barrier: every use follows a later barrier).
 template <typename C>
 __device__ __forceinline__ const C* stage_twiddles(C* s_tw, const C* __restrict__ tw, int n) {

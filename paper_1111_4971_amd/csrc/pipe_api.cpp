@@ -200,6 +200,7 @@ struct pipe_plan_s {
     int tile = 0;            // kz tile of the table layout (and of the fused x pass)
     int apad = 0;            // schedule: unused slots per row of the y-transformed array
     int zcap = 2048;         // schedule: block cap of the persistent z passes
+    int xnt = 0;             // schedule: the x pass writes its rows with non-temporal stores
     int nval = 9;            // values per orbit: 9 (four terms), 1 (free space: T_cc only)
     int band = -1;           // banded plan: planes kept each side of the z sum (Eq. 18); -1 = 3-D plan
     double g0 = 0;           // free-space plans: G at zero separation
@@ -520,7 +521,7 @@ pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, h
     HIP_TRY(launch_strided<real>(ly, false, A1, A2, ny, ly, nh, (long)nx * pa, nh, (long)ny * nh, pa, nx, tw, st),
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
-    HIP_TRY(launch_xprod<real>(p->lx, adjoint, A2, nx, ly, nh, pa, p->tile, (const real*)p->table,
+    HIP_TRY(launch_xprod<real>(p->lx, adjoint, A2, nx, ly, nh, pa, p->tile, p->xnt != 0, (const real*)p->table,
                                (const real*)p->nyq, tw, st, nullptr, 1, false, p->nval),
             "x pass with spectral product");
     if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event");
@@ -920,10 +921,11 @@ pipe_status_t autotune_lengths(pipe_plan_s* tmpl, int members, hipStream_t st, i
 // the kz tile of the fused x pass (its widest T or T/2), the row pitch of the
 // y-transformed array (lz/2 plus 0, 16 or 32 unused slots: its rows are read
 // and written at a stride of pitch values by the fused and y passes), and the
-// block cap of the persistent z passes (1024 or 2048).  Each plan times
-// the (tile, pitch) pairs, then the two caps, on scratch buffers, and keeps the
+// block cap of the persistent z passes (1024, 2048 or 4096), and whether the
+// fused x pass writes its rows with non-temporal stores.  Each plan times the
+// (tile, pitch) pairs, then the caps and the stores, on scratch buffers, and keeps the
 // fastest; the choice is cached like the lengths.  PIPE_SCHEDULE=fixed uses
-// (widest T, no pad, 2048); PIPE_SCHEDULE=T,pad,cap forces one.
+// (widest T, no pad, 2048, plain stores); PIPE_SCHEDULE=T,pad,cap[,nt] forces one.
 
 struct SchedKey {
     std::string arch;
@@ -933,12 +935,14 @@ struct SchedKey {
                std::tie(o.arch, o.nx, o.ny, o.nz, o.lx, o.ly, o.lz, o.rb, o.nval, o.members);
     }
 };
-std::map<SchedKey, std::array<int, 3>> g_sched;
+std::map<SchedKey, std::array<int, 4>> g_sched;
 std::string g_sched_loaded;
 
-bool schedule_ok(int lx, int rb, const std::array<int, 3>& v) {
+bool schedule_ok(int lx, int rb, const std::array<int, 4>& v) {
     const int T = xprod_tile(lx, rb);
-    return (v[0] == T || (T > 1 && v[0] == T / 2)) && v[1] >= 0 && v[1] <= 256 && v[2] >= 1 && v[2] <= 65536;
+    // non-temporal x-pass stores exist in FP64 only
+    return (v[0] == T || (T > 1 && v[0] == T / 2)) && v[1] >= 0 && v[1] <= 256 && v[2] >= 1 && v[2] <= 65536 &&
+           (v[3] == 0 || (v[3] == 1 && rb == 8));
 }
 
 void sched_cache_load() {
@@ -950,9 +954,9 @@ void sched_cache_load() {
     char line[512], arch[128];
     while (fgets(line, sizeof line, f)) {
         SchedKey k;
-        std::array<int, 3> v;
-        if (sscanf(line, "pipe-sched-v1 %127s %d %d %d %d %d %d %d %d %d %d %d %d", arch, &k.nx, &k.ny, &k.nz, &k.lx,
-                   &k.ly, &k.lz, &k.rb, &k.nval, &k.members, &v[0], &v[1], &v[2]) != 13)
+        std::array<int, 4> v;
+        if (sscanf(line, "pipe-sched-v2 %127s %d %d %d %d %d %d %d %d %d %d %d %d %d", arch, &k.nx, &k.ny, &k.nz,
+                   &k.lx, &k.ly, &k.lz, &k.rb, &k.nval, &k.members, &v[0], &v[1], &v[2], &v[3]) != 14)
             continue;
         k.arch = arch;
         if (schedule_ok(k.lx, k.rb, v)) g_sched[k] = v;
@@ -960,29 +964,33 @@ void sched_cache_load() {
     fclose(f);
 }
 
-void sched_cache_store(const SchedKey& k, const std::array<int, 3>& v) {
+void sched_cache_store(const SchedKey& k, const std::array<int, 4>& v) {
     const char* path = getenv("PIPE_TUNE_CACHE");
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "pipe-sched-v1 %s %d %d %d %d %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.nx, k.ny, k.nz, k.lx, k.ly,
-            k.lz, k.rb, k.nval, k.members, v[0], v[1], v[2]);
+    fprintf(f, "pipe-sched-v2 %s %d %d %d %d %d %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.nx, k.ny, k.nz, k.lx,
+            k.ly, k.lz, k.rb, k.nval, k.members, v[0], v[1], v[2], v[3]);
     fclose(f);
 }
 
-// Sets p->tile, p->apad, p->zcap (p's lengths and sizes already set).
+// Sets p->tile, p->apad, p->zcap, p->xnt (p's lengths and sizes already set).
 pipe_status_t tune_schedule(pipe_plan_s* p, int members, hipStream_t st) {
     const int T = xprod_tile(p->lx, p->rb);
-    std::array<int, 3> v{T, 0, 2048};
+    std::array<int, 4> v{T, 0, 2048, 0};
+    auto apply = [&] {
+        p->tile = v[0]; p->apad = v[1]; p->zcap = v[2]; p->xnt = v[3];
+    };
     if (const char* f = getenv("PIPE_SCHEDULE")) {
         if (!strcmp(f, "fixed")) {
-            p->tile = v[0]; p->apad = v[1]; p->zcap = v[2];
+            apply();
             return PIPE_OK;
         }
-        if (sscanf(f, "%d,%d,%d", &v[0], &v[1], &v[2]) != 3 || !schedule_ok(p->lx, p->rb, v))
-            return fail(PIPE_ERR_INVALID_ARG, "PIPE_SCHEDULE must be 'fixed' or 'T,pad,cap' with T %d or %d, "
-                        "0 <= pad <= 256, cap >= 1 (got '%s')", T, T / 2, f);
-        p->tile = v[0]; p->apad = v[1]; p->zcap = v[2];
+        const int got = sscanf(f, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]);
+        if ((got != 3 && got != 4) || !schedule_ok(p->lx, p->rb, v))
+            return fail(PIPE_ERR_INVALID_ARG, "PIPE_SCHEDULE must be 'fixed' or 'T,pad,cap[,nt]' with T %d or %d, "
+                        "0 <= pad <= 256, cap >= 1, nt 0 or 1 (1 in FP64 only) (got '%s')", T, T / 2, f);
+        apply();
         return PIPE_OK;
     }
     const SchedKey key{device_arch(p->device), p->nx, p->ny, p->nz, p->lx, p->ly, p->lz, p->rb, p->nval, members};
@@ -991,17 +999,18 @@ pipe_status_t tune_schedule(pipe_plan_s* p, int members, hipStream_t st) {
         sched_cache_load();
         auto it = g_sched.find(key);
         if (it != g_sched.end()) {
-            p->tile = it->second[0]; p->apad = it->second[1]; p->zcap = it->second[2];
+            v = it->second;
+            apply();
             return PIPE_OK;
         }
     }
-    // (tile, pad) pairs first, then the z cap with the best pair
+    // (tile, pad) pairs first, then the z cap and the x-pass stores with the best pair
     std::vector<pipe_plan_s> cands;
     for (int t : {T, T / 2}) {
         if (t < 1 || (t == T / 2 && T == 1)) continue;
         for (int pad : {0, 16, 32}) {
             pipe_plan_s q = *p;
-            q.tile = t; q.apad = pad; q.zcap = 2048;
+            q.tile = t; q.apad = pad; q.zcap = 2048; q.xnt = 0;
             cands.push_back(q);
         }
     }
@@ -1009,13 +1018,21 @@ pipe_status_t tune_schedule(pipe_plan_s* p, int members, hipStream_t st) {
     pipe_status_t rs = time_candidates(cands, members, st, ms);
     if (rs != PIPE_OK) return rs;
     size_t bi = std::min_element(ms.begin(), ms.end()) - ms.begin();
-    v = {cands[bi].tile, cands[bi].apad, 2048};
-    std::vector<pipe_plan_s> caps(1, cands[bi]);
-    caps[0].zcap = 1024;
+    v = {cands[bi].tile, cands[bi].apad, 2048, 0};
+    double best = ms[bi];
+    std::vector<pipe_plan_s> more(p->rb == 8 ? 3 : 2, cands[bi]);
+    more[0].zcap = 1024;
+    more[1].zcap = 4096;
+    if (p->rb == 8) more[2].xnt = 1;
     std::vector<double> ms2;
-    if ((rs = time_candidates(caps, members, st, ms2)) != PIPE_OK) return rs;
-    if (ms2[0] < ms[bi]) v[2] = 1024;
-    p->tile = v[0]; p->apad = v[1]; p->zcap = v[2];
+    if ((rs = time_candidates(more, members, st, ms2)) != PIPE_OK) return rs;
+    for (int i = 0; i < 2; ++i)
+        if (ms2[i] < best) {
+            best = ms2[i];
+            v[2] = more[i].zcap;
+        }
+    if (p->rb == 8 && ms2[2] < ms[bi]) v[3] = 1;   // judged against the same z cap
+    apply();
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_sched[key] = v;
     sched_cache_store(key, v);
@@ -1294,6 +1311,7 @@ pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     out->xtile = p->band >= 0 ? (p->band == 0 ? p->band_tile0 : 0) : p->tile;
     out->apad = p->band >= 0 ? 0 : p->apad;
     out->zblocks = p->band >= 0 ? 0 : p->zcap;
+    out->xnt = p->band >= 0 ? 0 : p->xnt;
     return PIPE_OK;
 }
 
@@ -1540,8 +1558,8 @@ pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al
     HIP_TRY(launch_strided<real>(ly, false, nullptr, nullptr, ny, ly, nh, (long)nx * pa, nh, (long)ny * nh, pa, nx,
                                  tw, st, args + n, n),
             "grouped y forward pass");
-    HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, pa, p->tile, nullptr, nullptr, tw, st,
-                               args + 2 * n, n, shared_table, p->nval),
+    HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, pa, p->tile, p->xnt != 0, nullptr, nullptr, tw,
+                               st, args + 2 * n, n, shared_table, p->nval),
             "grouped x pass with spectral product");
     HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, (long)nx * pa, nh, nh, pa, (long)ny * nh, nx,
                                  tw, st, args + 3 * n, n),
@@ -1575,7 +1593,7 @@ pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_
             pipe_plan_s* r = b->groups[k].rep;
             if (!b->groups[k].banded && r->nx == p->nx && r->ny == p->ny && r->nz == p->nz && r->lx == p->lx &&
                 r->ly == p->ly && r->lz == p->lz && r->nval == p->nval && r->tile == p->tile &&
-                r->apad == p->apad && r->zcap == p->zcap)
+                r->apad == p->apad && r->zcap == p->zcap && r->xnt == p->xnt)
                 g = (int)k;
         }
         if (g < 0) {

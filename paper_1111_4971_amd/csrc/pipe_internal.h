@@ -91,8 +91,9 @@ template <typename real>
 // nval: values per orbit in the table, 9 (four terms) or 1 (T_cc only: free space).
 // pitch: row stride of the (ly, nx, pitch) array, >= nh; tile: the kz tile,
 // xprod_tile(lx, .) or half of it (the table must be laid out for that tile).
+// nt_store: write the output rows with non-temporal stores.
 hipError_t launch_xprod(int lx, bool adjoint, void* data, int nx, int ly, int nh, long pitch, int tile,
-                        const real* table, const real* nyq, const TwiddleBank& tw, hipStream_t s,
+                        bool nt_store, const real* table, const real* nyq, const TwiddleBank& tw, hipStream_t s,
                         const GroupArgs* group = nullptr, int ngroup = 1, bool shared_table = false,
                         int nval = 9);
 

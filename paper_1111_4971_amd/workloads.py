@@ -266,3 +266,15 @@ def accuracy_study_bunch(n, nz, sigma_z, a=4.0, kind=IGF_Z, modes=20):
     wl = Workload("accuracy_study_n%d_nz%d_sz%g" % (n, nz, sigma_z), n, n, nz, hx, hy, hz, a, b, kind,
                   modes, modes, rho)
     return wl, (n // 2 - 1, n // 2 - 1)
+
+
+def gaussian_bunch(nx, ny, nz, modes=256, seed=6):
+    """A smooth bunch on any mesh, for timing and profiling other sizes than the
+    benchmark's: pipe 1 x 1, h = 1/(n+1), z over +-10 (hz = 20/(nz-1)), IGF,
+    modes min(2n, `modes`) per dimension; Gaussian at (0.5, 0.45, 0.3) with
+    sigma (0.1, 0.12, 2.0), unit charge plus 1e-3 uniform noise (seeded)."""
+    hx, hy, hz = 1.0 / (nx + 1), 1.0 / (ny + 1), 20.0 / (nz - 1)
+    rho = gaussian(nx, ny, nz, hx, hy, hz, (0.5, 0.45, 0.3), (0.1, 0.12, 2.0))
+    rho = _add_noise(_unit_charge(rho, hx, hy, hz), np.random.default_rng(seed))
+    return Workload("gaussian_bunch_%dx%dx%d" % (nx, ny, nz), nx, ny, nz, hx, hy, hz, 1.0, 1.0, IGF_Z,
+                    min(2 * nx, modes), min(2 * ny, modes), rho)

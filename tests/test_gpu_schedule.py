@@ -48,13 +48,15 @@ def test_every_forced_schedule_matches_eq10_oracle(torch_cuda, monkeypatch, shap
     tiles = [T, T // 2] if T > 1 else [T]
     for t in tiles:
         for pad in (0, 16, 32):
-            for cap in (1, 7, 2048):
-                monkeypatch.setenv("PIPE_SCHEDULE", "%d,%d,%d" % (t, pad, cap))
-                log("schedule %s %s T=%d pad=%d cap=%d" % (prec, shape, t, pad, cap))
+            for cap, nt in ((1, 0), (7, 1), (2048, 0), (4096, 1)):
+                if prec == "fp32":
+                    nt = 0          # non-temporal stores are an FP64 option
+                monkeypatch.setenv("PIPE_SCHEDULE", "%d,%d,%d,%d" % (t, pad, cap, nt))
+                log("schedule %s %s T=%d pad=%d cap=%d nt=%d" % (prec, shape, t, pad, cap, nt))
                 plan = _mk(shape, prec)
-                assert (plan.info.xtile, plan.info.apad, plan.info.zblocks) == (t, pad, cap)
+                assert (plan.info.xtile, plan.info.apad, plan.info.zblocks, plan.info.xnt) == (t, pad, cap, nt)
                 got = gpu_solve(plan, rho)
-                assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (t, pad, cap)
+                assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (t, pad, cap, nt)
                 plan.close()
 
 
@@ -67,6 +69,12 @@ def test_bad_forced_schedule_is_rejected(torch_cuda, monkeypatch):
     monkeypatch.setenv("PIPE_SCHEDULE", "8,-1,2048")
     with pytest.raises(pipe.PipeError):
         _mk((13, 11, 40), "fp32")
+    monkeypatch.setenv("PIPE_SCHEDULE", "8,0,2048,2")
+    with pytest.raises(pipe.PipeError):
+        _mk((13, 11, 40), "fp32")
+    monkeypatch.setenv("PIPE_SCHEDULE", "8,0,2048,1")     # an FP64-only option
+    with pytest.raises(pipe.PipeError):
+        _mk((13, 11, 40), "fp32")
 
 
 def test_timed_schedule_is_cached_and_adjoint_agrees(torch_cuda, monkeypatch):
@@ -77,7 +85,7 @@ def test_timed_schedule_is_cached_and_adjoint_agrees(torch_cuda, monkeypatch):
     p2 = _mk(shape, "fp32")
     s1 = (p1.info.xtile, p1.info.apad, p1.info.zblocks)
     assert s1 == (p2.info.xtile, p2.info.apad, p2.info.zblocks)
-    assert p1.info.apad in (0, 16, 32) and p1.info.zblocks in (1024, 2048)
+    assert p1.info.apad in (0, 16, 32) and p1.info.zblocks in (1024, 2048, 4096)
     rho = np.random.default_rng(4).standard_normal(shape)
     got = gpu_solve(p1, rho)
     ref = _ref(shape, rho, "fp32")
@@ -93,7 +101,7 @@ def test_batch_groups_plans_by_schedule(torch_cuda, monkeypatch):
     from paper_1111_4971_amd import pipe
     shape = (20, 18, 50)
     plans = []
-    for sched in ("8,0,2048", "8,16,1024", "4,32,7", "8,0,2048"):
+    for sched in ("8,0,2048", "8,16,1024,0", "4,32,7", "8,0,2048,0"):
         monkeypatch.setenv("PIPE_SCHEDULE", sched)
         plans.append(_mk(shape, "fp32"))
     rng = np.random.default_rng(6)
