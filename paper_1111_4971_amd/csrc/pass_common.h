@@ -54,20 +54,34 @@ constexpr int ce_max(int a, int b) { return a > b ? a : b; }
     X(8) X(12) X(16) X(24) X(32) X(36) X(48) X(64) X(72) X(96) X(108) X(128) X(144) X(192) X(216)       \
     X(256) X(288) X(384) X(432) X(512) X(576) X(768) X(864) X(1024)
 
-// Plan of the y passes: FP64 takes the narrow variant where the default plan
-// holds more than 8 values per thread (a block of ~256 threads then needs
-// 256 E complex values of LDS).
-template <typename real, int N> constexpr int strided_V() {
-    return narrow_variant<N>(sizeof(real) == 8 ? 8 : 24);
-}
-// Column tile of the y passes: PIPE_STRIDED_TMAX columns per row segment,
-// halved until the block's LDS (slabs x N x T complex) fits in PIPE_LDS_CAP.
-template <typename real, int N> constexpr int strided_T() {
-    constexpr int P = N / Plan<N, strided_V<real, N>()>::E;
+// Column tile of the y passes for plan variant V: PIPE_STRIDED_TMAX columns per
+// row segment, halved until the block's LDS (slabs x N x T complex) fits in
+// PIPE_LDS_CAP and its P x T threads (P = N / E per line) fit in 1024.
+template <typename real, int N, int V> constexpr int strided_T_of() {
+    constexpr int P = N / Plan<N, V>::E;
     int t = PIPE_STRIDED_TMAX;
-    while (t > 1 && ce_max(1, 256 / (P * t)) * N * t * (int)sizeof(real) * 2 > PIPE_LDS_CAP) t /= 2;
+    while (t > 1 && (ce_max(1, 256 / (P * t)) * N * t * (int)sizeof(real) * 2 > PIPE_LDS_CAP || P * t > 1024)) t /= 2;
     return t;
 }
+// Plan of the y passes: the narrow variant where the default plan holds more
+// than 8 values per thread in FP64, and in FP32 where it holds more than 16
+// and the narrow plan keeps the same column tile.  A block's LDS tile is N x T
+// complex values whatever the plan, so fewer values per thread means more
+// waves on the same tile (FP32 432: 5 -> 9 waves per block, y passes 0.33 ->
+// 0.39 of HBM peak; 324: 0.42 -> 0.52); the 16-value power-of-two plans stay,
+// their narrow variants measured 5 % slower.
+template <typename real, int N> constexpr int strided_V() {
+    if constexpr (sizeof(real) == 8) {
+        return narrow_variant<N>(8);
+    } else {
+        constexpr int v = narrow_variant<N>(16);
+        if constexpr (v != 0) {
+            if constexpr (strided_T_of<real, N, v>() >= strided_T_of<real, N, 0>()) return v;
+        }
+        return 0;
+    }
+}
+template <typename real, int N> constexpr int strided_T() { return strided_T_of<real, N, strided_V<real, N>()>(); }
 
 // Pointer into device global memory.  Buffers taken from a grouped launch's
 // descriptor array arrive as generic pointers, which compile to flat memory

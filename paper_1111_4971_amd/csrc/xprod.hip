@@ -17,6 +17,17 @@ namespace pipe {
 
 template <typename real> using C_of = cplx<real>;
 
+// Length plan of the fused x pass: the narrow variant where the default plan
+// holds more than 16 values per thread (8 in FP64): more threads on the same
+// LDS tile and fewer registers per thread.
+template <typename real, int N> constexpr int xprod_V() { return narrow_variant<N>(sizeof(real) == 8 ? 8 : 16); }
+
+// Waves per SIMD the register allocation must allow (1: no constraint).  The
+// FP32 length-512 pass needs 66 registers left alone, which fits one
+// 1024-thread block per CU although the LDS holds two; at 64 registers two fit
+// (measured: 1049 -> 913 us at 256x256x1024, no spills at T = 8).
+template <typename real, int N> constexpr int xprod_waves() { return (sizeof(real) == 4 && N == 512) ? 8 : 1; }
+
 // P3: for one ky pair (ky, ly-ky) and T consecutive kz: forward x transform of
 // the nx nonzero rows, the mixed product on each orbit {+-kx} x {+-ky} (see
 // orbit_product), inverse x transform, rows i < nx written back in place.  The
@@ -27,7 +38,7 @@ template <typename real> using C_of = cplx<real>;
 // (Plan<N, V>: the variant with fewer values per thread gives FP64 more
 // threads for the same LDS tile).
 template <typename real, int N, int V, int T, bool ADJ, int NV, bool NTS>
-__global__ __launch_bounds__(2 * (N / Plan<N, V>::E) * T)
+__global__ __launch_bounds__(2 * (N / Plan<N, V>::E) * T) __attribute__((amdgpu_waves_per_eu(xprod_waves<real, N>())))
 void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, long xs, const real* __restrict__ table,
                   const real* __restrict__ nyq, const twid<real>* __restrict__ tw,
                   const GroupArgs* __restrict__ group, int shared_table) {
@@ -193,11 +204,6 @@ void xprod_kernel(cplx<real>* data, int nx, int ly, int nh, long xs, const real*
         },
         view);
 }
-
-// Length plan of the fused x pass: the narrow variant where the default plan
-// holds more than 16 values per thread (8 in FP64): more threads on the same
-// LDS tile and fewer registers per thread.
-template <typename real, int N> constexpr int xprod_V() { return narrow_variant<N>(sizeof(real) == 8 ? 8 : 16); }
 
 // kz tile of the fused x pass: 2 lines x lx x T complex values in LDS.
 template <typename real, int N> constexpr int xprod_T() {
