@@ -111,7 +111,7 @@ typedef struct pipe_plan_info {
  * nx, ny, nz >= 1 nodes; hx, hy, hz > 0 spacings; a, b > 0 pipe widths with
  * nx*hx <= a and ny*hy <= b (1e-12 relative slack, so a node may sit on a
  * wall).  kind = PIPE_GREEN_* | PIPE_PREC_*.  Modes default to mx = 2nx,
- * my = 2ny and padded lengths to the smallest supported even L >= 2n.
+ * my = 2ny and padded lengths as pipe_green_plan_ex describes.
  * Blocks until the plan is built.  *out receives an opaque handle owned by
  * the caller (free with pipe_plan_destroy).
  * Errors: INVALID_ARG, UNSUPPORTED_SIZE, NO_DEVICE, OUT_OF_MEMORY, HIP.
@@ -125,8 +125,13 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
  * at least 2n - 1 (Appendix: N >= M = J + K - 1, else INVALID_ARG); lx and ly
  * must be of the form 2^p 3^q in [8, 1024] (odd ones included), and lz must be
  * even with lz/2 of that form (z is transformed real-to-complex as lz/2 packed
- * pairs), i.e. lz in [16, 2048]; otherwise UNSUPPORTED_SIZE.  The default is
- * the smallest such length >= 2n (lz: lz/2 >= nz).  The physical result does
+ * pairs), i.e. lz in [16, 2048]; otherwise UNSUPPORTED_SIZE.  The default
+ * (length 0) is, per dimension, the supported length >= 2n (lz: lz/2 >= nz)
+ * with the lowest modelled pass time among those within 20 % of the smallest
+ * one: a table of the HBM-peak fraction each length's passes reached on
+ * MI355X, so a slow factorisation (432 = 27 * 16) gives way to a fast one
+ * (512) when that is quicker overall; below 64 it is the smallest length.
+ * The physical result does
  * not depend on the padded lengths.  hip_stream (a hipStream_t, may be NULL) orders the build's GPU
  * work; the call still returns only when the build has finished.
  * Every 3-D plan (here, pipe_green_plan_region, pipe_free_plan) also picks a
@@ -142,9 +147,9 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
  * if T is neither the widest tile nor half of it, pad is outside [0, 256] or
  * nt is not 0 or 1; non-temporal stores are an FP64 option only).
  * With PIPE_AUTOTUNE in kind and all lengths 0, the plan times the five
- * passes for each candidate factorisation per dimension (the smallest
- * supported length >= 2n, the smallest even one, the smallest power of two,
- * the smallest 3 * 2^k)
+ * passes for each candidate factorisation per dimension (the default above,
+ * the smallest supported length >= 2n, the smallest even one, the smallest
+ * power of two, the smallest 3 * 2^k)
  * on scratch buffers and keeps the fastest: one solve at a time (latency)
  * with PIPE_AUTOTUNE, one grouped launch of 16 concurrent solves (throughput,
  * the batched form) with PIPE_AUTOTUNE_BATCH.  The choice is cached for the

@@ -178,6 +178,66 @@ int pick_length(int need) {
     return -1;
 }
 
+// Fraction of the HBM peak the passes of one length reached on MI355X, with
+// the mesh padded exactly to that length (x and y: n = L/2 rows, nz = 256, the
+// y passes and the fused x pass together; z: a 128 x 128 mesh, nz = L, both z
+// passes), FP32 and FP64.  Plans with more stages and more values per thread
+// (27 * 2^k, 9 * 2^k) run well below their neighbours.
+struct LengthEff {
+    int n;
+    float xy32, xy64, z32, z64;
+};
+constexpr LengthEff kLengthEff[] = {
+    {64, 0.155, 0.256, 0.199, 0.299},
+    {72, 0.148, 0.229, 0.161, 0.256},
+    {81, 0.200, 0.316, 0.193, 0.306},
+    {96, 0.220, 0.340, 0.202, 0.321},
+    {108, 0.240, 0.327, 0.193, 0.275},
+    {128, 0.368, 0.530, 0.298, 0.392},
+    {144, 0.335, 0.481, 0.222, 0.319},
+    {162, 0.334, 0.476, 0.257, 0.363},
+    {192, 0.460, 0.570, 0.295, 0.404},
+    {216, 0.318, 0.396, 0.242, 0.344},
+    {243, 0.519, 0.564, 0.282, 0.397},
+    {256, 0.624, 0.646, 0.386, 0.522},
+    {288, 0.434, 0.508, 0.270, 0.380},
+    {324, 0.435, 0.505, 0.246, 0.372},
+    {384, 0.488, 0.526, 0.327, 0.425},
+    {432, 0.329, 0.409, 0.286, 0.373},
+    {486, 0.380, 0.386, 0.328, 0.409},
+    {512, 0.594, 0.606, 0.476, 0.536},
+    {576, 0.390, 0.469, 0.298, 0.413},
+    {648, 0.361, 0.441, 0.266, 0.360},
+    {729, 0.434, 0.403, 0.386, 0.404},
+    {768, 0.451, 0.484, 0.358, 0.383},
+    {864, 0.272, 0.302, 0.286, 0.370},
+    {972, 0.303, 0.291, 0.292, 0.352},
+    {1024, 0.490, 0.451, 0.485, 0.517},
+};
+
+// Default padded length: among the supported lengths >= need and within 20 %
+// of the smallest such length, the one with the lowest modelled pass time.
+// x, y: time ~ L / eff_xy(L).  z (half = true, lengths are NH = lz/2): every
+// pass scales with NH, the z passes carry about a sixth of a solve's bytes, so
+// time ~ NH (1/6 / eff_z(NH) + 5/6 / 0.55).  Below length 64 (latency-bound
+// meshes, not modelled) the smallest length is taken.
+int pick_modelled_length(int need, bool half, bool fp64) {
+    const int first = pick_length(need);
+    if (first < 64) return first;
+    int best = first;
+    double best_cost = 0.0;
+    for (const LengthEff& e : kLengthEff) {
+        if (e.n < first || e.n > first + first / 5) continue;
+        const double eff = half ? (fp64 ? e.z64 : e.z32) : (fp64 ? e.xy64 : e.xy32);
+        const double cost = half ? e.n * (1.0 / 6.0 / eff + 5.0 / 6.0 / 0.55) : e.n / eff;
+        if (best_cost == 0.0 || cost < best_cost) {
+            best = e.n;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 int pick_band_length(int need) {
     for (int v : kBandLengths)
         if (v >= need) return v;
@@ -282,7 +342,7 @@ pipe_status_t validate(int nx, int ny, int nz, double hx, double hy, double hz, 
     // padded lengths
     auto choose = [&](int n, int* L, bool half, const char* nm) -> pipe_status_t {
         if (*L == 0) {
-            const int h = pick_length(half ? n : 2 * n);
+            const int h = pick_modelled_length(half ? n : 2 * n, half, pr == PIPE_PREC_FP64);
             if (h < 0) return fail(PIPE_ERR_UNSUPPORTED_SIZE, "%s: no supported padded length for n = %d", nm, n);
             *L = half ? 2 * h : h;
             return PIPE_OK;
@@ -750,9 +810,10 @@ std::string device_arch(int dev) {
 }
 
 // supported lengths >= need: the smallest, the smallest even one, the smallest
-// power of two and the smallest 3 * 2^k (each a different radix plan)
-std::vector<int> length_candidates(int need) {
-    std::vector<int> out;
+// power of two, the smallest 3 * 2^k (each a different radix plan) and the
+// modelled default
+std::vector<int> length_candidates(int need, bool half, bool fp64) {
+    std::vector<int> out{pick_modelled_length(need, half, fp64)};
     int best = -1, even = -1, pow2 = -1, three = -1;
     for (int v : kFftLengths) {
         if (v < need) continue;
@@ -881,8 +942,9 @@ pipe_status_t autotune_lengths(pipe_plan_s* tmpl, int members, hipStream_t st, i
             return PIPE_OK;
         }
     }
-    const std::vector<int> cx = length_candidates(2 * tmpl->nx), cy = length_candidates(2 * tmpl->ny),
-                           cz = length_candidates(tmpl->nz);
+    const bool f64 = tmpl->rb == 8;
+    const std::vector<int> cx = length_candidates(2 * tmpl->nx, false, f64),
+                           cy = length_candidates(2 * tmpl->ny, false, f64), cz = length_candidates(tmpl->nz, true, f64);
     std::vector<pipe_plan_s> cands;
     for (int a : cx)
         for (int b : cy)

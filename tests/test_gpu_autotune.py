@@ -29,9 +29,9 @@ def test_autotuned_lengths_same_result_and_cached(tmp_path):
     log("autotune: tuned plan")
     tuned = pipe.GreenPlan(nx, ny, nz, hx, hy, hz, a, b, kind=pipe.IGF_Z, precision="fp32", autotune=True)
     i = tuned.info
-    # candidates per dimension: the smallest 2^p 3^q >= 2n, the smallest even one,
-    # the smallest power of two, the smallest 3 * 2^k (x: 96, 128; y: 81, 96, 128;
-    # z: lz/2 >= nz: 96, 128)
+    # candidates per dimension: the modelled default, the smallest 2^p 3^q >= 2n,
+    # the smallest even one, the smallest power of two, the smallest 3 * 2^k
+    # (x: 96, 128; y: 81, 96, 128; z: lz/2 >= nz: 96, 128)
     assert i.lx in (96, 128) and i.ly in (81, 96, 128) and i.lz in (192, 256)
     assert i.lx >= 2 * nx and i.ly >= 2 * ny and i.lz >= 2 * nz
     assert i.tune_ms > 0

@@ -144,9 +144,10 @@ def test_every_23_smooth_length_matches_eq10_oracle(torch_cuda, L, dim, prec):
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_default_lengths_take_the_smallest_smooth_length(torch_cuda, kind, prec):
-    """Default plans pad to the smallest 2^p 3^q >= 2n (x, y; may be odd) and
-    lz/2 >= nz: a 70 x 40 x 75 mesh gets 144 x 81 x 162 (not 192 x 96 x 192),
-    several tiles and ragged tails in every pass, against the oracle."""
+    """Where the smallest 2^p 3^q >= 2n (x, y; may be odd) and lz/2 >= nz is
+    also the fastest modelled length, default plans take it: a 70 x 40 x 75
+    mesh gets 144 x 81 x 162 (not 192 x 96 x 192), several tiles and ragged
+    tails in every pass, against the oracle."""
     from oracle import fourterm
     from paper_1111_4971_amd import pipe
     shape = (70, 40, 75)
@@ -160,6 +161,24 @@ def test_default_lengths_take_the_smallest_smooth_length(torch_cuda, kind, prec)
     got = gpu_solve(plan, rho)
     ref = fourterm.solve(oracle_input(rho, prec), hx, hy, 0.04, a, b, 2 * nx, 2 * ny, kind)
     assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (rel_l2(got, ref), rel_max(got, ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_default_lengths_skip_a_slow_factorisation(torch_cuda, prec):
+    """The length model: 27 * 16 = 432 and 216 run far below 512 and 256 per
+    element, so a 200 x 100 x 216 mesh defaults to 512 x 256 in x and y, while
+    z keeps lz/2 = 216; the result equals the solve at the smallest lengths
+    (432, 216, 432)."""
+    from paper_1111_4971_amd import pipe
+    nx, ny, nz = 200, 100, 216
+    a, b = 1.0, 1.0
+    hx, hy = a / (nx + 1), b / (ny + 1)
+    rho = np.random.default_rng(216).standard_normal((nx, ny, nz))
+    log("modelled default lengths %s" % prec)
+    plan = pipe.GreenPlan(nx, ny, nz, hx, hy, 0.05, a, b, kind=1, precision=prec, mx=24, my=24)
+    assert (plan.info.lx, plan.info.ly, plan.info.lz) == (512, 256, 432)
+    small = pipe.GreenPlan(nx, ny, nz, hx, hy, 0.05, a, b, kind=1, precision=prec, mx=24, my=24, L=(432, 216, 432))
+    assert rel_l2(gpu_solve(plan, rho), gpu_solve(small, rho)) <= 10 * TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
