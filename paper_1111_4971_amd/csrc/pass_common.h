@@ -14,12 +14,17 @@ template <typename C, int T> struct LdsCol {
     __device__ __forceinline__ void set(int e, C v) const { base[e * T] = v; }
 };
 
-// Contiguous line padded by one slot every 16 (breaks power-of-two strides).
-__device__ __forceinline__ int lpad(int e) { return e + (e >> 4); }
-template <typename C> struct LdsLine {
+// Contiguous line padded by one slot every 2^SH values (SH = 0: no padding);
+// the padding breaks the power-of-two strides of the exchanges.
+template <int SH> __device__ __forceinline__ int lpad(int e) {
+    if constexpr (SH == 0) return e;
+    else return e + (e >> SH);
+}
+template <int SH> constexpr int lpad_len(int n) { return SH == 0 ? n : n + (n >> SH) + 1; }
+template <typename C, int SH = 4> struct LdsLine {
     C* base;
-    __device__ __forceinline__ C get(int e) const { return base[lpad(e)]; }
-    __device__ __forceinline__ void set(int e, C v) const { base[lpad(e)] = v; }
+    __device__ __forceinline__ C get(int e) const { return base[lpad<SH>(e)]; }
+    __device__ __forceinline__ void set(int e, C v) const { base[lpad<SH>(e)] = v; }
 };
 
 constexpr int ce_max(int a, int b) { return a > b ? a : b; }
@@ -147,6 +152,16 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned p, unsigned total) {
 // Plan of the z passes: each thread holds two line groups (current and
 // prefetched), so plans with more than 12 values per thread (8 in FP64) take
 // the narrow variant.
+// LDS padding of the z passes' lines: one slot every 16 for power-of-two
+// lengths; none where the length has a factor 3 (its exchange strides are not
+// powers of two, and the padding itself then adds bank conflicts).
+#ifndef PIPE_Z_PAD_POW2
+#define PIPE_Z_PAD_POW2 4
+#endif
+#ifndef PIPE_Z_PAD_SMOOTH
+#define PIPE_Z_PAD_SMOOTH 0
+#endif
+template <int NH> constexpr int z_pad() { return (NH & (NH - 1)) == 0 ? PIPE_Z_PAD_POW2 : PIPE_Z_PAD_SMOOTH; }
 template <typename real, int NH> constexpr int z_V() { return narrow_variant<NH>(sizeof(real) == 8 ? 8 : 12); }
 
 template <typename real, int NH> constexpr Sync z_sync() {
@@ -156,7 +171,7 @@ template <typename real, int NH> constexpr Sync z_sync() {
 
 template <typename real, int NH> constexpr int z_lines() {
     int l = ce_max(1, PIPE_Z_THREADS / (NH / Plan<NH, z_V<real, NH>()>::E));
-    while (l > 1 && l * (NH + NH / 16 + 1) * 2 * (int)sizeof(real) > PIPE_LDS_CAP) l /= 2;
+    while (l > 1 && l * lpad_len<z_pad<NH>()>(NH) * 2 * (int)sizeof(real) > PIPE_LDS_CAP) l /= 2;
     return l;
 }
 

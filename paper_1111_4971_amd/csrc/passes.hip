@@ -120,7 +120,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     using PL = Plan<NH, z_V<real, NH>()>;
     constexpr int E = PL::E, P = NH / E, LPW = z_lines<real, NH>();
     constexpr int R0 = PL::radix(0);
-    constexpr int PADN = NH + NH / 16 + 1;
+    constexpr int PADN = lpad_len<z_pad<NH>()>(NH);
     constexpr Sync ZS = z_sync<real, NH>();
     __shared__ C lds[LPW * PADN];
     __shared__ twid<real> s_tw[NH], s_tw2[NH];
@@ -128,7 +128,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
     const int t = threadIdx.x % P, l = threadIdx.x / P;
-    LdsLine<C> view{lds + l * PADN};
+    LdsLine<C, z_pad<NH>()> view{lds + l * PADN};
     const long ngroups = (nlines + LPW - 1) / LPW;
     // stage-0 inputs of line `line` (zero beyond n_in or past the last line)
     const gptr<const real> gin = to_global(in);
@@ -197,7 +197,7 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
     }
     using PL = Plan<NH, z_V<real, NH>()>;
     constexpr int E = PL::E, P = NH / E, LPW = z_lines<real, NH>();
-    constexpr int PADN = NH + NH / 16 + 1;
+    constexpr int PADN = lpad_len<z_pad<NH>()>(NH);
     constexpr Sync ZS = z_sync<real, NH>();
     __shared__ C lds[LPW * PADN];
     __shared__ twid<real> s_tw[NH], s_tw2[NH];
@@ -205,7 +205,7 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
     tw2 = stage_twiddles(s_tw2, tw2, NH);
     if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
     const int t = threadIdx.x % P, l = threadIdx.x / P;
-    LdsLine<C> view{lds + l * PADN};
+    LdsLine<C, z_pad<NH>()> view{lds + l * PADN};
     const long ngroups = (nlines + LPW - 1) / LPW;
     // the packed bins of line `line`, element k = t + q P in slot q
     const gptr<const C> gin = to_global(in);

@@ -188,31 +188,31 @@ struct LengthEff {
     float xy32, xy64, z32, z64;
 };
 constexpr LengthEff kLengthEff[] = {
-    {64, 0.155, 0.256, 0.199, 0.299},
-    {72, 0.148, 0.229, 0.161, 0.256},
-    {81, 0.200, 0.316, 0.193, 0.306},
-    {96, 0.220, 0.340, 0.202, 0.321},
-    {108, 0.240, 0.327, 0.193, 0.275},
-    {128, 0.368, 0.530, 0.298, 0.392},
-    {144, 0.335, 0.481, 0.222, 0.319},
-    {162, 0.334, 0.476, 0.257, 0.363},
-    {192, 0.460, 0.570, 0.295, 0.404},
-    {216, 0.318, 0.396, 0.242, 0.344},
-    {243, 0.519, 0.564, 0.282, 0.397},
-    {256, 0.624, 0.646, 0.386, 0.522},
-    {288, 0.434, 0.508, 0.270, 0.380},
-    {324, 0.435, 0.505, 0.246, 0.372},
-    {384, 0.488, 0.526, 0.327, 0.425},
-    {432, 0.329, 0.409, 0.286, 0.373},
-    {486, 0.380, 0.386, 0.328, 0.409},
-    {512, 0.594, 0.606, 0.476, 0.536},
-    {576, 0.390, 0.469, 0.298, 0.413},
-    {648, 0.361, 0.441, 0.266, 0.360},
-    {729, 0.434, 0.403, 0.386, 0.404},
-    {768, 0.451, 0.484, 0.358, 0.383},
-    {864, 0.272, 0.302, 0.286, 0.370},
-    {972, 0.303, 0.291, 0.292, 0.352},
-    {1024, 0.490, 0.451, 0.485, 0.517},
+    {64, 0.155, 0.256, 0.194, 0.299},
+    {72, 0.148, 0.229, 0.163, 0.237},
+    {81, 0.200, 0.316, 0.197, 0.303},
+    {96, 0.220, 0.340, 0.211, 0.315},
+    {108, 0.240, 0.327, 0.197, 0.289},
+    {128, 0.368, 0.530, 0.298, 0.393},
+    {144, 0.335, 0.481, 0.223, 0.285},
+    {162, 0.334, 0.476, 0.255, 0.353},
+    {192, 0.460, 0.570, 0.321, 0.399},
+    {216, 0.318, 0.396, 0.249, 0.334},
+    {243, 0.519, 0.564, 0.312, 0.393},
+    {256, 0.624, 0.646, 0.386, 0.519},
+    {288, 0.434, 0.508, 0.287, 0.373},
+    {324, 0.435, 0.505, 0.292, 0.367},
+    {384, 0.488, 0.526, 0.356, 0.439},
+    {432, 0.329, 0.409, 0.332, 0.393},
+    {486, 0.380, 0.386, 0.345, 0.433},
+    {512, 0.594, 0.606, 0.466, 0.541},
+    {576, 0.390, 0.469, 0.340, 0.409},
+    {648, 0.361, 0.441, 0.305, 0.368},
+    {729, 0.434, 0.403, 0.381, 0.400},
+    {768, 0.451, 0.484, 0.382, 0.479},
+    {864, 0.272, 0.302, 0.310, 0.373},
+    {972, 0.303, 0.291, 0.337, 0.401},
+    {1024, 0.490, 0.451, 0.464, 0.528},
 };
 
 // Default padded length: among the supported lengths >= need and within 20 %
