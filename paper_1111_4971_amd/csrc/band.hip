@@ -326,8 +326,13 @@ template <typename real, int N> constexpr int band0_T() {
 // ten coefficients of each of a thread's orbits are loaded with the rows,
 // before the forward transform (they depend on ky and kx only); the Nyquist
 // orbit kx = N/2, whose T items go to the first T threads, is staged in LDS.
+// Waves per SIMD the register allocation must allow (1: no constraint): as the
+// 3-D fused pass, the FP32 length-512 kernel fits one 1024-thread block per CU
+// at its natural 72 registers although the LDS holds two; at 64 (no spills at
+// T = 8) two fit (256x256x1024, N = 0: 472 -> 438 us).
+template <typename real, int N> constexpr int xband0_waves() { return (sizeof(real) == 4 && N == 512) ? 8 : 1; }
 template <typename real, int N, int T>
-__global__ __launch_bounds__((2 * (N / Plan<N>::E) * T))
+__global__ __launch_bounds__((2 * (N / Plan<N>::E) * T)) __attribute__((amdgpu_waves_per_eu(xband0_waves<real, N>())))
 void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz,
                    const real* __restrict__ table, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
