@@ -172,6 +172,20 @@ def batch_leg(pipe, torch, workloads, replays=20, warmup=3):
     ref = [o.double().cpu().numpy() for o in o64]
     err = max(float(np.linalg.norm(g - r) / np.linalg.norm(r)) for g, r in zip(got, ref))
     model = sum(p.info.model_bytes for p in p32)
+    # the same solves' model bytes at the smallest padded lengths the Appendix
+    # allows (L >= 2n - 1, a supported 2^p 3^q; lz even with lz/2 >= nz): one
+    # plan per shape at those lengths, few modes (the bytes do not depend on them)
+    smooth = sorted(2 ** p * 3 ** q for p in range(11) for q in range(7) if 8 <= 2 ** p * 3 ** q <= 1024)
+    least = lambda need: next(v for v in smooth if v >= need)
+    per_shape = {}
+    for w in members:
+        if w.shape not in per_shape:
+            L = (least(2 * w.nx - 1), least(2 * w.ny - 1), 2 * least(w.nz))
+            q = pipe.GreenPlan(w.nx, w.ny, w.nz, w.hx, w.hy, w.hz, w.a, w.b, kind=w.kind, precision="fp32",
+                               mx=2, my=2, L=L)
+            per_shape[w.shape] = q.info.model_bytes
+            q.close()
+    model_min = sum(per_shape[w.shape] for w in members)
     n = len(members)
     tuned = {}
     for w, p in zip(members, p32):
@@ -183,6 +197,9 @@ def batch_leg(pipe, torch, workloads, replays=20, warmup=3):
            "speedup_batched_fp32_over_sequential_fp64": t_seq64 / t_batch,
            "speedup_batched_fp32_over_sequential_fp32": t_seq32 / t_batch,
            "model_bytes_per_batch": model, "batched_model_GBps": model / t_batch / 1e9,
+           "batched_hbm_frac": model / t_batch / 8e12,
+           "model_bytes_per_batch_smallest_lengths": model_min,
+           "batched_hbm_frac_smallest_lengths": model_min / t_batch / 8e12,
            "max_member_rel_l2_fp32_vs_fp64": err}
     b.close()
     for p in p32 + p64:
