@@ -101,6 +101,12 @@ int fft_stage_exponents(int n, int variant, int* m_out) {
 // transforming the current one, so each block keeps reads in flight while it
 // computes.  Twiddles are staged into LDS once per block.
 
+#ifndef PIPE_Z_PAIR_STORE
+#define PIPE_Z_PAIR_STORE 1
+#endif
+template <typename real, int NH, int E>
+constexpr bool Z_PAIR_STORE = PIPE_Z_PAIR_STORE && sizeof(real) == 4 && NH % 2 == 0 && E % 2 == 0;
+
 // P1 / spectra z pass: real lines of n_in values (zero-padded to 2*NH) -> NH packed bins.
 // A real line x of length L = 2 NH is read as z[m] = x[2m] + i x[2m+1]; with
 // Z = DFT_NH(z) the half spectrum is
@@ -158,19 +164,31 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
         fft_line_regs<PL, false, ZS>(cur, t, tw, [&](int k, C v) { view.set(k, v); }, view);
         line_sync<ZS>();
         const long line = g * LPW + l;
+        // bin k of the half spectrum from Z[k] and Z[NH - k] (slot 0: X[0] and X[NH])
+        auto bin = [&](int k) -> C {
+            const C zk = view.get(k);
+            if (k == 0) return cmake<C>(zk.x + zk.y, zk.x - zk.y);
+            const C zn = cconj(view.get(NH - k));
+            const C A = cadd(zk, zn), B = csub(zk, zn);
+            const C wb = ctw<false>(B, tw2[k]);  // W^k B;  X = (A - i W^k B) / 2
+            return cscale(cmake<C>(A.x + wb.y, A.y - wb.x), (real)0.5);
+        };
         if (line < nlines) {
             const gptr<C> dst = gout + line * out_pitch;
+            if constexpr (Z_PAIR_STORE<real, NH, E>) {
+                // FP32, even NH: each thread writes two adjacent bins with one 16-byte store
+                // (out_pitch is NH and the buffer 16-byte aligned, so 2k lands on 16 bytes)
 #pragma unroll
-            for (int q = 0; q < E; ++q) {
-                const int k = t + q * P;
-                const C zk = view.get(k);
-                if (k == 0) {
-                    out_store(dst, cmake<C>(zk.x + zk.y, zk.x - zk.y));
-                } else {
-                    const C zn = cconj(view.get(NH - k));
-                    const C A = cadd(zk, zn), B = csub(zk, zn);
-                    const C wb = ctw<false>(B, tw2[k]);  // W^k B;  X = (A - i W^k B) / 2
-                    out_store(dst + k, cscale(cmake<C>(A.x + wb.y, A.y - wb.x), (real)0.5));
+                for (int q = 0; q < E / 2; ++q) {
+                    const int k = 2 * (t + q * P);
+                    const C x0 = bin(k), x1 = bin(k + 1);
+                    *reinterpret_cast<gptr<float4>>(dst + k) = make_float4(x0.x, x0.y, x1.x, x1.y);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    const int k = t + q * P;
+                    out_store(dst + k, bin(k));
                 }
             }
         }
