@@ -76,7 +76,7 @@ enum {
 
 typedef struct pipe_plan_info {
     int nx, ny, nz;          /* physical mesh                                               */
-    int lx, ly, lz;          /* padded transform lengths (each even, >= 2n - 1)             */
+    int lx, ly, lz;          /* padded transform lengths (each >= 2n - 1; lz even)          */
     int mx, my;              /* mode truncation m <= mx, n <= my                            */
     int kind;                /* as passed                                                   */
     int real_bytes;          /* 8 (FP64) or 4 (FP32)                                        */
@@ -230,6 +230,21 @@ pipe_status_t pipe_free_plan(int nx, int ny, int nz, double hx, double hy, doubl
 
 /* pipe_plan_info -- sizes and constants of a plan.  Errors: INVALID_ARG. */
 pipe_status_t pipe_plan_info(pipe_plan_t plan, pipe_plan_info_t* out);
+
+/*
+ * pipe_default_lengths -- the padded lengths a 3-D plan of an nx x ny x nz
+ * mesh gets when it leaves them at 0 (pipe_green_plan, pipe_green_plan_ex,
+ * pipe_green_plan_region, pipe_free_plan without PIPE_AUTOTUNE): per dimension
+ * the supported length >= 2n (lz: lz/2 >= nz) with the lowest modelled pass
+ * time among those within 20 % of the smallest such length (any padded
+ * length >= 2n - 1 gives the same potential: Appendix, after Eq. A.3).  kind:
+ * PIPE_PREC_FP32 or PIPE_PREC_FP64 (the model has one table per precision),
+ * optionally with a PIPE_GREEN_* kind, which does not change the result.
+ * *lx, *ly, *lz receive the lengths.  Host only: no GPU, no HIP call.
+ * Errors: INVALID_ARG (n < 1, other kind bits, a null output),
+ * UNSUPPORTED_SIZE (no supported length is long enough).
+ */
+pipe_status_t pipe_default_lengths(int nx, int ny, int nz, int kind, int* lx, int* ly, int* lz);
 
 /*
  * pipe_poisson_solve -- phi = A rho for the plan's mesh (Eq. 10, all four

@@ -1351,6 +1351,25 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
     return pipe_green_plan_ex(nx, ny, nz, hx, hy, hz, a, b, kind, 2 * nx, 2 * ny, 0, 0, 0, nullptr, out);
 }
 
+pipe_status_t pipe_default_lengths(int nx, int ny, int nz, int kind, int* lx, int* ly, int* lz) {
+    if (!lx || !ly || !lz) return fail(PIPE_ERR_INVALID_ARG, "lx, ly and lz must be non-null");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(PIPE_ERR_INVALID_ARG, "nx, ny, nz must be >= 1");
+    const int g = kind & 0x0f, pr = kind & ~0x0f;
+    if (g != PIPE_GREEN_POINT && g != PIPE_GREEN_IGF_Z && g != PIPE_GREEN_FREE)
+        return fail(PIPE_ERR_INVALID_ARG, "unknown Green kind %d", g);
+    if (pr != PIPE_PREC_FP64 && pr != PIPE_PREC_FP32)
+        return fail(PIPE_ERR_INVALID_ARG, "kind may hold only a Green kind and a precision flag (got 0x%x)", kind);
+    const bool f64 = pr == PIPE_PREC_FP64;
+    const int x = pick_modelled_length(2 * nx, false, f64), y = pick_modelled_length(2 * ny, false, f64),
+              h = pick_modelled_length(nz, true, f64);
+    if (x < 0 || y < 0 || h < 0)
+        return fail(PIPE_ERR_UNSUPPORTED_SIZE, "no supported padded length for %s", x < 0 ? "nx" : y < 0 ? "ny" : "nz");
+    *lx = x;
+    *ly = y;
+    *lz = 2 * h;
+    return PIPE_OK;
+}
+
 pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     if (!reg_has(p)) return fail(PIPE_ERR_INVALID_ARG, "invalid or destroyed plan handle");
     if (!out) return fail(PIPE_ERR_INVALID_ARG, "out must be non-null");

@@ -82,6 +82,7 @@ def lib():
         "pipe_free_plan": ([_I, _I, _I, _D, _D, _D, _D, _I, _I, _I, _I, _P, ctypes.POINTER(_P)], _I),
         "pipe_fft3d": ([_I, _I, _I, _I, ctypes.c_char_p, _P, _P, _P], _I),
         "pipe_plan_info": ([_P, ctypes.POINTER(PlanInfo)], _I),
+        "pipe_default_lengths": ([_I, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
         "pipe_poisson_solve": ([_P, _P, _P, _P, _P], _I),
         "pipe_poisson_adjoint": ([_P, _P, _P, _P, _P], _I),
         "pipe_poisson_solve_noalloc": ([_P, _P, _P, _P], _I),
@@ -116,6 +117,17 @@ def header_functions():
 def check(status):
     if status != 0:
         raise PipeError(status, lib().pipe_last_error().decode())
+
+
+def default_lengths(nx, ny, nz, precision="fp64"):
+    """(lx, ly, lz) a default plan of this mesh and precision gets
+    (pipe_default_lengths; host only)."""
+    if precision not in ("fp32", "fp64"):
+        raise ValueError("precision must be 'fp32' or 'fp64'")
+    out = [_I(), _I(), _I()]
+    check(lib().pipe_default_lengths(int(nx), int(ny), int(nz), PREC_FP32 if precision == "fp32" else PREC_FP64,
+                                     *[ctypes.byref(v) for v in out]))
+    return tuple(v.value for v in out)
 
 
 def _torch():

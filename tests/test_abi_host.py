@@ -326,3 +326,62 @@ def test_banded_plan_lengths(lx, expect):
     st = L.pipe_green_plan_banded(9, 4, 4, 0.1, 0.1, 0.1, 1.0, 1.0, 0.0, 0.0, 0, 8, 8, lx, 0, 1, 1e-6, None,
                                   ctypes.byref(h))
     assert st == expect, (lx, st, L.pipe_last_error())
+
+
+def _least_smooth(need, lo=8, hi=1024):
+    return next((v for v in range(max(need, lo), hi + 1) if _smooth23(v)), None)
+
+
+@needs_lib
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_default_lengths_stay_in_the_model_window(prec):
+    """Default padded lengths (host only): each a supported length >= 2n (lz/2 >=
+    nz), and within 20 % of the smallest such length (the smallest itself below
+    64), for every n up to the largest mesh the lengths allow."""
+    for n in range(1, 513):
+        lx, ly, lz = pipe.default_lengths(n, n, min(n, 1024), prec)
+        first = _least_smooth(2 * n)
+        assert lx == ly and _smooth23(lx) and lx >= 2 * n, (n, lx)
+        assert lx == first if first < 64 else first <= lx <= first + first // 5, (n, lx, first)
+        h = lz // 2
+        hfirst = _least_smooth(n)
+        assert lz % 2 == 0 and _smooth23(h) and h >= n, (n, lz)
+        assert h == hfirst if hfirst < 64 else hfirst <= h <= hfirst + hfirst // 5, (n, lz, hfirst)
+
+
+@needs_lib
+@pytest.mark.parametrize("mesh,prec,want", [
+    ((128, 128, 512), "fp32", (256, 256, 1024)),    # the benchmark mesh keeps its powers of two
+    ((128, 128, 512), "fp64", (256, 256, 1024)),
+    ((32, 32, 32), "fp64", (64, 64, 64)),
+    ((64, 64, 256), "fp64", (128, 128, 512)),
+    ((70, 40, 75), "fp32", (144, 81, 162)),         # the smallest lengths are also the fastest
+    ((70, 40, 75), "fp64", (144, 81, 162)),
+    ((200, 200, 512), "fp32", (512, 512, 1024)),    # 432 = 27 * 16 runs far below 512 per element
+    ((200, 200, 512), "fp64", (512, 512, 1024)),
+    ((100, 100, 256), "fp32", (256, 256, 512)),     # 216 likewise against 256
+    ((200, 100, 216), "fp32", (512, 256, 432)),     # z keeps lz/2 = 216
+    ((200, 100, 216), "fp64", (512, 256, 432)),
+    ((150, 150, 256), "fp32", (324, 324, 512)),     # 324 = 81 * 4 beats 384
+    ((300, 300, 256), "fp32", (729, 729, 512)),     # 729 beats 648 and 768
+])
+def test_default_lengths_follow_the_measured_model(mesh, prec, want):
+    """The per-length efficiency model picks the lengths measured fastest on the
+    meshes it was checked on."""
+    assert pipe.default_lengths(*mesh, prec) == want
+
+
+@needs_lib
+def test_default_lengths_errors():
+    L = pipe.lib()
+    out = [ctypes.c_int() for _ in range(3)]
+    refs = [ctypes.byref(v) for v in out]
+    assert L.pipe_default_lengths(0, 4, 4, 0, *refs) == 1
+    assert L.pipe_default_lengths(4, 4, 4, 0x210, *refs) == 1          # an autotune bit is not a length choice
+    assert L.pipe_default_lengths(4, 4, 4, 0x03, *refs) == 1           # unknown Green kind
+    assert L.pipe_default_lengths(4, 4, 4, 0, None, refs[1], refs[2]) == 1
+    assert L.pipe_default_lengths(513, 4, 4, 0, *refs) == 2            # 2n > 1024
+    assert L.pipe_default_lengths(4, 4, 1025, 0x10, *refs) == 2        # lz/2 > 1024
+    assert L.pipe_default_lengths(4, 4, 4, 0x12, *refs) == 0           # free-space kind, FP32
+    with pytest.raises(ValueError):
+        pipe.default_lengths(4, 4, 4, "fp16")

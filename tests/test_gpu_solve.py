@@ -182,6 +182,18 @@ def test_default_lengths_skip_a_slow_factorisation(torch_cuda, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plans_take_the_queried_default_lengths(torch_cuda, prec):
+    """pipe_default_lengths (host only) reports the lengths a default plan builds."""
+    from paper_1111_4971_amd import pipe
+    for mesh in [(200, 100, 216), (70, 40, 75), (33, 17, 100), (5, 130, 300)]:
+        nx, ny, nz = mesh
+        plan = pipe.GreenPlan(nx, ny, nz, 1.0 / (nx + 1), 1.0 / (ny + 1), 0.05, 1.0, 1.0, kind=1, precision=prec,
+                              mx=4, my=4)
+        assert (plan.info.lx, plan.info.ly, plan.info.lz) == pipe.default_lengths(nx, ny, nz, prec), mesh
+        plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_padded_length_does_not_change_the_result(torch_cuda, prec):
     from paper_1111_4971_amd import pipe
     nx, ny, nz = 10, 7, 12
