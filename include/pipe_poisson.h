@@ -132,7 +132,7 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
  * MI355X, so a slow factorisation (432 = 27 * 16) gives way to a fast one
  * (512) when that is quicker overall; below 64 it is the smallest length.
  * The physical result does
- * not depend on the padded lengths.  hip_stream (a hipStream_t, may be NULL) orders the build's GPU
+ * not depend on the padded lengths.  hip_stream (a hipStream_t, may be NULL) orders the plan build's GPU
  * work; the call still returns only when the build has finished.
  * Every 3-D plan (here, pipe_green_plan_region, pipe_free_plan) also picks a
  * launch schedule by timing the solve on scratch buffers during the build:
