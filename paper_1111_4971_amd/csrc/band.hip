@@ -133,8 +133,8 @@ __device__ __forceinline__ int floor_half(int x) { return x >= 0 ? x / 2 : -((1 
 // on the spectra, which the inverse y pass removes with its scale.
 template <typename real, int N>
 __global__ __launch_bounds__((2 * (N / Plan<N>::E) * band_T<real, N>()))
-void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz, int nb,
-                  int to, const real* __restrict__ table, const twid<real>* __restrict__ tw) {
+void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz, long pitch,
+                  int nb, int to, const real* __restrict__ table, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
     constexpr int T = band_T<real, N>(), TS = T + 1;
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NH = N / 2, NKX = NH + 1;
@@ -156,7 +156,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
     const bool self = (ky == 0) || (2 * ky == ly);
     const int nzp = (nz + 1) / 2;
     const int z0 = 2 * to * tile;   // to <= T output columns per block
-    const long xs = nzp;
+    const long xs = pitch;   // row (x) stride of the packed arrays
     const real* trow = table + (long)ky * (nb + 1) * 10 * NKX;
     for (int idx = threadIdx.x; idx < 10 * NKX; idx += NT) sK[idx] = trow[idx];   // distance 0 (barriers follow)
     LdsCol<C, TS> view{lds + l * N * TS + c};
@@ -186,7 +186,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
         if (ch > 0) __syncthreads();   // previous chunk's products have read the LDS
         const int pc = pbase + ch * T + c;
         const bool act = ch * T + c < ncolp && pc >= 0 && pc < nzp;
-        const C* line = in + (act ? (long)kyl * nx * nzp + pc : 0);
+        const C* line = in + (act ? (long)kyl * nx * pitch + pc : 0);
         fft_line<Plan<N>, false, false>(
             t, tw, [&](int e) -> C { return (act && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
             [&](int e, C v) { view.set(e, v); }, view);
@@ -301,7 +301,7 @@ void xband_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ ou
     // inverse x transforms of the output columns c < to, rows i < nx
     const int pco = to * tile + c;
     const bool oact = c < to && pco < nzp && !(l == 1 && self);
-    C* oline = out + (oact ? (long)kyl * nx * nzp + pco : 0);
+    C* oline = out + (oact ? (long)kyl * nx * pitch + pco : 0);
     fft_line<Plan<N>, true, true>(
         t, tw, [&](int e) -> C { return view.get(e); },
         [&](int e, C v) {
@@ -334,7 +334,7 @@ template <typename real, int N> constexpr int xband0_waves() { return (sizeof(re
 template <typename real, int N, int T>
 __global__ __launch_bounds__((2 * (N / Plan<N>::E) * T)) __attribute__((amdgpu_waves_per_eu(xband0_waves<real, N>())))
 void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz,
-                   const real* __restrict__ table, const twid<real>* __restrict__ tw) {
+                   long pitch, const real* __restrict__ table, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NKX = N / 2 + 1, NO = N / 2;
     constexpr int IT = (NO * T + NT - 1) / NT, KN = (10 + NT - 1) / NT;
@@ -353,9 +353,9 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     const int nzp = (nz + 1) / 2;
     const int pc = tile * T + c;
     const bool active = pc < nzp;
-    const long xs = nzp;
-    const C* iline = in + (active ? (long)kyl * nx * nzp + pc : 0);
-    C* oline = out + (active ? (long)kyl * nx * nzp + pc : 0);
+    const long xs = pitch;   // row (x) stride of the packed arrays
+    const C* iline = in + (active ? (long)kyl * nx * pitch + pc : 0);
+    C* oline = out + (active ? (long)kyl * nx * pitch + pc : 0);
     LdsCol<C, T> view{lds + l * N * T + c};
 
     const real* trow = table + (long)ky * 10 * NKX;
@@ -442,7 +442,7 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
 template <typename real, int N>
 __global__ __launch_bounds__((2 * (N / Plan<N>::E) * band0_T<real, N>()))
 void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz,
-                   int nb, int to, const real* __restrict__ table, const twid<real>* __restrict__ tw) {
+                   long pitch, int nb, int to, const real* __restrict__ table, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
     constexpr int T = band0_T<real, N>(), TS = T + 1;
     constexpr int P = N / Plan<N>::E, NT = 2 * P * T, NH = N / 2, NKX = NH + 1;
@@ -459,7 +459,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     const bool self = (ky == 0) || (2 * ky == ly);
     const int nzp = (nz + 1) / 2;
     const int z0 = 2 * to * tile;
-    const long xs = nzp;
+    const long xs = pitch;   // row (x) stride of the packed arrays
     const real* trow = table + (long)ky * (nb + 1) * 10 * NKX;
     LdsCol<C, TS> view{lds + l * N * TS + c};
 
@@ -469,7 +469,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
     {
         const int pc = pbase + c;
         const bool act = c < ncolp && pc >= 0 && pc < nzp;
-        const C* line = in + (act ? (long)kyl * nx * nzp + pc : 0);
+        const C* line = in + (act ? (long)kyl * nx * pitch + pc : 0);
         fft_line<Plan<N>, false, false>(
             t, tw, [&](int e) -> C { return (act && e < nx) ? line[e * xs] : cmake<C>(0, 0); },
             [&](int e, C v) { view.set(e, v); }, view);
@@ -554,7 +554,7 @@ void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
 
     const int pco = to * tile + c;
     const bool oact = c < to && pco < nzp && !(l == 1 && self);
-    C* oline = out + (oact ? (long)kyl * nx * nzp + pco : 0);
+    C* oline = out + (oact ? (long)kyl * nx * pitch + pco : 0);
     fft_line<Plan<N>, true, true>(
         t, tw, [&](int e) -> C { return view.get(e); },
         [&](int e, C v) {
@@ -760,12 +760,12 @@ int band_small_columns_for(int lx, int real_bytes, int nb) {
 #endif
 
 template <typename real>
-hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, int nb, const real* table,
-                        const TwiddleBank& twb, hipStream_t s, bool single_window, int tile0) {
+hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int nz, long pitch, int nb,
+                        const real* table, const TwiddleBank& twb, hipStream_t s, bool single_window, int tile0) {
     using C = cplx<real>;
     const twid<real>* tw = twb.stage<twid<real>>(lx);
-    if (!tw || nb < 0 || nx > lx || nz < 1) return hipErrorInvalidValue;
     const int nzp = (nz + 1) / 2;
+    if (!tw || nb < 0 || nx > lx || nz < 1 || pitch < nzp) return hipErrorInvalidValue;
     switch (lx) {
 #define X(N_)                                                                                        \
     case N_: {                                                                                       \
@@ -775,24 +775,24 @@ hipError_t launch_xband(int lx, const void* in, void* out, int nx, int ly, int n
             if (tile0 == T2 && T > 1) {                                                              \
                 dim3 grid((unsigned)((nzp + T2 - 1) / T2), (unsigned)(ly / 2 + 1));                  \
                 hipLaunchKernelGGL((xband0_kernel<real, N_, T2>), grid, dim3(2 * P * T2), 0, s,      \
-                                   (const C*)in, (C*)out, nx, ly, nz, table, tw);                    \
+                                   (const C*)in, (C*)out, nx, ly, nz, pitch, table, tw);                    \
             } else {                                                                                 \
                 dim3 grid((unsigned)((nzp + T - 1) / T), (unsigned)(ly / 2 + 1));                    \
                 hipLaunchKernelGGL((xband0_kernel<real, N_, T>), grid, dim3(2 * P * T), 0, s,        \
-                                   (const C*)in, (C*)out, nx, ly, nz, table, tw);                    \
+                                   (const C*)in, (C*)out, nx, ly, nz, pitch, table, tw);                    \
             }                                                                                        \
         } else if (single_window && band_small_columns(band0_T<real, N_>(), nb) > 0) {               \
             constexpr int T = band0_T<real, N_>();                                                   \
             const int to = band_small_columns(T, nb);                                                \
             dim3 grid((unsigned)((nzp + to - 1) / to), (unsigned)(ly / 2 + 1));                      \
             hipLaunchKernelGGL((xband1_kernel<real, N_>), grid, dim3(2 * P * T), 0, s,               \
-                               (const C*)in, (C*)out, nx, ly, nz, nb, to, table, tw);                \
+                               (const C*)in, (C*)out, nx, ly, nz, pitch, nb, to, table, tw);                \
         } else {                                                                                     \
             constexpr int T = band_T<real, N_>();                                                    \
             const int to = band_out_columns(T, nb);                                                  \
             dim3 grid((unsigned)((nzp + to - 1) / to), (unsigned)(ly / 2 + 1));                      \
             hipLaunchKernelGGL((xband_kernel<real, N_>), grid, dim3(2 * P * T), 0, s,                \
-                               (const C*)in, (C*)out, nx, ly, nz, nb, to, table, tw);                \
+                               (const C*)in, (C*)out, nx, ly, nz, pitch, nb, to, table, tw);                \
         }                                                                                            \
         return hipGetLastError();                                                                    \
     }
@@ -834,7 +834,7 @@ hipError_t launch_band_coefficients(const double* tmp, void* table, int real_byt
                                                   long, long, int, real, const TwiddleBank&, hipStream_t);   \
     template hipError_t launch_strided_real<real>(int, bool, const void*, void*, int, int, long, long, long, \
                                                   long, long, long, real, const TwiddleBank&, hipStream_t);  \
-    template hipError_t launch_xband<real>(int, const void*, void*, int, int, int, int, const real*,         \
+    template hipError_t launch_xband<real>(int, const void*, void*, int, int, int, long, int, const real*,   \
                                            const TwiddleBank&, hipStream_t, bool, int);
 
 #if PIPE_TU_FP32

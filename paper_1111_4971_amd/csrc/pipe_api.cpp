@@ -266,6 +266,7 @@ struct pipe_plan_s {
     double g0 = 0;           // free-space plans: G at zero separation
     bool band_single = false; // banded x pass: single-window kernel (else chunked), chosen by timing
     int band_tile0 = 0;       // banded N = 0 x pass: packed-column tile, chosen by timing
+    int band_pad = PIPE_BAND_PAD;   // banded: row pitch of the packed array = ceil(nz/2) + band_pad
     double band_speedup = 0;  // banded build: measured 3-D solve time / banded solve time
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
@@ -283,9 +284,11 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+long band_pitch(const pipe_plan_s* p) { return (p->nz + 1) / 2 + p->band_pad; }
+
 size_t plan_ws_bytes(const pipe_plan_s* p) {
     const size_t cb = 2 * (size_t)p->rb;
-    if (p->band >= 0) return 2 * align256((size_t)p->nx * p->ly * ((p->nz + 1) / 2) * cb);   // A, B: packed pairs
+    if (p->band >= 0) return 2 * align256((size_t)p->nx * p->ly * band_pitch(p) * cb);   // A, B: packed pairs
     const size_t a1 = (size_t)p->nx * p->ny * p->nh * cb;
     const size_t a2 = (size_t)p->nx * p->ly * a2_pitch(p->nh, p->apad) * cb;
     return align256(a1) + align256(a2);
@@ -653,11 +656,11 @@ pipe_status_t choose_band_kernel(pipe_plan_s* p, hipStream_t st) {
     pipe_status_t s = PIPE_OK;
     for (size_t v = 0; v < cands.size() && s == PIPE_OK; ++v) {
         auto launch = [&]() -> hipError_t {
-            return p->rb == 8 ? launch_xband<double>(p->lx, ws, (char*)ws + half, p->nx, p->ly, p->nz, p->band,
-                                                     (const double*)p->table, p->ctx->tw, st, cands[v].single,
-                                                     cands[v].tile0)
-                              : launch_xband<float>(p->lx, ws, (char*)ws + half, p->nx, p->ly, p->nz, p->band,
-                                                    (const float*)p->table, p->ctx->tw, st, cands[v].single,
+            return p->rb == 8 ? launch_xband<double>(p->lx, ws, (char*)ws + half, p->nx, p->ly, p->nz, band_pitch(p),
+                                                     p->band, (const double*)p->table, p->ctx->tw, st,
+                                                     cands[v].single, cands[v].tile0)
+                              : launch_xband<float>(p->lx, ws, (char*)ws + half, p->nx, p->ly, p->nz, band_pitch(p),
+                                                    p->band, (const float*)p->table, p->ctx->tw, st, cands[v].single,
                                                     cands[v].tile0);
         };
         hipError_t e = launch();   // warm-up
@@ -685,23 +688,24 @@ pipe_status_t run_band_passes(pipe_plan_s* p, const void* rho, void* phi, void* 
                               hipEvent_t* ev) {
     const size_t cb = 2 * sizeof(real);
     char* A = (char*)ws;
-    const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly, nzp = (nz + 1) / 2;
-    char* B = A + align256((size_t)nx * ly * nzp * cb);
+    const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly;
+    const long pitch = band_pitch(p);
+    char* B = A + align256((size_t)nx * ly * pitch * cb);
     const TwiddleBank& tw = p->ctx->tw;
     if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event");
-    HIP_TRY(launch_strided_pair<real>(ly, false, rho, A, ny, ly, nz, (long)nx * nzp, (long)ny * nz, nzp, nx, nz,
+    HIP_TRY(launch_strided_pair<real>(ly, false, rho, A, ny, ly, nz, (long)nx * pitch, (long)ny * nz, pitch, nx, nz,
                                       (real)1, tw, st),
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
     (void)adjoint;   // the banded coefficient matrices are symmetric: same kernel both ways
-    HIP_TRY(launch_xband<real>(p->lx, A, B, nx, ly, nz, p->band, (const real*)p->table, tw, st, p->band_single,
-                               p->band_tile0),
+    HIP_TRY(launch_xband<real>(p->lx, A, B, nx, ly, nz, pitch, p->band, (const real*)p->table, tw, st,
+                               p->band_single, p->band_tile0),
             "x pass with banded product");
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
     // 1/2 undoes the factor 2 of the split in the x pass
     const real scale = (real)(0.5 * p->hx * p->hy * p->hz / ((double)p->lx * p->ly));
-    HIP_TRY(launch_strided_pair<real>(ly, true, B, phi, ly, ny, nz, (long)nx * nzp, (long)ny * nz, nzp, nx, nz, scale,
-                                      tw, st),
+    HIP_TRY(launch_strided_pair<real>(ly, true, B, phi, ly, ny, nz, (long)nx * pitch, (long)ny * nz, pitch, nx, nz,
+                                      scale, tw, st),
             "y inverse pass");
     if (ev)
         for (int i = 3; i < 6; ++i) HIP_TRY(hipEventRecord(ev[i], st), "event");
