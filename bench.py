@@ -113,7 +113,7 @@ def time_leg(pipe, torch, wl, precision, steps, warmup):
         "events_recorded": n,
         "plan_build_ms": info.build_ms,
         "schedule": {"x_tile": info.xtile, "a2_row_pad": info.apad, "z_block_cap": info.zblocks,
-                     "x_nontemporal_stores": info.xnt},
+                     "x_nontemporal_stores": info.xnt, "a1_row_pad": info.a1pad},
         "padded_lengths": [info.lx, info.ly, info.lz],
         "model_bytes_per_solve": info.model_bytes,
         "model_GBps_whole_solve": info.model_bytes / (ms_step * 1e-3) / 1e9,

@@ -101,6 +101,7 @@ typedef struct pipe_plan_info {
     int zblocks;             /* slots per row of the y-transformed array, block cap of the  */
                              /* z passes; none of them changes a result                    */
     int xnt;                 /* schedule: 1 if the x pass writes with non-temporal stores  */
+    int a1pad;               /* schedule: slots per row of the z-transformed array = lz/2 + a1pad */
 } pipe_plan_info_t;
 
 /*
@@ -139,13 +140,16 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
  * the kz tile of the x pass (its widest or half of it), the row pitch of the
  * y-transformed array (lz/2 plus 0, 16 or 32), the block cap of the z
  * passes (1024, 2048 or 4096) and whether the x pass writes with non-temporal
- * stores.  None of these changes any result; the choice is cached for the
- * process (and in PIPE_TUNE_CACHE, "pipe-sched-v2" lines) and reported in
- * pipe_plan_info (xtile, apad, zblocks, xnt).  The environment variable
- * PIPE_SCHEDULE=fixed skips the timing (widest tile, no pad, 2048 blocks,
- * plain stores); PIPE_SCHEDULE=T,pad,cap[,nt] forces a schedule (INVALID_ARG
- * if T is neither the widest tile nor half of it, pad is outside [0, 256] or
- * nt is not 0 or 1; non-temporal stores are an FP64 option only).
+ * stores; the row pitch of the z-transformed array is lz/2 plus 16 where lz/2
+ * is a power of two and a row spans at least 8 KB, else lz/2.  None
+ * of these changes any result; the choice is cached for the process (and in
+ * PIPE_TUNE_CACHE, "pipe-sched-v3" lines) and reported in pipe_plan_info
+ * (xtile, apad, zblocks, xnt, a1pad).  The environment variable
+ * PIPE_SCHEDULE=fixed skips the timing (widest tile, no y pad, 2048 blocks,
+ * plain stores, the A1 pad by the rule above); PIPE_SCHEDULE=T,pad,cap[,nt[,a1pad]] forces a schedule
+ * (INVALID_ARG if T is neither the widest tile nor half of it, pad is outside
+ * [0, 256], nt is not 0 or 1, or a1pad is not even in [0, 256]; non-temporal
+ * stores are an FP64 option only).
  * With PIPE_AUTOTUNE in kind and all lengths 0, the plan times the five
  * passes for each candidate factorisation per dimension (the default above,
  * the smallest supported length >= 2n, the smallest even one, the smallest

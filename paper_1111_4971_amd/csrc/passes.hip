@@ -177,7 +177,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
             const gptr<C> dst = gout + line * out_pitch;
             if constexpr (Z_PAIR_STORE<real, NH, E>) {
                 // FP32, even NH: each thread writes two adjacent bins with one 16-byte store
-                // (out_pitch is NH and the buffer 16-byte aligned, so 2k lands on 16 bytes)
+                // (the launcher checks that out_pitch is even and the buffer 16-byte aligned)
 #pragma unroll
                 for (int q = 0; q < E / 2; ++q) {
                     const int k = 2 * (t + q * P);
@@ -339,6 +339,10 @@ hipError_t launch_z_r2c(int nh, const real* in, long in_pitch, int n_in, void* o
         constexpr int V = z_V<real, N_>(), P = N_ / Plan<N_, V>::E, LPW = z_lines<real, N_>();       \
         const twid<real>* tw = twb.stage<twid<real>>(N_, V);                                                      \
         if (!tw) return hipErrorInvalidValue;                                                   \
+        /* paired 16-byte stores need an even output pitch and 16-byte aligned lines */        \
+        if (Z_PAIR_STORE<real, N_, Plan<N_, V>::E> &&                                           \
+            (out_pitch % 2 || (!group && (uintptr_t)out % 16)))                                 \
+            return hipErrorInvalidValue;                                                        \
         dim3 grid(z_grid((nlines + LPW - 1) / LPW, ngroup, zcap), 1, (unsigned)ngroup);               \
         hipLaunchKernelGGL((z_r2c_kernel<real, N_>), grid, dim3(LPW * P), 0, s, in, in_pitch,   \
                            n_in, (C*)out, out_pitch, nlines, tw, tw2, vec2, group);             \

@@ -267,6 +267,7 @@ struct pipe_plan_s {
     bool band_single = false; // banded x pass: single-window kernel (else chunked), chosen by timing
     int band_tile0 = 0;       // banded N = 0 x pass: packed-column tile, chosen by timing
     int band_pad = PIPE_BAND_PAD;   // banded: row pitch of the packed array = ceil(nz/2) + band_pad
+    int a1pad = PIPE_A1_PAD;        // row pitch of A1 = lz/2 + a1pad
     double band_speedup = 0;  // banded build: measured 3-D solve time / banded solve time
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
@@ -285,11 +286,21 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 long band_pitch(const pipe_plan_s* p) { return (p->nz + 1) / 2 + p->band_pad; }
+long a1_pitch(const pipe_plan_s* p) { return p->nh + p->a1pad; }
+// A1's row pad by rule rather than by timing (its effect, about 1 %, is below
+// what a few timed solves resolve): 16 slots where lz/2 is a power of two and
+// a row spans at least 8 KB, where the power-of-two stride slowed the y passes
+// (256x256x1024: y forward 6 % faster padded, solve 1.0 % (FP32) and 1.7 %
+// (FP64); 128x128x512 FP32, 4 KB rows: 0-0.7 % slower padded).
+int a1_pad_rule(const pipe_plan_s* p) {
+    const long row = (long)p->nh * 2 * p->rb;
+    return ((p->nh & (p->nh - 1)) == 0 && row >= 8192) ? 16 : 0;
+}
 
 size_t plan_ws_bytes(const pipe_plan_s* p) {
     const size_t cb = 2 * (size_t)p->rb;
     if (p->band >= 0) return 2 * align256((size_t)p->nx * p->ly * band_pitch(p) * cb);   // A, B: packed pairs
-    const size_t a1 = (size_t)p->nx * p->ny * p->nh * cb;
+    const size_t a1 = (size_t)p->nx * p->ny * a1_pitch(p) * cb;
     const size_t a2 = (size_t)p->nx * p->ly * a2_pitch(p->nh, p->apad) * cb;
     return align256(a1) + align256(a2);
 }
@@ -571,28 +582,29 @@ pipe_status_t run_passes(pipe_plan_s* p, const void* rho, void* phi, void* ws, h
                          hipEvent_t* ev) {
     const size_t cb = 2 * sizeof(real);
     char* A1 = (char*)ws;
-    char* A2 = A1 + align256((size_t)p->nx * p->ny * p->nh * cb);
+    char* A2 = A1 + align256((size_t)p->nx * p->ny * a1_pitch(p) * cb);
     const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly, nh = p->nh;
+    const long p1 = a1_pitch(p);
     const TwiddleBank& tw = p->ctx->tw;
     if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event");
-    HIP_TRY(launch_z_r2c<real>(nh, (const real*)rho, nz, nz, A1, nh, (long)nx * ny, tw, st, nullptr, 1, true,
+    HIP_TRY(launch_z_r2c<real>(nh, (const real*)rho, nz, nz, A1, p1, (long)nx * ny, tw, st, nullptr, 1, true,
                                p->zcap),
             "z forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event");
     // A2 is (ly, nx, lz/2): ky-major, see passes.hip
     const long pa = a2_pitch(nh, p->apad);
-    HIP_TRY(launch_strided<real>(ly, false, A1, A2, ny, ly, nh, (long)nx * pa, nh, (long)ny * nh, pa, nx, tw, st),
+    HIP_TRY(launch_strided<real>(ly, false, A1, A2, ny, ly, p1, (long)nx * pa, nh, (long)ny * p1, pa, nx, tw, st),
             "y forward pass");
     if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event");
     HIP_TRY(launch_xprod<real>(p->lx, adjoint, A2, nx, ly, nh, pa, p->tile, p->xnt != 0, (const real*)p->table,
                                (const real*)p->nyq, tw, st, nullptr, 1, false, p->nval),
             "x pass with spectral product");
     if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event");
-    HIP_TRY(launch_strided<real>(ly, true, A2, A1, ly, ny, (long)nx * pa, nh, nh, pa, (long)ny * nh, nx, tw, st),
+    HIP_TRY(launch_strided<real>(ly, true, A2, A1, ly, ny, (long)nx * pa, p1, nh, pa, (long)ny * p1, nx, tw, st),
             "y inverse pass");
     if (ev) HIP_TRY(hipEventRecord(ev[4], st), "event");
     const real scale = (real)(p->hx * p->hy * p->hz / ((double)p->lx * p->ly * p->lz));
-    HIP_TRY(launch_z_c2r<real>(nh, A1, nh, (real*)phi, nz, nz, (long)nx * ny, scale, tw, st, nullptr, 1, true,
+    HIP_TRY(launch_z_c2r<real>(nh, A1, p1, (real*)phi, nz, nz, (long)nx * ny, scale, tw, st, nullptr, 1, true,
                                p->zcap),
             "z inverse pass");
     if (ev) HIP_TRY(hipEventRecord(ev[5], st), "event");
@@ -885,7 +897,7 @@ pipe_status_t time_candidates(std::vector<pipe_plan_s>& cands, int members, hipS
             std::vector<GroupArgs> a(5 * members);
             for (int k = 0; k < members; ++k) {
                 char* A1 = (char*)ws + ws_max * k;
-                char* A2 = A1 + align256((size_t)q.nx * q.ny * q.nh * 2 * q.rb);
+                char* A2 = A1 + align256((size_t)q.nx * q.ny * a1_pitch(&q) * 2 * q.rb);
                 char* ph = (char*)phi + field * k;
                 a[0 * members + k] = {rho, A1, nullptr, nullptr, 0.0};
                 a[1 * members + k] = {A1, A2, nullptr, nullptr, 0.0};
@@ -1001,14 +1013,14 @@ struct SchedKey {
                std::tie(o.arch, o.nx, o.ny, o.nz, o.lx, o.ly, o.lz, o.rb, o.nval, o.members);
     }
 };
-std::map<SchedKey, std::array<int, 4>> g_sched;
+std::map<SchedKey, std::array<int, 5>> g_sched;
 std::string g_sched_loaded;
 
-bool schedule_ok(int lx, int rb, const std::array<int, 4>& v) {
+bool schedule_ok(int lx, int rb, const std::array<int, 5>& v) {
     const int T = xprod_tile(lx, rb);
-    // non-temporal x-pass stores exist in FP64 only
+    // non-temporal x-pass stores exist in FP64 only; the A1 pad keeps rows 16-byte aligned (even)
     return (v[0] == T || (T > 1 && v[0] == T / 2)) && v[1] >= 0 && v[1] <= 256 && v[2] >= 1 && v[2] <= 65536 &&
-           (v[3] == 0 || (v[3] == 1 && rb == 8));
+           (v[3] == 0 || (v[3] == 1 && rb == 8)) && v[4] >= 0 && v[4] <= 256 && v[4] % 2 == 0;
 }
 
 void sched_cache_load() {
@@ -1020,9 +1032,9 @@ void sched_cache_load() {
     char line[512], arch[128];
     while (fgets(line, sizeof line, f)) {
         SchedKey k;
-        std::array<int, 4> v;
-        if (sscanf(line, "pipe-sched-v2 %127s %d %d %d %d %d %d %d %d %d %d %d %d %d", arch, &k.nx, &k.ny, &k.nz,
-                   &k.lx, &k.ly, &k.lz, &k.rb, &k.nval, &k.members, &v[0], &v[1], &v[2], &v[3]) != 14)
+        std::array<int, 5> v;
+        if (sscanf(line, "pipe-sched-v3 %127s %d %d %d %d %d %d %d %d %d %d %d %d %d %d", arch, &k.nx, &k.ny, &k.nz,
+                   &k.lx, &k.ly, &k.lz, &k.rb, &k.nval, &k.members, &v[0], &v[1], &v[2], &v[3], &v[4]) != 15)
             continue;
         k.arch = arch;
         if (schedule_ok(k.lx, k.rb, v)) g_sched[k] = v;
@@ -1030,32 +1042,33 @@ void sched_cache_load() {
     fclose(f);
 }
 
-void sched_cache_store(const SchedKey& k, const std::array<int, 4>& v) {
+void sched_cache_store(const SchedKey& k, const std::array<int, 5>& v) {
     const char* path = getenv("PIPE_TUNE_CACHE");
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "pipe-sched-v2 %s %d %d %d %d %d %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.nx, k.ny, k.nz, k.lx,
-            k.ly, k.lz, k.rb, k.nval, k.members, v[0], v[1], v[2], v[3]);
+    fprintf(f, "pipe-sched-v3 %s %d %d %d %d %d %d %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.nx, k.ny, k.nz,
+            k.lx, k.ly, k.lz, k.rb, k.nval, k.members, v[0], v[1], v[2], v[3], v[4]);
     fclose(f);
 }
 
-// Sets p->tile, p->apad, p->zcap, p->xnt (p's lengths and sizes already set).
+// Sets p->tile, p->apad, p->zcap, p->xnt, p->a1pad (p's lengths and sizes already set).
 pipe_status_t tune_schedule(pipe_plan_s* p, int members, hipStream_t st) {
     const int T = xprod_tile(p->lx, p->rb);
-    std::array<int, 4> v{T, 0, 2048, 0};
+    std::array<int, 5> v{T, 0, 2048, 0, a1_pad_rule(p)};
     auto apply = [&] {
-        p->tile = v[0]; p->apad = v[1]; p->zcap = v[2]; p->xnt = v[3];
+        p->tile = v[0]; p->apad = v[1]; p->zcap = v[2]; p->xnt = v[3]; p->a1pad = v[4];
     };
     if (const char* f = getenv("PIPE_SCHEDULE")) {
         if (!strcmp(f, "fixed")) {
             apply();
             return PIPE_OK;
         }
-        const int got = sscanf(f, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]);
-        if ((got != 3 && got != 4) || !schedule_ok(p->lx, p->rb, v))
-            return fail(PIPE_ERR_INVALID_ARG, "PIPE_SCHEDULE must be 'fixed' or 'T,pad,cap[,nt]' with T %d or %d, "
-                        "0 <= pad <= 256, cap >= 1, nt 0 or 1 (1 in FP64 only) (got '%s')", T, T / 2, f);
+        const int got = sscanf(f, "%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4]);
+        if (got < 3 || !schedule_ok(p->lx, p->rb, v))
+            return fail(PIPE_ERR_INVALID_ARG, "PIPE_SCHEDULE must be 'fixed' or 'T,pad,cap[,nt[,a1pad]]' with T %d or "
+                        "%d, 0 <= pad <= 256, cap >= 1, nt 0 or 1 (1 in FP64 only), a1pad even in [0, 256] (got '%s')",
+                        T, T / 2, f);
         apply();
         return PIPE_OK;
     }
@@ -1076,7 +1089,7 @@ pipe_status_t tune_schedule(pipe_plan_s* p, int members, hipStream_t st) {
         if (t < 1 || (t == T / 2 && T == 1)) continue;
         for (int pad : {0, 16, 32}) {
             pipe_plan_s q = *p;
-            q.tile = t; q.apad = pad; q.zcap = 2048; q.xnt = 0;
+            q.tile = t; q.apad = pad; q.zcap = 2048; q.xnt = 0; q.a1pad = a1_pad_rule(p);
             cands.push_back(q);
         }
     }
@@ -1084,7 +1097,7 @@ pipe_status_t tune_schedule(pipe_plan_s* p, int members, hipStream_t st) {
     pipe_status_t rs = time_candidates(cands, members, st, ms);
     if (rs != PIPE_OK) return rs;
     size_t bi = std::min_element(ms.begin(), ms.end()) - ms.begin();
-    v = {cands[bi].tile, cands[bi].apad, 2048, 0};
+    v = {cands[bi].tile, cands[bi].apad, 2048, 0, a1_pad_rule(p)};
     double best = ms[bi];
     std::vector<pipe_plan_s> more(p->rb == 8 ? 3 : 2, cands[bi]);
     more[0].zcap = 1024;
@@ -1397,6 +1410,7 @@ pipe_status_t pipe_plan_info(pipe_plan_t p, pipe_plan_info_t* out) {
     out->apad = p->band >= 0 ? 0 : p->apad;
     out->zblocks = p->band >= 0 ? 0 : p->zcap;
     out->xnt = p->band >= 0 ? 0 : p->xnt;
+    out->a1pad = p->band >= 0 ? 0 : p->a1pad;
     return PIPE_OK;
 }
 
@@ -1637,19 +1651,20 @@ pipe_status_t launch_group(pipe_plan_s* p, const GroupArgs* args, int n, bool al
     const int nx = p->nx, ny = p->ny, nz = p->nz, ly = p->ly, nh = p->nh;
     const TwiddleBank& tw = p->ctx->tw;
     const real scale = (real)0;  // taken from each member's GroupArgs
-    HIP_TRY(launch_z_r2c<real>(nh, nullptr, nz, nz, nullptr, nh, (long)nx * ny, tw, st, args, n, al_in, p->zcap),
+    const long p1 = a1_pitch(p);
+    HIP_TRY(launch_z_r2c<real>(nh, nullptr, nz, nz, nullptr, p1, (long)nx * ny, tw, st, args, n, al_in, p->zcap),
             "grouped z forward pass");
     const long pa = a2_pitch(nh, p->apad);
-    HIP_TRY(launch_strided<real>(ly, false, nullptr, nullptr, ny, ly, nh, (long)nx * pa, nh, (long)ny * nh, pa, nx,
+    HIP_TRY(launch_strided<real>(ly, false, nullptr, nullptr, ny, ly, p1, (long)nx * pa, nh, (long)ny * p1, pa, nx,
                                  tw, st, args + n, n),
             "grouped y forward pass");
     HIP_TRY(launch_xprod<real>(p->lx, false, nullptr, nx, ly, nh, pa, p->tile, p->xnt != 0, nullptr, nullptr, tw,
                                st, args + 2 * n, n, shared_table, p->nval),
             "grouped x pass with spectral product");
-    HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, (long)nx * pa, nh, nh, pa, (long)ny * nh, nx,
+    HIP_TRY(launch_strided<real>(ly, true, nullptr, nullptr, ly, ny, (long)nx * pa, p1, nh, pa, (long)ny * p1, nx,
                                  tw, st, args + 3 * n, n),
             "grouped y inverse pass");
-    HIP_TRY(launch_z_c2r<real>(nh, nullptr, nh, nullptr, nz, nz, (long)nx * ny, scale, tw, st, args + 4 * n, n,
+    HIP_TRY(launch_z_c2r<real>(nh, nullptr, p1, nullptr, nz, nz, (long)nx * ny, scale, tw, st, args + 4 * n, n,
                                al_out, p->zcap),
             "grouped z inverse pass");
     return PIPE_OK;
@@ -1678,7 +1693,7 @@ pipe_status_t pipe_batch_create(const pipe_plan_t* plans, int count, pipe_batch_
             pipe_plan_s* r = b->groups[k].rep;
             if (!b->groups[k].banded && r->nx == p->nx && r->ny == p->ny && r->nz == p->nz && r->lx == p->lx &&
                 r->ly == p->ly && r->lz == p->lz && r->nval == p->nval && r->tile == p->tile &&
-                r->apad == p->apad && r->zcap == p->zcap && r->xnt == p->xnt)
+                r->apad == p->apad && r->zcap == p->zcap && r->xnt == p->xnt && r->a1pad == p->a1pad)
                 g = (int)k;
         }
         if (g < 0) {
@@ -1779,7 +1794,7 @@ pipe_status_t pipe_batch_solve(pipe_batch_t b, const void* const* rho, void* con
                 const int i = g.members[k];
                 pipe_plan_s* p = b->plans[i];
                 char* A1 = (char*)ws + b->ws_off[i];
-                char* A2 = A1 + align256((size_t)p->nx * p->ny * p->nh * 2 * p->rb);
+                char* A2 = A1 + align256((size_t)p->nx * p->ny * a1_pitch(p) * 2 * p->rb);
                 const double scale = p->hx * p->hy * p->hz / ((double)p->lx * p->ly * p->lz);
                 a[0 * m + k] = {rho[i], A1, nullptr, nullptr, 0.0};
                 a[1 * m + k] = {A1, A2, nullptr, nullptr, 0.0};

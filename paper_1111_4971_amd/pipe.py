@@ -49,7 +49,8 @@ class PlanInfo(ctypes.Structure):
                 ("model_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double * 5),
                 ("build_ms", ctypes.c_double), ("tune_ms", ctypes.c_double), ("band", ctypes.c_int),
                 ("band_speedup", ctypes.c_double),
-                ("xtile", ctypes.c_int), ("apad", ctypes.c_int), ("zblocks", ctypes.c_int), ("xnt", ctypes.c_int)]
+                ("xtile", ctypes.c_int), ("apad", ctypes.c_int), ("zblocks", ctypes.c_int), ("xnt", ctypes.c_int),
+                ("a1pad", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

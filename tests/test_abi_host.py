@@ -385,3 +385,29 @@ def test_default_lengths_errors():
     assert L.pipe_default_lengths(4, 4, 4, 0x12, *refs) == 0           # free-space kind, FP32
     with pytest.raises(ValueError):
         pipe.default_lengths(4, 4, 4, "fp16")
+
+
+def test_plan_info_layout_matches_the_header(tmp_path):
+    """The binding's PlanInfo has the size and field offsets of the header's
+    pipe_plan_info_t (a C program compiled against the header reports them)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in pipe.PlanInfo._fields_]
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"pipe_poisson.h\"\nint main(void) {\n"
+                   "  printf(\"size %zu\\n\", sizeof(pipe_plan_info_t));\n" +
+                   "".join("  printf(\"%s %%zu\\n\", offsetof(pipe_plan_info_t, %s));\n" % (f, f) for f in fields) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       timeout=60).stdout.splitlines())
+    assert int(got["size"]) == ctypes.sizeof(pipe.PlanInfo)
+    for f in fields:
+        assert int(got[f]) == getattr(pipe.PlanInfo, f).offset, f

@@ -1,5 +1,6 @@
-"""Launch schedules (kz tile of the x pass, row pitch of the y-transformed
-array, block cap of the persistent z passes) change no result: every forced
+"""Launch schedules (kz tile of the x pass, row pitches of the y- and
+z-transformed arrays, block cap of the persistent z passes, FP64 non-temporal
+stores) change no result: every forced
 schedule against the literal Eq. 10 oracle, element by element, and the
 timed choice is reported, cached and grouped correctly in batches.
 """
@@ -48,15 +49,16 @@ def test_every_forced_schedule_matches_eq10_oracle(torch_cuda, monkeypatch, shap
     tiles = [T, T // 2] if T > 1 else [T]
     for t in tiles:
         for pad in (0, 16, 32):
-            for cap, nt in ((1, 0), (7, 1), (2048, 0), (4096, 1)):
+            for cap, nt, a1 in ((1, 0, 16), (7, 1, 0), (2048, 0, 0), (4096, 1, 16)):
                 if prec == "fp32":
                     nt = 0          # non-temporal stores are an FP64 option
-                monkeypatch.setenv("PIPE_SCHEDULE", "%d,%d,%d,%d" % (t, pad, cap, nt))
-                log("schedule %s %s T=%d pad=%d cap=%d nt=%d" % (prec, shape, t, pad, cap, nt))
+                monkeypatch.setenv("PIPE_SCHEDULE", "%d,%d,%d,%d,%d" % (t, pad, cap, nt, a1))
+                log("schedule %s %s T=%d pad=%d cap=%d nt=%d a1=%d" % (prec, shape, t, pad, cap, nt, a1))
                 plan = _mk(shape, prec)
-                assert (plan.info.xtile, plan.info.apad, plan.info.zblocks, plan.info.xnt) == (t, pad, cap, nt)
+                i = plan.info
+                assert (i.xtile, i.apad, i.zblocks, i.xnt, i.a1pad) == (t, pad, cap, nt, a1)
                 got = gpu_solve(plan, rho)
-                assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (t, pad, cap, nt)
+                assert rel_l2(got, ref) <= TOL[prec] and rel_max(got, ref) <= TOL[prec], (t, pad, cap, nt, a1)
                 plan.close()
 
 
@@ -75,6 +77,10 @@ def test_bad_forced_schedule_is_rejected(torch_cuda, monkeypatch):
     monkeypatch.setenv("PIPE_SCHEDULE", "8,0,2048,1")     # an FP64-only option
     with pytest.raises(pipe.PipeError):
         _mk((13, 11, 40), "fp32")
+    for bad in ("8,0,2048,0,3", "8,0,2048,0,258", "8,0,2048,0,-2"):   # the A1 pad: even, 0 .. 256
+        monkeypatch.setenv("PIPE_SCHEDULE", bad)
+        with pytest.raises(pipe.PipeError):
+            _mk((13, 11, 40), "fp32")
 
 
 def test_timed_schedule_is_cached_and_adjoint_agrees(torch_cuda, monkeypatch):
@@ -85,7 +91,8 @@ def test_timed_schedule_is_cached_and_adjoint_agrees(torch_cuda, monkeypatch):
     p2 = _mk(shape, "fp32")
     s1 = (p1.info.xtile, p1.info.apad, p1.info.zblocks)
     assert s1 == (p2.info.xtile, p2.info.apad, p2.info.zblocks)
-    assert p1.info.apad in (0, 16, 32) and p1.info.zblocks in (1024, 2048, 4096)
+    assert p1.info.apad in (0, 16, 32) and p1.info.zblocks in (1024, 2048, 4096) and p1.info.a1pad in (0, 16)
+    assert p1.info.a1pad == p2.info.a1pad
     rho = np.random.default_rng(4).standard_normal(shape)
     got = gpu_solve(p1, rho)
     ref = _ref(shape, rho, "fp32")
@@ -101,7 +108,7 @@ def test_batch_groups_plans_by_schedule(torch_cuda, monkeypatch):
     from paper_1111_4971_amd import pipe
     shape = (20, 18, 50)
     plans = []
-    for sched in ("8,0,2048", "8,16,1024,0", "4,32,7", "8,0,2048,0"):
+    for sched in ("8,0,2048", "8,16,1024,0", "4,32,7", "8,0,2048,0", "8,0,2048,0,16"):
         monkeypatch.setenv("PIPE_SCHEDULE", sched)
         plans.append(_mk(shape, "fp32"))
     rng = np.random.default_rng(6)
