@@ -888,51 +888,57 @@ pipe_status_t time_candidates(std::vector<pipe_plan_s>& cands, int members, hipS
     }
     ms_out.assign(cands.size(), 1e30);
     pipe_status_t rs = PIPE_OK;
-    for (size_t i = 0; i < cands.size() && rs == PIPE_OK; ++i) {
-        pipe_plan_s& q = cands[i];
+    for (pipe_plan_s& q : cands) {
         q.table = tab;
         q.nyq = (char*)tab + q.table_elems * q.rb;
         q.tev.clear(); q.tmax = 0; q.tn = 0;
-        if (members > 1) {
-            std::vector<GroupArgs> a(5 * members);
-            for (int k = 0; k < members; ++k) {
-                char* A1 = (char*)ws + ws_max * k;
-                char* A2 = A1 + align256((size_t)q.nx * q.ny * a1_pitch(&q) * 2 * q.rb);
-                char* ph = (char*)phi + field * k;
-                a[0 * members + k] = {rho, A1, nullptr, nullptr, 0.0};
-                a[1 * members + k] = {A1, A2, nullptr, nullptr, 0.0};
-                a[2 * members + k] = {A2, A2, q.table, q.nyq, 0.0};
-                a[3 * members + k] = {A2, A1, nullptr, nullptr, 0.0};
-                a[4 * members + k] = {A1, ph, nullptr, nullptr, 1.0};
+    }
+    // Rounds over all candidates, each candidate's best round kept, so that
+    // drift during the timing does not favour whichever candidate ran first.
+    const int rounds = cands.size() > 1 ? 3 : 1, reps = 3;
+    for (int round = 0; round < rounds && rs == PIPE_OK; ++round) {
+        for (size_t i = 0; i < cands.size() && rs == PIPE_OK; ++i) {
+            pipe_plan_s& q = cands[i];
+            if (members > 1) {
+                std::vector<GroupArgs> a(5 * members);
+                for (int k = 0; k < members; ++k) {
+                    char* A1 = (char*)ws + ws_max * k;
+                    char* A2 = A1 + align256((size_t)q.nx * q.ny * a1_pitch(&q) * 2 * q.rb);
+                    char* ph = (char*)phi + field * k;
+                    a[0 * members + k] = {rho, A1, nullptr, nullptr, 0.0};
+                    a[1 * members + k] = {A1, A2, nullptr, nullptr, 0.0};
+                    a[2 * members + k] = {A2, A2, q.table, q.nyq, 0.0};
+                    a[3 * members + k] = {A2, A1, nullptr, nullptr, 0.0};
+                    a[4 * members + k] = {A1, ph, nullptr, nullptr, 1.0};
+                }
+                he = hipMemcpyAsync(dargs, a.data(), a.size() * sizeof(GroupArgs), hipMemcpyHostToDevice, st);
+                if (he == hipSuccess) he = hipStreamSynchronize(st);
+                if (he != hipSuccess) {
+                    rs = hip_fail(he, "tuning descriptors");
+                    break;
+                }
             }
-            he = hipMemcpyAsync(dargs, a.data(), a.size() * sizeof(GroupArgs), hipMemcpyHostToDevice, st);
-            if (he == hipSuccess) he = hipStreamSynchronize(st);
-            if (he != hipSuccess) {
-                rs = hip_fail(he, "tuning descriptors");
-                break;
-            }
-        }
-        const int reps = 5;
-        for (int r = 0; r < 2 + reps && rs == PIPE_OK; ++r) {
-            if (r == 2) {
-                he = hipEventRecord(e0, st);
-                if (he != hipSuccess) rs = hip_fail(he, "tuning timing");
+            for (int r = 0; r < 1 + reps && rs == PIPE_OK; ++r) {   // one warm-up solve, then reps timed
+                if (r == 1) {
+                    he = hipEventRecord(e0, st);
+                    if (he != hipSuccess) rs = hip_fail(he, "tuning timing");
+                }
+                if (rs != PIPE_OK) break;
+                if (members > 1)
+                    rs = q.rb == 8 ? launch_group<double>(&q, dargs, members, true, true, st)
+                                   : launch_group<float>(&q, dargs, members, true, true, st);
+                else
+                    rs = q.rb == 8 ? run_passes<double>(&q, rho, phi, ws, st, false, nullptr)
+                                   : run_passes<float>(&q, rho, phi, ws, st, false, nullptr);
             }
             if (rs != PIPE_OK) break;
-            if (members > 1)
-                rs = q.rb == 8 ? launch_group<double>(&q, dargs, members, true, true, st)
-                               : launch_group<float>(&q, dargs, members, true, true, st);
-            else
-                rs = q.rb == 8 ? run_passes<double>(&q, rho, phi, ws, st, false, nullptr)
-                               : run_passes<float>(&q, rho, phi, ws, st, false, nullptr);
+            float ms = 0.f;
+            he = hipEventRecord(e1, st);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he != hipSuccess) rs = hip_fail(he, "tuning timing");
+            else ms_out[i] = std::min(ms_out[i], (double)ms / (reps * members));
         }
-        if (rs != PIPE_OK) break;
-        float ms = 0.f;
-        he = hipEventRecord(e1, st);
-        if (he == hipSuccess) he = hipEventSynchronize(e1);
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he != hipSuccess) rs = hip_fail(he, "tuning timing");
-        else ms_out[i] = ms / (reps * members);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
