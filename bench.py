@@ -425,6 +425,43 @@ def cpu_baseline(wl, min_seconds=10.0, max_solves=12):
             "seconds": dt, "solves": n, "host_cpus": os.cpu_count()}, phi
 
 
+def cpu_o2_leg(wl, L, solves=3):
+    """The oracle's literal Eq. 10 form (one forward transform of the padded
+    charge, four products with the mixed-direction Green spectra, four inverse
+    transforms; scipy.fft on the host cores) on the same charge at the GPU
+    plan's padded lengths, median of `solves`.  Its four Green spectra are
+    built once before the timed solves and reported separately (minutes at
+    this size, so the leg is opt-in)."""
+    import statistics
+    import numpy as np
+    from oracle import fourterm
+    g = wl.geometry()
+    log("[bench] cpu O2: building the four Green spectra at %s" % (L,))
+    t = time.perf_counter()
+    spectra = []
+    for term in fourterm.TERMS:   # as fourterm.green_spectra, one term at a time with progress
+        gdir = term[3]
+        xi = fourterm.green_array(wl.rho.shape, L, (g["hx"], g["hy"], g["hz"]), (g["a"], g["b"], g["mx"], g["my"]),
+                                  g["kind"], term[1], term[2])
+        spectra.append(fourterm._F3(xi.astype(np.complex128), gdir))
+        del xi
+        log("[bench] cpu O2: spectrum %d of 4 built, %.1f s" % (len(spectra), time.perf_counter() - t))
+    build = time.perf_counter() - t
+    log("[bench] cpu O2: spectra built in %.1f s" % build)
+    ts = []
+    for i in range(solves):
+        t = time.perf_counter()
+        fourterm.solve(wl.rho, **g, L=L, spectra=spectra)
+        ts.append(time.perf_counter() - t)
+        log("[bench] cpu O2: solve %d of %d, %.1f s" % (i + 1, solves, ts[-1]))
+    med = statistics.median(ts)
+    return {"value": 1.0 / med, "unit": "solves/s", "kind": "oracle O2 (literal Eq. 10)", "median_s": med,
+            "solves": solves, "seconds": ts, "spectra_build_s": build, "fft_workers": fourterm._WORKERS,
+            "host_cpus": os.cpu_count(),
+            "sample": "%d full %dx%dx%d solves (%dx%d modes), FP64, padded %dx%dx%d, spectra prebuilt"
+                      % (solves, wl.nx, wl.ny, wl.nz, g["mx"], g["my"], L[0], L[1], L[2])}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +471,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--cpu-o2", action="store_true",
+                    help="also time the oracle's literal Eq. 10 form on the host (median of 3; minutes)")
     ap.add_argument("--mesh", default=None,
                     help="NXxNYxNZ: time a smooth bunch on this mesh instead of the benchmark charge "
                          "(profiling other sizes; implies --no-batch and --no-cpu-baseline)")
@@ -530,6 +569,9 @@ def main():
                                                     e["fp64"]["speedup_over_full"], e["fp64"]["rel_max_vs_full_fp64"]))
     if not args.no_cpu_baseline:
         cb, ophi = cpu_baseline(wl)
+        if args.cpu_o2:
+            cb["o2_literal_eq10"] = cpu_o2_leg(wl, tuple(res["legs"]["fp64" if "fp64" in res["legs"] else "fp32"]
+                                                         ["padded_lengths"]))
         res["cpu_baseline"] = cb
         for prec in outs:
             d = outs[prec] - ophi

@@ -27,7 +27,8 @@ import scipy.fft as sfft
 
 from . import green
 
-_WORKERS = os.cpu_count() or 1
+# FFT threads: the host's thread budget where one is set, else every core
+_WORKERS = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
 
 
 def _F(a, axis, direction):
