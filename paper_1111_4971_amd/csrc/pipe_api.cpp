@@ -267,7 +267,7 @@ struct pipe_plan_s {
     bool band_single = false; // banded x pass: single-window kernel (else chunked), chosen by timing
     int band_tile0 = 0;       // banded N = 0 x pass: packed-column tile, chosen by timing
     int band_pad = PIPE_BAND_PAD;   // banded: row pitch of the packed array = ceil(nz/2) + band_pad
-    int a1pad = PIPE_A1_PAD;        // row pitch of A1 = lz/2 + a1pad
+    int a1pad = 0;                  // row pitch of A1 = lz/2 + a1pad (set with the launch schedule)
     double band_speedup = 0;  // banded build: measured 3-D solve time / banded solve time
     double* green = nullptr; // optional copy of Rbar
     double build_ms = 0;
@@ -1116,7 +1116,7 @@ pipe_status_t tune_schedule(pipe_plan_s* p, int members, hipStream_t st) {
             best = ms2[i];
             v[2] = more[i].zcap;
         }
-    if (p->rb == 8 && ms2[2] < ms[bi]) v[3] = 1;   // judged against the same z cap
+    if (p->rb == 8 && ms2[2] < ms[bi]) v[3] = 1;   // compared at the same z cap
     apply();
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_sched[key] = v;

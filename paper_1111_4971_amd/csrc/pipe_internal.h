@@ -158,9 +158,6 @@ template <typename real>
 // ceil(nz/2) + PIPE_BAND_PAD apart instead of a power-of-two stride (measured
 // at 256x256x1024: the y inverse pass 448 -> 336 us in FP64, 180 -> 167 us in
 // FP32; the x pass 4 % slower in FP64; neutral at 128x128x256).
-#ifndef PIPE_A1_PAD
-#define PIPE_A1_PAD 0
-#endif
 #ifndef PIPE_BAND_PAD
 #define PIPE_BAND_PAD 16
 #endif
