@@ -439,8 +439,13 @@ void xband0_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ o
 // pass (T packed columns of the lines ky, -ky, padded LDS columns so the
 // orbit-wise product reads are conflict-free); the coefficients of each plane
 // distance are read from global memory, coalesced over orbits.
+// As xband0: the FP32 length-512 kernel fits one 1024-thread block per CU at
+// its natural 76 registers; held to 64 (9 spilled) two fit (256x256x1024,
+// N = 1: 1096 -> 918 us).
+template <typename real, int N> constexpr int xband1_waves() { return (sizeof(real) == 4 && N == 512) ? 8 : 1; }
 template <typename real, int N>
 __global__ __launch_bounds__((2 * (N / Plan<N>::E) * band0_T<real, N>()))
+__attribute__((amdgpu_waves_per_eu(xband1_waves<real, N>())))
 void xband1_kernel(const cplx<real>* __restrict__ in, cplx<real>* __restrict__ out, int nx, int ly, int nz,
                    long pitch, int nb, int to, const real* __restrict__ table, const twid<real>* __restrict__ tw) {
     using C = cplx<real>;
