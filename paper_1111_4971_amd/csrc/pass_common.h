@@ -162,6 +162,16 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned p, unsigned total) {
 #define PIPE_Z_PAD_SMOOTH 0
 #endif
 template <int NH> constexpr int z_pad() { return (NH & (NH - 1)) == 0 ? PIPE_Z_PAD_POW2 : PIPE_Z_PAD_SMOOTH; }
+// Waves per SIMD the FP32 z forward pass's registers must allow where its plan
+// holds 12 values per thread (1: no constraint).  Left alone the compiler takes
+// 120-150 registers there (3 waves per SIMD); at 4 waves most lengths fit
+// without spills and lengths 288-768 ran 4-7 % faster (432: 33.8 -> 31.4 us at
+// 128x128x432), 48-192 unchanged; 972 would spill heavily and keeps 1.  (The z
+// inverse pass gained at 768 but lost up to 4 % at the small lengths.)
+template <typename real, int NH> constexpr int z_V();
+template <typename real, int NH> constexpr int z_waves() {
+    return (sizeof(real) == 4 && Plan<NH, z_V<real, NH>()>::E == 12 && NH != 972) ? 4 : 1;
+}
 template <typename real, int NH> constexpr int z_V() { return narrow_variant<NH>(sizeof(real) == 8 ? 8 : 12); }
 
 template <typename real, int NH> constexpr Sync z_sync() {

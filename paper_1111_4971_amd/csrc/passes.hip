@@ -114,7 +114,7 @@ constexpr bool Z_PAIR_STORE = PIPE_Z_PAIR_STORE && sizeof(real) == 4 && NH % 2 =
 //   X[0] = Re Z[0] + Im Z[0],  X[NH] = Re Z[0] - Im Z[0]  (stored as slot 0 = (X[0], X[NH])).
 // vec2: n_in and in_pitch even and `in` 2-element aligned, so x[2m], x[2m+1] load as one pair.
 template <typename real, int NH>
-__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH, z_V<real, NH>()>::E)))
+__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH, z_V<real, NH>()>::E))) __attribute__((amdgpu_waves_per_eu(z_waves<real, NH>())))
 void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long out_pitch, long nlines,
                   const twid<real>* __restrict__ tw, const twid<real>* __restrict__ tw2, int vec2,
                   const GroupArgs* __restrict__ group) {
