@@ -145,8 +145,10 @@ pipe_status_t pipe_green_plan(int nx, int ny, int nz, double hx, double hy, doub
  * of these changes any result; the choice is cached for the process (and in
  * PIPE_TUNE_CACHE, "pipe-sched-v3" lines) and reported in pipe_plan_info
  * (xtile, apad, zblocks, xnt, a1pad).  The environment variable
- * PIPE_SCHEDULE=fixed skips the timing (widest tile, no y pad, 2048 blocks,
- * plain stores, the A1 pad by the rule above); PIPE_SCHEDULE=T,pad,cap[,nt[,a1pad]] forces a schedule
+ * PIPE_SCHEDULE=fixed skips the timing (widest tile, no pad on the
+ * y-transformed array, 2048 blocks, plain stores, the z-transformed array's
+ * pitch by the rule above); PIPE_SCHEDULE=T,pad,cap[,nt[,a1pad]] forces a
+ * schedule, a1pad being the slots added to the z-transformed array's pitch
  * (INVALID_ARG if T is neither the widest tile nor half of it, pad is outside
  * [0, 256], nt is not 0 or 1, or a1pad is not even in [0, 256]; non-temporal
  * stores are an FP64 option only).
