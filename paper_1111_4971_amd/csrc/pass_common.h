@@ -172,6 +172,10 @@ template <typename real, int NH> constexpr int z_V();
 template <typename real, int NH> constexpr int z_waves() {
     return (sizeof(real) == 4 && Plan<NH, z_V<real, NH>()>::E == 12 && NH != 972) ? 4 : 1;
 }
+// The z forward pass in FP64 at lz/2 >= 1024, where the split table is read
+// from global memory (see z_tw2_lds): 3 waves per SIMD, the blocks the LDS allows.
+template <typename real, int NH> constexpr bool z_tw2_lds();
+template <typename real, int NH> constexpr int z_waves_big() { return z_tw2_lds<real, NH>() ? 1 : 3; }
 template <typename real, int NH> constexpr int z_V() { return narrow_variant<NH>(sizeof(real) == 8 ? 8 : 12); }
 
 template <typename real, int NH> constexpr Sync z_sync() {
@@ -183,6 +187,17 @@ template <typename real, int NH> constexpr int z_lines() {
     int l = ce_max(1, PIPE_Z_THREADS / (NH / Plan<NH, z_V<real, NH>()>::E));
     while (l > 1 && l * lpad_len<z_pad<NH>()>(NH) * 2 * (int)sizeof(real) > PIPE_LDS_CAP) l /= 2;
     return l;
+}
+// Whether a z forward block stages the real/complex split's table W_2N in LDS.
+// Each line reads it once, at consecutive entries; in FP64 at lz/2 >= 1024
+// the staged table (16 KB) costs a block per CU (2 instead of 3), so there the
+// forward pass reads it from global memory and is held to the 168 registers
+// of 3 waves per SIMD (no spills).
+#ifndef PIPE_Z_TW2_RULE
+#define PIPE_Z_TW2_RULE 1
+#endif
+template <typename real, int NH> constexpr bool z_tw2_lds() {
+    return !(PIPE_Z_TW2_RULE && sizeof(real) == 8 && NH >= 1024);
 }
 
 

@@ -114,7 +114,8 @@ constexpr bool Z_PAIR_STORE = PIPE_Z_PAIR_STORE && sizeof(real) == 4 && NH % 2 =
 //   X[0] = Re Z[0] + Im Z[0],  X[NH] = Re Z[0] - Im Z[0]  (stored as slot 0 = (X[0], X[NH])).
 // vec2: n_in and in_pitch even and `in` 2-element aligned, so x[2m], x[2m+1] load as one pair.
 template <typename real, int NH>
-__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH, z_V<real, NH>()>::E))) __attribute__((amdgpu_waves_per_eu(z_waves<real, NH>())))
+__global__ __launch_bounds__((z_lines<real, NH>() * (NH / Plan<NH, z_V<real, NH>()>::E)))
+__attribute__((amdgpu_waves_per_eu(z_waves<real, NH>() > 1 ? z_waves<real, NH>() : z_waves_big<real, NH>())))
 void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long out_pitch, long nlines,
                   const twid<real>* __restrict__ tw, const twid<real>* __restrict__ tw2, int vec2,
                   const GroupArgs* __restrict__ group) {
@@ -129,9 +130,15 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
     constexpr int PADN = lpad_len<z_pad<NH>()>(NH);
     constexpr Sync ZS = z_sync<real, NH>();
     __shared__ C lds[LPW * PADN];
-    __shared__ twid<real> s_tw[NH], s_tw2[NH];
+    constexpr bool TW2L = z_tw2_lds<real, NH>();
+    __shared__ twid<real> s_tw[NH], s_tw2[TW2L ? NH : 1];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
-    tw2 = stage_twiddles(s_tw2, tw2, NH);
+    if constexpr (TW2L) tw2 = stage_twiddles(s_tw2, tw2, NH);
+    const gptr<const twid<real>> gtw2 = to_global(tw2);
+    auto w2 = [&](int k) -> twid<real> {
+        if constexpr (TW2L) return tw2[k];
+        else return gtw2[k];
+    };
     if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
     const int t = threadIdx.x % P, l = threadIdx.x / P;
     LdsLine<C, z_pad<NH>()> view{lds + l * PADN};
@@ -170,7 +177,7 @@ void z_r2c_kernel(const real* in, long in_pitch, int n_in, cplx<real>* out, long
             if (k == 0) return cmake<C>(zk.x + zk.y, zk.x - zk.y);
             const C zn = cconj(view.get(NH - k));
             const C A = cadd(zk, zn), B = csub(zk, zn);
-            const C wb = ctw<false>(B, tw2[k]);  // W^k B;  X = (A - i W^k B) / 2
+            const C wb = ctw<false>(B, w2(k));  // W^k B;  X = (A - i W^k B) / 2
             return cscale(cmake<C>(A.x + wb.y, A.y - wb.x), (real)0.5);
         };
         if (line < nlines) {
@@ -218,9 +225,16 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
     constexpr int PADN = lpad_len<z_pad<NH>()>(NH);
     constexpr Sync ZS = z_sync<real, NH>();
     __shared__ C lds[LPW * PADN];
-    __shared__ twid<real> s_tw[NH], s_tw2[NH];
+    constexpr bool TW2L = true;   // the inverse pass keeps the table staged (reading it from
+                                  // global memory would need 28 more registers: spills)
+    __shared__ twid<real> s_tw[NH], s_tw2[TW2L ? NH : 1];
     tw = stage_twiddles(s_tw, tw, stage_tw_size<PL>());
-    tw2 = stage_twiddles(s_tw2, tw2, NH);
+    if constexpr (TW2L) tw2 = stage_twiddles(s_tw2, tw2, NH);
+    const gptr<const twid<real>> gtw2 = to_global(tw2);
+    auto w2 = [&](int k) -> twid<real> {
+        if constexpr (TW2L) return tw2[k];
+        else return gtw2[k];
+    };
     if constexpr (ZS == Sync::WAVE) __syncthreads();   // the twiddles, written by every wave
     const int t = threadIdx.x % P, l = threadIdx.x / P;
     LdsLine<C, z_pad<NH>()> view{lds + l * PADN};
@@ -256,7 +270,7 @@ void z_c2r_kernel(const cplx<real>* in, long in_pitch, real* out, long out_pitch
                 if (k == 0) return cmake<C>(xk.x + xk.y, xk.x - xk.y);
                 const C xn = cconj(view.get(NH - k));
                 const C A = cadd(xk, xn), B = csub(xk, xn);
-                const C wb = ctw<true>(B, tw2[k]);  // W^{-k} B
+                const C wb = ctw<true>(B, w2(k));  // W^{-k} B
                 return cmake<C>(A.x - wb.y, A.y + wb.x);  // A + i W^{-k} B
             },
             [&](int m, C v) {
